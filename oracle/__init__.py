@@ -1,0 +1,204 @@
+"""FP64 CPU oracle for the quadric Gaussian splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or runs anything here.
+
+The arithmetic lives in ``qgs_oracle.c`` (plain C, FP64, OpenMP), which this
+module builds with gcc and calls through ctypes.  See the header of that file
+for the equations it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qgs_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+# Readings of the unstated constants (the renderer inherits them from the 3DGS
+# framework the paper builds on); every one is an input.
+DEFAULT_OPTS = dict(near=0.2, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99,
+                    T_eps=1e-4, A_eps=1e-6, bg=(0.0, 0.0, 0.0))
+
+# Margin scales for the discrete decisions: a pixel whose relative distance to a
+# decision boundary is below its scale is reported with margin < 1.
+DEFAULT_DELTA = dict(A=1e-3, D=1e-5, near=1e-5, E=1e-5, alpha_min=1e-4, T=1e-4,
+                     normal=1e-4, clamp=1e-4)
+_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp"]
+
+
+def build() -> str:
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", _SO, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _SO
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if (not os.path.exists(_SO)) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
+        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P]
+        L.oracle_keys.restype = None
+        L.oracle_bin_sort.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P]
+        L.oracle_bin_sort.restype = i64
+        L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
+                                    i32, i32, i32, i32, i32,
+                                    P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.oracle_render.restype = i64
+        L.oracle_gfun.argtypes = [f64]
+        L.oracle_gfun.restype = f64
+        L.oracle_gprime.argtypes = [f64]
+        L.oracle_gprime.restype = f64
+        L.oracle_arc_length.argtypes = [f64, f64]
+        L.oracle_arc_length.restype = f64
+        L.oracle_ray_hit.argtypes = [P, P, P, P, P, P, P, P]
+        L.oracle_ray_hit.restype = None
+        _lib_handle = L
+    return _lib_handle
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, np.float64)
+
+
+def cam_array(cam, dtype=np.float32):
+    return np.concatenate([np.asarray(cam.R, np.float64).reshape(9), np.asarray(cam.t, np.float64).reshape(3),
+                           [cam.fx, cam.fy, cam.cx, cam.cy]]).astype(np.float32).astype(dtype)
+
+
+def opts_array(opts=None):
+    o = dict(DEFAULT_OPTS)
+    if opts:
+        o.update(opts)
+    # thresholds are FP32 values on the GPU; the oracle uses the same values
+    vals = [o["near"], o["k_sigma"], o["alpha_min"], o["alpha_max"], o["T_eps"], o["A_eps"], *o["bg"]]
+    return np.asarray(vals, np.float32).astype(np.float64)
+
+
+def delta_array(delta=None):
+    d = dict(DEFAULT_DELTA)
+    if delta:
+        d.update(delta)
+    return np.asarray([d[k] for k in _DELTA_ORDER], np.float64)
+
+
+def gfun(u: float) -> float:
+    return _lib().oracle_gfun(float(u))
+
+
+def gprime(u: float) -> float:
+    return _lib().oracle_gprime(float(u))
+
+
+def arc_length(a: float, rho: float) -> float:
+    return _lib().oracle_arc_length(float(a), float(rho))
+
+
+def keys(scene, cam, opts=None):
+    """Key stage: cull flag, FP32 depth key bits, pixel and tile rectangles."""
+    o = opts_array(opts)
+    n = scene.n
+    culled = np.zeros(n, np.uint8)
+    depth_bits = np.zeros(n, np.uint32)
+    rect_px = np.zeros((n, 4), np.int32)
+    rect_tile = np.zeros((n, 4), np.int32)
+    tiles = np.zeros(n, np.uint32)
+    arrs = [_f32(a) for a in scene.arrays()]
+    camv = cam_array(cam)
+    _lib().oracle_keys(n, *[_ptr(a) for a in arrs], _ptr(camv), cam.width, cam.height,
+                       ctypes.c_float(o[0]), ctypes.c_float(o[1]),
+                       _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles))
+    return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles)
+
+
+def bin_sort(k, cam):
+    """Sorted tile|depth key list and per-tile ranges from the key stage."""
+    n = k["culled"].shape[0]
+    tx, ty = cam.tiles_x, cam.tiles_y
+    ranges = np.zeros((tx * ty, 2), np.uint32)
+    L = _lib()
+    total = L.oracle_bin_sort(n, _ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), tx, ty,
+                              0, None, None, _ptr(ranges))
+    keys_out = np.zeros(max(total, 1), np.uint64)
+    prims = np.zeros(max(total, 1), np.uint32)
+    total2 = L.oracle_bin_sort(n, _ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), tx, ty,
+                               total, _ptr(keys_out), _ptr(prims), _ptr(ranges))
+    assert total2 == total
+    return keys_out[:total], prims[:total], ranges
+
+
+def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=None,
+           key_stage=None, delta=None, cam_vec64=None):
+    """FP64 render of a pixel window (x0, y0, w, h) (default: the full view).
+
+    params64: optional tuple of FP64 parameter arrays overriding the scene's
+    (used for finite differences; order and culling still come from the key
+    stage of the FP32 scene).  cam_vec64: optional FP64 camera vector
+    {R[9], t[3], fx, fy, cx, cy} overriding the FP32 one.  dL: optional (dcolor[3,H,W], ddepth[H,W],
+    dnormal[3,H,W]) over the full view; runs the backward.
+    Returns a dict of window-sized FP64 maps and, with dL, parameter gradients.
+    """
+    o = opts_array(opts)
+    dv = delta_array(delta)
+    if key_stage is None:
+        key_stage = keys(scene, cam, opts)
+    x0, y0, w, h = window if window is not None else (0, 0, cam.width, cam.height)
+    n = scene.n
+    prm = params64 if params64 is not None else scene.arrays()
+    arrs = [_f64(a) for a in prm]
+    camv = cam_array(cam, np.float64) if cam_vec64 is None else _f64(cam_vec64)
+    color = np.zeros((3, h, w)); depth = np.zeros((h, w)); normal = np.zeros((3, h, w))
+    T = np.zeros((h, w)); nb = np.zeros((h, w), np.int32); margin = np.zeros((h, w))
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    grads = None
+    gp = [None] * 9
+    if dL is not None:
+        dc = _f64(dL[0][:, y0:y0 + h, x0:x0 + w])
+        dd = _f64(dL[1][y0:y0 + h, x0:x0 + w])
+        dn = _f64(dL[2][:, y0:y0 + h, x0:x0 + w])
+        grads = dict(center=np.zeros((n, 3)), quat=np.zeros((n, 4)), scale=np.zeros((n, 2)),
+                     curv=np.zeros((n, 2)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+        gp = [_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(grads[k]) for k in
+                                               ("center", "quat", "scale", "curv", "opacity", "rgb")]
+    ev = _lib().oracle_render(n, *[_ptr(a) for a in arrs], _ptr(key_stage["culled"]), _ptr(key_stage["depth_bits"]),
+                              _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv),
+                              x0, y0, w, h, int(nthreads),
+                              _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin), *gp)
+    if ev < 0:
+        raise ValueError("bad window")
+    out = dict(color=color, depth=depth, normal=normal, T_final=T, n_blend=nb, margin=margin, evals=int(ev))
+    if grads is not None:
+        out["grads"] = grads
+    return out
+
+
+def ray_hit(center, quat, scale, curv, cam_vec64, dcam, opts=None):
+    """One ray against one primitive.  Returns a dict of the hit quantities."""
+    out = np.zeros(14)
+    o = opts_array(opts)
+    _lib().oracle_ray_hit(_ptr(_f64(center)), _ptr(_f64(quat)), _ptr(_f64(scale)), _ptr(_f64(curv)),
+                          _ptr(_f64(cam_vec64)), _ptr(_f64(dcam)), _ptr(o), _ptr(out))
+    return dict(ok=bool(out[0]), linear=bool(out[1]), t=out[2], x=out[3], y=out[4], z=out[5], E=out[6], G=out[7],
+                A=out[8], B=out[9], C=out[10], normal=out[11:14].copy())

@@ -1,0 +1,877 @@
+/*
+ * FP64 CPU oracle for the quadric Gaussian splatting rasterizer
+ * (Quadratic Gaussian Splatting, arXiv 2411.16392).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or constant generator with
+ * the HIP library.
+ *
+ * Two parts:
+ *
+ *  A. Key stage (oracle_keys, oracle_bin_sort).  The discrete, order-defining
+ *     outputs of preprocessing -- the cull flag, the depth key, the screen
+ *     rectangle and the tile|depth key list -- written out as a fixed sequence
+ *     of IEEE double operations on the FP32 inputs (round to nearest, no
+ *     contraction, fma() only where written), then a plain comparison sort.
+ *     This is a bit-exact reference for the GPU's discrete outputs.
+ *
+ *  B. Renderer (oracle_render).  Everything continuous, in FP64, as the plain
+ *     per-pixel definition: for each pixel, every active primitive whose
+ *     ray-splat hit passes the rules is composited front to back in global
+ *     key order (depth key, then primitive index).  Binning here uses the
+ *     oracle's own conservative bound (a projected ball), which does not
+ *     change the result.  The backward pass is reverse-mode differentiation of
+ *     the same sequence with the same discrete decisions.
+ *
+ * Notation follows the paper:
+ *   local frame        x = R xhat + c                    (Sec. 3.2, congruent transform)
+ *   paraboloid         zhat = lambda1 xhat^2 + lambda2 yhat^2
+ *                      (explicit form, Sec. 3.2; lambda_i = sign(s_i) s_3 / s_i^2)
+ *   ray                phat = ohat + t dhat, |dhat| = 1  (supplement, ray-splat intersection)
+ *   quadratic          A t^2 + B t + C = 0              (supplement, intersection equation)
+ *   small |A|          t = -C/B (tangent-plane intersection, |A| < 1e-6)
+ *   arc length         l = rho g(u), u = 2|a| rho, g(u) = (asinh u + u sqrt(1+u^2)) / (2u)
+ *                      (geodesic equation, Sec. 3.2, and its derivation in the supplement)
+ *   density            G = exp(-l^2 / (2 sigma(theta)^2)), and l^2/sigma^2 = g^2 Q with
+ *                      Q = xhat^2/s1^2 + yhat^2/s2^2  (sigma(theta) equation, Sec. 3.2)
+ *   root selection     near root if l <= 3 sigma, else far root if l <= 3 sigma,
+ *                      else no hit (Sec. 3.2.1, ray-splat intersection)
+ *   normal             gradient of the implicit function (Sec. 3.2.1, normal equation)
+ *   compositing        X = sum alpha_i G_i T_i X_i, T_i = prod_{j<i}(1 - alpha_j G_j)
+ *                      (Eq. 1 and the N/K render equation, Sec. 3)
+ *   adjoint            dX/dabar_i = (X_i - sum_{j>i} X_j abar_j T_j / T_{i+1}) T_i
+ *                      (supplement, per-tile sorting and per-pixel resorting)
+ *
+ * Readings where the paper is silent or garbled (near plane 0.2, alpha clamp
+ * 0.99, alpha skip 1/255, stop before blending once T < 1e-4, inclusive 3-sigma
+ * test, camera-space normals flipped to face the camera, depth = sum w t along
+ * the unit ray, roots ordered t_n <= t_f and computed in the cancellation-free
+ * form) are inputs or fixed below and listed in the design notes.
+ *
+ * Parity of whole images on random scenes is pinned only through the pins of
+ * its parts (arc length vs quadrature, planar reduction, surface residual,
+ * compositing invariants, symmetries, finite differences).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OT 16 /* tile edge in pixels (16 x 16 tiles, supplement: per-tile sorting) */
+
+/* ======================================================================== */
+/* A. key stage                                                             */
+/* ======================================================================== */
+
+static int finite_f(const float *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+static double min3(double a, double b, double c) { double m = a < b ? a : b; return m < c ? m : c; }
+static double max3(double a, double b, double c) { double m = a > b ? a : b; return m > c ? m : c; }
+
+/*
+ * Per primitive: cull flag, FP32 depth key, pixel rectangle and tile rectangle.
+ * cam = {R[9] (world->camera, row-major), t[3], fx, fy, cx, cy} as FP32.
+ * rect_px / rect_tile: {x0, y0, x1, y1} inclusive; empty = {0, 0, -1, -1}.
+ */
+void oracle_keys(int64_t n, const float *center, const float *quat, const float *scale,
+                 const float *curv, const float *opac, const float *rgb,
+                 const float *cam, int32_t width, int32_t height, float near_f, float k_sigma,
+                 uint8_t *culled, uint32_t *depth_bits, int32_t *rect_px, int32_t *rect_tile,
+                 uint32_t *tiles)
+{
+    double W[9], T[3];
+    for (int i = 0; i < 9; ++i) W[i] = cam[i];
+    for (int i = 0; i < 3; ++i) T[i] = cam[9 + i];
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const double near_d = near_f;
+    const double infl = 1.0 + 1.0 / 1024.0;
+    const double pad_px = 1.0 / 64.0;
+
+    for (int64_t p = 0; p < n; ++p) {
+        int32_t *rp = rect_px + 4 * p, *rt = rect_tile + 4 * p;
+        rp[0] = rp[1] = 0; rp[2] = rp[3] = -1;
+        rt[0] = rt[1] = 0; rt[2] = rt[3] = -1;
+        tiles[p] = 0;
+        depth_bits[p] = 0;
+        culled[p] = 1;
+
+        const float *cf = center + 3 * p, *qf = quat + 4 * p, *sf = scale + 2 * p, *lf = curv + 2 * p;
+        if (!finite_f(cf, 3) || !finite_f(qf, 4) || !finite_f(sf, 2) || !finite_f(lf, 2) ||
+            !finite_f(opac + p, 1) || !finite_f(rgb + 3 * p, 3))
+            continue;
+        const double s1 = sf[0], s2 = sf[1], l1 = lf[0], l2 = lf[1];
+        if (!(s1 > 0.0) || !(s2 > 0.0)) continue;
+        const double w = qf[0], x = qf[1], y = qf[2], z = qf[3];
+        const double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+        const double qn = (ww + xx) + (yy + zz);
+        if (!(qn > 0.0)) continue;
+
+        double cc[3];
+        for (int i = 0; i < 3; ++i)
+            cc[i] = fma(W[3 * i + 0], (double)cf[0], fma(W[3 * i + 1], (double)cf[1], fma(W[3 * i + 2], (double)cf[2], T[i])));
+        const float zf = (float)cc[2];
+        if (!(zf > near_f)) continue;
+
+        /* rotation from the (unnormalised) quaternion: R = rot(q / |q|) */
+        const double s = 2.0 / qn;
+        const double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+        double Rm[9];
+        Rm[0] = 1.0 - s * (yy + zz); Rm[1] = s * (xy - wz);        Rm[2] = s * (xz + wy);
+        Rm[3] = s * (xy + wz);       Rm[4] = 1.0 - s * (xx + zz);  Rm[5] = s * (yz - wx);
+        Rm[6] = s * (xz - wy);       Rm[7] = s * (yz + wx);        Rm[8] = 1.0 - s * (xx + yy);
+        double Rc[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                Rc[3 * i + j] = fma(W[3 * i + 0], Rm[j], fma(W[3 * i + 1], Rm[3 + j], W[3 * i + 2] * Rm[6 + j]));
+
+        /* conservative local box of the support: an accepted hit has
+           g^2 Q <= k^2 with g >= 1, so |x| <= k s1, |y| <= k s2; its height
+           lambda1 x^2 + lambda2 y^2 lies between the simplex vertices
+           {0, k^2 lambda1 s1^2, k^2 lambda2 s2^2}, and |z| <= arc length <= k max(s) */
+        const double k = k_sigma;
+        const double hx = (k * s1) * infl, hy = (k * s2) * infl;
+        const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
+        const double k2 = k * k;
+        const double smax = s1 > s2 ? s1 : s2;
+        const double zcap = k * smax;
+        double zlo = k2 * min3(0.0, m1, m2), zhi = k2 * max3(0.0, m1, m2);
+        if (zlo < -zcap) zlo = -zcap;
+        if (zhi > zcap) zhi = zcap;
+        const double zpad = zcap / 1024.0;
+        zlo = zlo * infl - zpad;
+        zhi = zhi * infl + zpad;
+
+        int behind = 0;
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int c = 0; c < 8; ++c) {
+            const double X = (c & 1) ? hx : -hx, Y = (c & 2) ? hy : -hy, Z = (c & 4) ? zhi : zlo;
+            double P[3];
+            for (int i = 0; i < 3; ++i)
+                P[i] = fma(Rc[3 * i + 0], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
+            if (!(P[2] > near_d)) { behind = 1; continue; }
+            const double u = fma(fx, P[0] / P[2], cx), v = fma(fy, P[1] / P[2], cy);
+            if (u < umin) umin = u;
+            if (u > umax) umax = u;
+            if (v < vmin) vmin = v;
+            if (v > vmax) vmax = v;
+        }
+        int px0, px1, py0, py1;
+        if (behind) {
+            px0 = 0; px1 = width - 1; py0 = 0; py1 = height - 1;
+        } else {
+            const double a0 = (umin - 0.5) - pad_px, a1 = (umax - 0.5) + pad_px;
+            const double b0 = (vmin - 0.5) - pad_px, b1 = (vmax - 0.5) + pad_px;
+            if (a1 < 0.0 || a0 > (double)(width - 1) || b1 < 0.0 || b0 > (double)(height - 1)) {
+                culled[p] = 0;
+                depth_bits[p] = 0;
+                memcpy(&depth_bits[p], &zf, 4);
+                continue;
+            }
+            px0 = a0 <= 0.0 ? 0 : (int)ceil(a0);
+            px1 = a1 >= (double)(width - 1) ? width - 1 : (int)floor(a1);
+            py0 = b0 <= 0.0 ? 0 : (int)ceil(b0);
+            py1 = b1 >= (double)(height - 1) ? height - 1 : (int)floor(b1);
+        }
+        culled[p] = 0;
+        memcpy(&depth_bits[p], &zf, 4);
+        if (px0 > px1 || py0 > py1) continue;
+        rp[0] = px0; rp[1] = py0; rp[2] = px1; rp[3] = py1;
+        rt[0] = px0 / OT; rt[1] = py0 / OT; rt[2] = px1 / OT; rt[3] = py1 / OT;
+        tiles[p] = (uint32_t)((rt[2] - rt[0] + 1) * (rt[3] - rt[1] + 1));
+    }
+}
+
+typedef struct {
+    uint64_t key; /* tile << 32 | depth bits */
+    uint64_t seq; /* emission index: primitive-major, tiles row-major in its rect */
+    uint32_t prim;
+} opair;
+
+static int cmp_pair(const void *a, const void *b)
+{
+    const opair *x = (const opair *)a, *y = (const opair *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->seq != y->seq) return x->seq < y->seq ? -1 : 1;
+    return 0;
+}
+
+/*
+ * Emits one (key, primitive) pair per tile of every rectangle, in primitive
+ * order and row-major within a rectangle, and sorts by key with ties kept in
+ * emission order.  Returns the pair count; writes outputs only if it fits cap.
+ * ranges[2t], ranges[2t+1] = [start, end) of tile t in the sorted list.
+ */
+int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_bits,
+                        const int32_t *rect_tile, int32_t tiles_x, int32_t tiles_y,
+                        int64_t cap, uint64_t *out_keys, uint32_t *out_prim, uint32_t *ranges)
+{
+    int64_t total = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t *r = rect_tile + 4 * p;
+        if (culled[p] || r[2] < r[0] || r[3] < r[1]) continue;
+        total += (int64_t)(r[2] - r[0] + 1) * (r[3] - r[1] + 1);
+    }
+    if (total > cap) return total;
+    opair *pairs = (opair *)malloc(sizeof(opair) * (size_t)(total > 0 ? total : 1));
+    int64_t k = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t *r = rect_tile + 4 * p;
+        if (culled[p] || r[2] < r[0] || r[3] < r[1]) continue;
+        for (int ty = r[1]; ty <= r[3]; ++ty)
+            for (int tx = r[0]; tx <= r[2]; ++tx) {
+                pairs[k].key = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | depth_bits[p];
+                pairs[k].seq = (uint64_t)k;
+                pairs[k].prim = (uint32_t)p;
+                ++k;
+            }
+    }
+    qsort(pairs, (size_t)total, sizeof(opair), cmp_pair);
+    const int64_t nt = (int64_t)tiles_x * tiles_y;
+    for (int64_t t = 0; t < 2 * nt; ++t) ranges[t] = 0;
+    for (int64_t i = 0; i < total; ++i) {
+        out_keys[i] = pairs[i].key;
+        out_prim[i] = pairs[i].prim;
+        const uint32_t t = (uint32_t)(pairs[i].key >> 32);
+        if (i == 0 || (uint32_t)(pairs[i - 1].key >> 32) != t) ranges[2 * t] = (uint32_t)i;
+        if (i == total - 1 || (uint32_t)(pairs[i + 1].key >> 32) != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+    }
+    free(pairs);
+    return total;
+}
+
+double oracle_gfun(double u);
+
+/* ======================================================================== */
+/* B. FP64 renderer                                                         */
+/* ======================================================================== */
+
+/* options: near, k_sigma, alpha_min, alpha_max, T_eps, A_eps, bg[3] */
+enum { O_NEAR = 0, O_K, O_AMIN, O_AMAX, O_TEPS, O_AEPS, O_BG };
+/* margin scales: |A| vs A_eps, D vs 0, near test, E vs k^2, alpha_min, T_eps,
+   normal facing, alpha clamp */
+enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_COUNT };
+
+typedef struct {
+    double Rc[9];  /* camera-from-local rotation: columns are the local axes */
+    double cc[3];  /* centre in camera space */
+    double o[3];   /* camera centre in the local frame, ohat = -Rc^T cc */
+    double C;      /* constant term of the quadratic: lambda1 o1^2 + lambda2 o2^2 - o3 */
+    double s1, s2, l1, l2, op, rgb[3];
+    double qn[4], qlen;
+} oprim;
+
+static void setup_prim(const double *c, const double *q, const double *s, const double *l,
+                       double op, const double *rgb, const double *W, const double *T, oprim *P)
+{
+    const double len = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / len, x = q[1] / len, y = q[2] / len, z = q[3] / len;
+    double Rm[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                    2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                    2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            P->Rc[3 * i + j] = W[3 * i] * Rm[j] + W[3 * i + 1] * Rm[3 + j] + W[3 * i + 2] * Rm[6 + j];
+    for (int i = 0; i < 3; ++i) P->cc[i] = W[3 * i] * c[0] + W[3 * i + 1] * c[1] + W[3 * i + 2] * c[2] + T[i];
+    for (int j = 0; j < 3; ++j)
+        P->o[j] = -(P->Rc[j] * P->cc[0] + P->Rc[3 + j] * P->cc[1] + P->Rc[6 + j] * P->cc[2]);
+    P->s1 = s[0]; P->s2 = s[1]; P->l1 = l[0]; P->l2 = l[1];
+    P->op = op;
+    P->rgb[0] = rgb[0]; P->rgb[1] = rgb[1]; P->rgb[2] = rgb[2];
+    P->C = P->l1 * P->o[0] * P->o[0] + P->l2 * P->o[1] * P->o[1] - P->o[2];
+    P->qn[0] = w; P->qn[1] = x; P->qn[2] = y; P->qn[3] = z;
+    P->qlen = len;
+}
+
+/* arc-length factor g(u) = l / rho and its derivative.  Below u = 0.1 the
+   closed forms lose digits (g' subtracts nearly equal terms), so the binomial
+   series of the integrand is used: sqrt(1 + u^2 s^2) = sum_k C(1/2, k) u^2k s^2k
+   integrated over s in [0, 1] gives g = sum_k C(1/2, k) u^2k / (2k + 1). */
+static const double G_SERIES[9] = {1.0, 1.0 / 6, -1.0 / 40, 1.0 / 112, -5.0 / 1152, 7.0 / 2816,
+                                   -21.0 / 13312, 11.0 / 10240, -429.0 / 557056};
+
+double oracle_gfun(double u)
+{
+    if (u < 0.1) {
+        const double v = u * u;
+        double acc = 0.0;
+        for (int k = 8; k >= 0; --k) acc = acc * v + G_SERIES[k];
+        return acc;
+    }
+    return (asinh(u) + u * sqrt(1.0 + u * u)) / (2.0 * u);
+}
+
+double oracle_gprime(double u)
+{
+    if (u < 0.1) {
+        const double v = u * u;
+        double acc = 0.0;
+        for (int k = 8; k >= 1; --k) acc = acc * v + 2.0 * k * G_SERIES[k];
+        return acc * u;
+    }
+    return (u * sqrt(1.0 + u * u) - asinh(u)) / (2.0 * u * u);
+}
+
+/* arc length l(a, rho) of the normal section z = a r^2 from 0 to rho */
+double oracle_arc_length(double a, double rho)
+{
+    return rho * oracle_gfun(2.0 * fabs(a) * rho);
+}
+
+typedef struct {
+    int ok;
+    int linear;     /* 1: small-|A| branch t = -C/B */
+    double d[3];    /* dhat */
+    double A, B, F1;/* F1 = dF/dt at the root (quadratic) or B (linear) */
+    double t, x, y, Q, rho, h, u, g, E;
+    double margin;
+} ohit;
+
+static inline double mscale(double v, const double *delta, int k) { return v / delta[k]; }
+
+/* l^2 / sigma^2 at ray parameter t (used only to decide which margins matter) */
+static double support_E(const oprim *P, double t, const double dcam[3])
+{
+    double d[3];
+    for (int j = 0; j < 3; ++j) d[j] = P->Rc[j] * dcam[0] + P->Rc[3 + j] * dcam[1] + P->Rc[6 + j] * dcam[2];
+    const double x = P->o[0] + t * d[0], y = P->o[1] + t * d[1];
+    const double Q = x * x / (P->s1 * P->s1) + y * y / (P->s2 * P->s2);
+    const double rho = sqrt(x * x + y * y);
+    const double h = P->l1 * x * x + P->l2 * y * y;
+    const double u = rho > 0.0 ? 2.0 * fabs(h) / rho : 0.0;
+    const double g = oracle_gfun(u);
+    return g * g * Q;
+}
+
+/* ray-splat intersection with root selection (Sec. 3.2.1 and supplement) */
+static void ray_hit(const oprim *P, const double dcam[3], const double *opts, const double *delta, ohit *H)
+{
+    double *d = H->d;
+    for (int j = 0; j < 3; ++j) d[j] = P->Rc[j] * dcam[0] + P->Rc[3 + j] * dcam[1] + P->Rc[6 + j] * dcam[2];
+    const double l1 = P->l1, l2 = P->l2, *o = P->o;
+    const double A = l1 * d[0] * d[0] + l2 * d[1] * d[1];
+    const double B = 2.0 * (l1 * o[0] * d[0] + l2 * o[1] * d[1]) - d[2];
+    const double C = P->C;
+    const double near_ = opts[O_NEAR], k2 = opts[O_K] * opts[O_K], Aeps = opts[O_AEPS];
+    H->A = A; H->B = B; H->ok = 0;
+    double margin = INFINITY, m;
+    m = mscale(fabs(fabs(A) - Aeps) / Aeps, delta, M_A);
+    if (m < margin) margin = m;
+
+    double cand[2];
+    int nc = 0;
+    if (fabs(A) < Aeps) {
+        H->linear = 1;
+        if (B != 0.0) cand[nc++] = -C / B;
+    } else {
+        H->linear = 0;
+        const double D = B * B - 4.0 * A * C;
+        /* the sign of D only matters where the double root t* = -B/(2A)
+           would be inside (or at the edge of) the support */
+        if (support_E(P, -B / (2.0 * A), dcam) <= 1.01 * k2) {
+            m = mscale(fabs(D) / (B * B + 4.0 * fabs(A * C)), delta, M_D);
+            if (m < margin) margin = m;
+        }
+        if (D >= 0.0) {
+            const double sq = sqrt(D);
+            const double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            double r1, r2;
+            if (qq == 0.0) { r1 = r2 = 0.0; }
+            else { r1 = qq / A; r2 = C / qq; }
+            cand[0] = r1 < r2 ? r1 : r2;
+            cand[1] = r1 < r2 ? r2 : r1;
+            nc = 2;
+        }
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+        const double t = cand[ci];
+        const double zc = t * dcam[2];
+        if (support_E(P, t, dcam) <= 1.01 * k2) {
+            m = mscale(fabs(zc - near_) / near_, delta, M_NEAR);
+            if (m < margin) margin = m;
+        }
+        if (!(zc > near_)) continue;
+        const double x = o[0] + t * d[0], y = o[1] + t * d[1];
+        const double Q = x * x / (P->s1 * P->s1) + y * y / (P->s2 * P->s2);
+        const double r2 = x * x + y * y;
+        const double rho = sqrt(r2);
+        const double h = l1 * x * x + l2 * y * y;
+        const double u = rho > 0.0 ? 2.0 * fabs(h) / rho : 0.0;
+        const double g = oracle_gfun(u);
+        const double E = g * g * Q;
+        m = mscale(fabs(E - k2) / k2, delta, M_E);
+        if (m < margin) margin = m;
+        if (E <= k2) {
+            H->ok = 1;
+            H->t = t; H->x = x; H->y = y; H->Q = Q; H->rho = rho; H->h = h; H->u = u; H->g = g; H->E = E;
+            H->F1 = H->linear ? B : 2.0 * A * t + B;
+            break;
+        }
+    }
+    H->margin = margin;
+}
+
+/* unit normal of the paraboloid at the hit, flipped to face the camera */
+static void hit_normal(const oprim *P, const ohit *H, double nl[3], double *flip, double *vlen)
+{
+    const double v[3] = {-2.0 * P->l1 * H->x, -2.0 * P->l2 * H->y, 1.0};
+    const double L = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    *vlen = L;
+    for (int j = 0; j < 3; ++j) nl[j] = v[j] / L;
+    const double nd = nl[0] * H->d[0] + nl[1] * H->d[1] + nl[2] * H->d[2];
+    *flip = nd > 0.0 ? -1.0 : 1.0;
+}
+
+/* per-primitive backward accumulator in the primitive's own variables */
+typedef struct {
+    double dRc[9], dcc[3], dl[2], ds[2], dop, drgb[3];
+} ograd;
+
+typedef struct {
+    int32_t list;   /* index into the active order */
+    double alpha, T;
+} oentry;
+
+typedef struct {
+    const oprim *prims;     /* compact: active primitives in window order */
+    const int64_t *ids;     /* compact index -> original primitive index */
+    int32_t *cell_start, *cell_items; /* CSR over cells of OT x OT pixels */
+    int32_t cells_x, cells_y;
+} obins;
+
+static void pixel_ray(const double *cam, int px, int py, double d[3])
+{
+    const double xn = ((px + 0.5) - cam[14]) / cam[12];
+    const double yn = ((py + 0.5) - cam[15]) / cam[13];
+    const double L = sqrt(xn * xn + yn * yn + 1.0);
+    d[0] = xn / L; d[1] = yn / L; d[2] = 1.0 / L;
+}
+
+/* backward of one blended entry: dalpha plus direct output gradients */
+static void entry_backward(const oprim *P, const ohit *H, const double *dcam, const double *opts,
+                           double dalpha, double w, const double gc[3], double gd, const double gn[3],
+                           ograd *G)
+{
+    /* direct colour, depth and normal terms */
+    for (int c = 0; c < 3; ++c) G->drgb[c] += gc[c] * w;
+    double dt = gd * w;
+    double nl[3], flip, vlen;
+    hit_normal(P, H, nl, &flip, &vlen);
+    double dncam[3] = {gn[0] * w, gn[1] * w, gn[2] * w};
+    double dx = 0.0, dy = 0.0;
+    /* n_cam = flip * Rc nl */
+    double dnl[3];
+    for (int j = 0; j < 3; ++j) {
+        dnl[j] = flip * (P->Rc[j] * dncam[0] + P->Rc[3 + j] * dncam[1] + P->Rc[6 + j] * dncam[2]);
+        for (int i = 0; i < 3; ++i) G->dRc[3 * i + j] += flip * dncam[i] * nl[j];
+    }
+    const double ndot = nl[0] * dnl[0] + nl[1] * dnl[1] + nl[2] * dnl[2];
+    double dv[3];
+    for (int j = 0; j < 3; ++j) dv[j] = (dnl[j] - nl[j] * ndot) / vlen;
+    /* v = (-2 l1 x, -2 l2 y, 1) */
+    G->dl[0] += -2.0 * H->x * dv[0];
+    G->dl[1] += -2.0 * H->y * dv[1];
+    dx += -2.0 * P->l1 * dv[0];
+    dy += -2.0 * P->l2 * dv[1];
+
+    /* opacity and density: alpha = min(alpha_max, op G), G = exp(-E/2) */
+    const double Gv = exp(-0.5 * H->E);
+    double dG = 0.0;
+    if (P->op * Gv < opts[O_AMAX]) {
+        G->dop += dalpha * Gv;
+        dG = dalpha * P->op;
+    }
+    const double dE = -0.5 * Gv * dG;
+    /* E = g(u)^2 Q */
+    const double dQ = H->g * H->g * dE;
+    const double du = 2.0 * H->g * oracle_gprime(H->u) * H->Q * dE;
+    /* Q = x^2/s1^2 + y^2/s2^2 */
+    const double s1 = P->s1, s2 = P->s2;
+    dx += 2.0 * H->x / (s1 * s1) * dQ;
+    dy += 2.0 * H->y / (s2 * s2) * dQ;
+    G->ds[0] += -2.0 * H->x * H->x / (s1 * s1 * s1) * dQ;
+    G->ds[1] += -2.0 * H->y * H->y / (s2 * s2 * s2) * dQ;
+    /* u = 2 |h| / rho, h = l1 x^2 + l2 y^2, rho = sqrt(x^2 + y^2) */
+    if (H->rho > 0.0 && du != 0.0) {
+        const double sg = H->h > 0.0 ? 1.0 : (H->h < 0.0 ? -1.0 : 0.0);
+        const double dh = du * 2.0 * sg / H->rho;
+        const double drho = -du * 2.0 * fabs(H->h) / (H->rho * H->rho);
+        G->dl[0] += H->x * H->x * dh;
+        G->dl[1] += H->y * H->y * dh;
+        dx += 2.0 * P->l1 * H->x * dh + H->x / H->rho * drho;
+        dy += 2.0 * P->l2 * H->y * dh + H->y / H->rho * drho;
+    }
+    /* phat = ohat + t dhat (only x, y are used) */
+    const double *d = H->d;
+    double dO[3] = {dx, dy, 0.0};
+    double dD[3] = {H->t * dx, H->t * dy, 0.0};
+    dt += d[0] * dx + d[1] * dy;
+    /* root: quadratic (implicit) or linear t = -C/B */
+    double dA = 0.0, dB, dC;
+    if (H->linear) {
+        dC = -dt / H->B;
+        dB = -H->t / H->B * dt; /* t = -C/B  ->  dt/dB = C/B^2 = -t/B */
+    } else {
+        dA = -H->t * H->t / H->F1 * dt;
+        dB = -H->t / H->F1 * dt;
+        dC = -1.0 / H->F1 * dt;
+    }
+    const double *o = P->o, l1 = P->l1, l2 = P->l2;
+    /* A = l1 d1^2 + l2 d2^2 */
+    G->dl[0] += d[0] * d[0] * dA;
+    G->dl[1] += d[1] * d[1] * dA;
+    dD[0] += 2.0 * l1 * d[0] * dA;
+    dD[1] += 2.0 * l2 * d[1] * dA;
+    /* B = 2 (l1 o1 d1 + l2 o2 d2) - d3 */
+    G->dl[0] += 2.0 * o[0] * d[0] * dB;
+    G->dl[1] += 2.0 * o[1] * d[1] * dB;
+    dO[0] += 2.0 * l1 * d[0] * dB;
+    dO[1] += 2.0 * l2 * d[1] * dB;
+    dD[0] += 2.0 * l1 * o[0] * dB;
+    dD[1] += 2.0 * l2 * o[1] * dB;
+    dD[2] += -dB;
+    /* C = l1 o1^2 + l2 o2^2 - o3 */
+    G->dl[0] += o[0] * o[0] * dC;
+    G->dl[1] += o[1] * o[1] * dC;
+    dO[0] += 2.0 * l1 * o[0] * dC;
+    dO[1] += 2.0 * l2 * o[1] * dC;
+    dO[2] += -dC;
+    /* dhat = Rc^T dcam ; ohat = -Rc^T cc */
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            G->dRc[3 * i + j] += dcam[i] * dD[j] - P->cc[i] * dO[j];
+            G->dcc[i] += -P->Rc[3 * i + j] * dO[j];
+        }
+}
+
+/* the whole per-pixel sequence; with dL != NULL also its backward */
+static void render_pixel(const obins *B, const double *cam, const double *opts, const double *delta,
+                         int px, int py, int cell, int32_t x0w, int32_t y0w,
+                         double out[7], double *T_out, int32_t *nb_out, double *margin_out, int64_t *evals,
+                         const double g7[7], ograd *grads, oentry **scratch, int *scratch_cap)
+{
+    double dcam[3];
+    pixel_ray(cam, px, py, dcam);
+    double T = 1.0, acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double margin = INFINITY;
+    int nb = 0;
+    const int32_t s = B->cell_start[cell], e = B->cell_start[cell + 1];
+    for (int32_t it = s; it < e; ++it) {
+        const int32_t li = B->cell_items[it];
+        const oprim *P = &B->prims[li];
+        ohit H;
+        ++*evals;
+        ray_hit(P, dcam, opts, delta, &H);
+        if (H.margin < margin) margin = H.margin;
+        if (!H.ok) continue;
+        const double Gv = exp(-0.5 * H.E);
+        const double aa = P->op * Gv;
+        double m = mscale(fabs(aa - opts[O_AMAX]) / opts[O_AMAX], delta, M_CLAMP);
+        if (m < margin) margin = m;
+        const double alpha = aa < opts[O_AMAX] ? aa : opts[O_AMAX];
+        m = mscale(fabs(alpha - opts[O_AMIN]) / opts[O_AMIN], delta, M_AMIN);
+        if (m < margin) margin = m;
+        if (alpha < opts[O_AMIN]) continue;
+        const double Tn = T * (1.0 - alpha);
+        m = mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T);
+        if (m < margin) margin = m;
+        if (Tn < opts[O_TEPS]) break;
+        const double w = alpha * T;
+        double nl[3], flip, vlen;
+        hit_normal(P, &H, nl, &flip, &vlen);
+        m = mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N);
+        if (m < margin) margin = m;
+        for (int c = 0; c < 3; ++c) acc[c] += w * P->rgb[c];
+        acc[3] += w * H.t;
+        for (int i = 0; i < 3; ++i)
+            acc[4 + i] += w * flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
+        if (g7) {
+            if (nb >= *scratch_cap) {
+                *scratch_cap = *scratch_cap ? 2 * *scratch_cap : 256;
+                *scratch = (oentry *)realloc(*scratch, sizeof(oentry) * (size_t)*scratch_cap);
+            }
+            (*scratch)[nb].list = li;
+            (*scratch)[nb].alpha = alpha;
+            (*scratch)[nb].T = T;
+        }
+        ++nb;
+        T = Tn;
+    }
+    for (int c = 0; c < 3; ++c) acc[c] += T * opts[O_BG + c];
+    for (int c = 0; c < 7; ++c) out[c] = acc[c];
+    *T_out = T;
+    *nb_out = nb;
+    *margin_out = margin;
+    (void)x0w; (void)y0w;
+
+    if (!g7) return;
+    /* back to front: S = sum_{j>i} w_j X_j + T_final bg */
+    double S[7] = {T * opts[O_BG], T * opts[O_BG + 1], T * opts[O_BG + 2], 0, 0, 0, 0};
+    for (int k = nb - 1; k >= 0; --k) {
+        const oentry *en = &(*scratch)[k];
+        const oprim *P = &B->prims[en->list];
+        ohit H;
+        ray_hit(P, dcam, opts, delta, &H);
+        double nl[3], flip, vlen;
+        hit_normal(P, &H, nl, &flip, &vlen);
+        double X[7];
+        for (int c = 0; c < 3; ++c) X[c] = P->rgb[c];
+        X[3] = H.t;
+        for (int i = 0; i < 3; ++i)
+            X[4 + i] = flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
+        const double a = en->alpha, Ti = en->T, w = a * Ti;
+        double dalpha = 0.0;
+        for (int c = 0; c < 7; ++c) dalpha += g7[c] * (Ti * X[c] - S[c] / (1.0 - a));
+        for (int c = 0; c < 7; ++c) S[c] += w * X[c];
+        entry_backward(P, &H, dcam, opts, dalpha, w, g7, g7[3], g7 + 4, &grads[en->list]);
+    }
+}
+
+/* conservative pixel box of the ball |p - cc| <= r (oracle's own binning) */
+static int ball_box(const double cc[3], double r, const double *cam, double near_, int width, int height,
+                    int *px0, int *py0, int *px1, int *py1)
+{
+    if (cc[2] - r <= near_) {
+        *px0 = 0; *py0 = 0; *px1 = width - 1; *py1 = height - 1;
+        return 1;
+    }
+    const double za = cc[2] - r, zb = cc[2] + r;
+    const double xl = fmin((cc[0] - r) / za, (cc[0] - r) / zb), xh = fmax((cc[0] + r) / za, (cc[0] + r) / zb);
+    const double yl = fmin((cc[1] - r) / za, (cc[1] - r) / zb), yh = fmax((cc[1] + r) / za, (cc[1] + r) / zb);
+    const double u0 = cam[12] * xl + cam[14] - 0.5 - 1.0, u1 = cam[12] * xh + cam[14] - 0.5 + 1.0;
+    const double v0 = cam[13] * yl + cam[15] - 0.5 - 1.0, v1 = cam[13] * yh + cam[15] - 0.5 + 1.0;
+    if (u1 < 0 || v1 < 0 || u0 > width - 1 || v0 > height - 1) return 0;
+    *px0 = u0 < 0 ? 0 : (int)ceil(u0);
+    *px1 = u1 > width - 1 ? width - 1 : (int)floor(u1);
+    *py0 = v0 < 0 ? 0 : (int)ceil(v0);
+    *py1 = v1 > height - 1 ? height - 1 : (int)floor(v1);
+    return *px0 <= *px1 && *py0 <= *py1;
+}
+
+typedef struct { uint32_t key; int64_t id; } oorder;
+
+static int cmp_order(const void *a, const void *b)
+{
+    const oorder *x = (const oorder *)a, *y = (const oorder *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id);
+}
+
+/*
+ * Render the pixel window [x0, x0+w) x [y0, y0+h) of a width x height view.
+ * Parameters are FP64 (exact copies of FP32 inputs, or perturbed for finite
+ * differences).  culled/depth_bits come from oracle_keys and fix the active set
+ * and the order.  cam = {R[9], t[3], fx, fy, cx, cy}.
+ * Outputs (window-sized, planar): color[3][h][w], depth, normal[3][h][w],
+ * T_final, n_blend (entries blended), margin (min over decisions of the
+ * relative distance to the boundary divided by its scale in delta).
+ * If dL_color != NULL the backward runs and parameter gradients are written
+ * (full [n] arrays, zero for inactive primitives).
+ * Returns the number of (pixel, candidate) evaluations, or -1 on error.
+ */
+int64_t oracle_render(int64_t n, const double *center, const double *quat, const double *scale,
+                      const double *curv, const double *opac, const double *rgb,
+                      const uint8_t *culled, const uint32_t *depth_bits,
+                      const double *cam, int32_t width, int32_t height,
+                      const double *opts, const double *delta,
+                      int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
+                      double *color, double *depth, double *normal, double *T_final,
+                      int32_t *n_blend, double *margin,
+                      const double *dL_color, const double *dL_depth, const double *dL_normal,
+                      double *g_center, double *g_quat, double *g_scale, double *g_curv,
+                      double *g_opac, double *g_rgb)
+{
+    if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height) return -1;
+    const double *W = cam, *T = cam + 9;
+    /* active primitives in global order: depth key, then index */
+    int64_t na = 0;
+    for (int64_t p = 0; p < n; ++p) na += culled[p] ? 0 : 1;
+    oorder *ord = (oorder *)malloc(sizeof(oorder) * (size_t)(na > 0 ? na : 1));
+    na = 0;
+    for (int64_t p = 0; p < n; ++p)
+        if (!culled[p]) { ord[na].key = depth_bits[p]; ord[na].id = p; ++na; }
+    qsort(ord, (size_t)na, sizeof(oorder), cmp_order);
+
+    /* bin into window cells with the ball bound; keep only primitives that touch */
+    const int cx_n = (w + OT - 1) / OT, cy_n = (h + OT - 1) / OT, ncell = cx_n * cy_n;
+    int32_t *cnt = (int32_t *)calloc((size_t)ncell + 1, sizeof(int32_t));
+    int32_t *box = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(na > 0 ? na : 1));
+    oprim *tmp = (oprim *)malloc(sizeof(oprim) * (size_t)(na > 0 ? na : 1));
+    int64_t nw = 0;
+    int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)(na > 0 ? na : 1));
+    for (int64_t i = 0; i < na; ++i) {
+        const int64_t p = ord[i].id;
+        oprim P;
+        setup_prim(center + 3 * p, quat + 4 * p, scale + 2 * p, curv + 2 * p, opac[p], rgb + 3 * p, W, T, &P);
+        const double r = opts[O_K] * (P.s1 > P.s2 ? P.s1 : P.s2) * 1.01 + 1e-9;
+        int a0, b0, a1, b1;
+        if (!ball_box(P.cc, r, cam, opts[O_NEAR], width, height, &a0, &b0, &a1, &b1)) continue;
+        /* intersect with window, to cell coordinates */
+        if (a1 < x0 || b1 < y0 || a0 >= x0 + w || b0 >= y0 + h) continue;
+        a0 = (a0 < x0 ? x0 : a0) - x0; a1 = (a1 >= x0 + w ? x0 + w - 1 : a1) - x0;
+        b0 = (b0 < y0 ? y0 : b0) - y0; b1 = (b1 >= y0 + h ? y0 + h - 1 : b1) - y0;
+        box[4 * nw] = a0 / OT; box[4 * nw + 1] = b0 / OT; box[4 * nw + 2] = a1 / OT; box[4 * nw + 3] = b1 / OT;
+        tmp[nw] = P;
+        ids[nw] = p;
+        for (int cy = box[4 * nw + 1]; cy <= box[4 * nw + 3]; ++cy)
+            for (int cx = box[4 * nw]; cx <= box[4 * nw + 2]; ++cx) cnt[cy * cx_n + cx + 1]++;
+        ++nw;
+    }
+    for (int c = 0; c < ncell; ++c) cnt[c + 1] += cnt[c];
+    int32_t *items = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cnt[ncell] > 0 ? cnt[ncell] : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncell > 0 ? ncell : 1));
+    memcpy(fill, cnt, sizeof(int32_t) * (size_t)ncell);
+    for (int64_t i = 0; i < nw; ++i)
+        for (int cy = box[4 * i + 1]; cy <= box[4 * i + 3]; ++cy)
+            for (int cx = box[4 * i]; cx <= box[4 * i + 2]; ++cx) items[fill[cy * cx_n + cx]++] = (int32_t)i;
+    obins Bn = {tmp, ids, cnt, items, cx_n, cy_n};
+
+    int nthr = nthreads > 0 ? nthreads : 1;
+#ifdef _OPENMP
+    omp_set_num_threads(nthr);
+#else
+    nthr = 1;
+#endif
+    const int do_bwd = dL_color != NULL;
+    ograd *grads = NULL;
+    if (do_bwd) grads = (ograd *)calloc((size_t)nthr * (size_t)(nw > 0 ? nw : 1), sizeof(ograd));
+    int64_t evals_total = 0;
+    const size_t npx = (size_t)w * h;
+
+#pragma omp parallel num_threads(nthr) reduction(+ : evals_total)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        oentry *scratch = NULL;
+        int cap = 0;
+        int64_t ev = 0;
+        ograd *mine = do_bwd ? grads + (size_t)tid * (size_t)(nw > 0 ? nw : 1) : NULL;
+#pragma omp for schedule(static, 1)
+        for (int j = 0; j < h; ++j) {
+            for (int i = 0; i < w; ++i) {
+                const size_t pix = (size_t)j * w + i;
+                const int cell = (j / OT) * cx_n + (i / OT);
+                double out[7], Tf, mg;
+                int32_t nb;
+                double g7[7];
+                if (do_bwd) {
+                    for (int c = 0; c < 3; ++c) g7[c] = dL_color[c * npx + pix];
+                    g7[3] = dL_depth[pix];
+                    for (int c = 0; c < 3; ++c) g7[4 + c] = dL_normal[c * npx + pix];
+                }
+                render_pixel(&Bn, cam, opts, delta, x0 + i, y0 + j, cell, x0, y0, out, &Tf, &nb, &mg, &ev,
+                             do_bwd ? g7 : NULL, mine, &scratch, &cap);
+                for (int c = 0; c < 3; ++c) color[c * npx + pix] = out[c];
+                depth[pix] = out[3];
+                for (int c = 0; c < 3; ++c) normal[c * npx + pix] = out[4 + c];
+                T_final[pix] = Tf;
+                n_blend[pix] = nb;
+                margin[pix] = mg;
+            }
+        }
+        free(scratch);
+        evals_total += ev;
+    }
+
+    if (do_bwd) {
+        memset(g_center, 0, sizeof(double) * 3 * (size_t)n);
+        memset(g_quat, 0, sizeof(double) * 4 * (size_t)n);
+        memset(g_scale, 0, sizeof(double) * 2 * (size_t)n);
+        memset(g_curv, 0, sizeof(double) * 2 * (size_t)n);
+        memset(g_opac, 0, sizeof(double) * (size_t)n);
+        memset(g_rgb, 0, sizeof(double) * 3 * (size_t)n);
+        for (int64_t i = 0; i < nw; ++i) {
+            ograd S;
+            memset(&S, 0, sizeof S);
+            for (int t = 0; t < nthr; ++t) {
+                const ograd *gt = &grads[(size_t)t * (size_t)nw + (size_t)i];
+                for (int k = 0; k < 9; ++k) S.dRc[k] += gt->dRc[k];
+                for (int k = 0; k < 3; ++k) { S.dcc[k] += gt->dcc[k]; S.drgb[k] += gt->drgb[k]; }
+                for (int k = 0; k < 2; ++k) { S.dl[k] += gt->dl[k]; S.ds[k] += gt->ds[k]; }
+                S.dop += gt->dop;
+            }
+            const int64_t p = ids[i];
+            const oprim *P = &tmp[i];
+            /* cc = W c + t  ->  dc = W^T dcc */
+            for (int j = 0; j < 3; ++j)
+                g_center[3 * p + j] = W[j] * S.dcc[0] + W[3 + j] * S.dcc[1] + W[6 + j] * S.dcc[2];
+            /* Rc = W Rm  ->  dRm = W^T dRc */
+            double dRm[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    dRm[3 * a + b] = W[a] * S.dRc[b] + W[3 + a] * S.dRc[3 + b] + W[6 + a] * S.dRc[6 + b];
+            /* Rm(qhat) entry derivatives, qhat = (w, x, y, z) */
+            const double qw = P->qn[0], qx = P->qn[1], qy = P->qn[2], qz = P->qn[3];
+            double dq[4] = {0, 0, 0, 0};
+            /* R00 = 1 - 2(y^2 + z^2) */
+            dq[2] += -4 * qy * dRm[0]; dq[3] += -4 * qz * dRm[0];
+            /* R01 = 2(xy - wz) */
+            dq[0] += -2 * qz * dRm[1]; dq[1] += 2 * qy * dRm[1]; dq[2] += 2 * qx * dRm[1]; dq[3] += -2 * qw * dRm[1];
+            /* R02 = 2(xz + wy) */
+            dq[0] += 2 * qy * dRm[2]; dq[1] += 2 * qz * dRm[2]; dq[2] += 2 * qw * dRm[2]; dq[3] += 2 * qx * dRm[2];
+            /* R10 = 2(xy + wz) */
+            dq[0] += 2 * qz * dRm[3]; dq[1] += 2 * qy * dRm[3]; dq[2] += 2 * qx * dRm[3]; dq[3] += 2 * qw * dRm[3];
+            /* R11 = 1 - 2(x^2 + z^2) */
+            dq[1] += -4 * qx * dRm[4]; dq[3] += -4 * qz * dRm[4];
+            /* R12 = 2(yz - wx) */
+            dq[0] += -2 * qx * dRm[5]; dq[1] += -2 * qw * dRm[5]; dq[2] += 2 * qz * dRm[5]; dq[3] += 2 * qy * dRm[5];
+            /* R20 = 2(xz - wy) */
+            dq[0] += -2 * qy * dRm[6]; dq[1] += 2 * qz * dRm[6]; dq[2] += -2 * qw * dRm[6]; dq[3] += 2 * qx * dRm[6];
+            /* R21 = 2(yz + wx) */
+            dq[0] += 2 * qx * dRm[7]; dq[1] += 2 * qw * dRm[7]; dq[2] += 2 * qz * dRm[7]; dq[3] += 2 * qy * dRm[7];
+            /* R22 = 1 - 2(x^2 + y^2) */
+            dq[1] += -4 * qx * dRm[8]; dq[2] += -4 * qy * dRm[8];
+            /* qhat = q / |q| */
+            const double dotq = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+            for (int k = 0; k < 4; ++k) g_quat[4 * p + k] = (dq[k] - P->qn[k] * dotq) / P->qlen;
+            g_scale[2 * p] = S.ds[0];
+            g_scale[2 * p + 1] = S.ds[1];
+            g_curv[2 * p] = S.dl[0];
+            g_curv[2 * p + 1] = S.dl[1];
+            g_opac[p] = S.dop;
+            for (int k = 0; k < 3; ++k) g_rgb[3 * p + k] = S.drgb[k];
+        }
+        free(grads);
+    }
+    free(items); free(fill); free(cnt); free(box); free(tmp); free(ids); free(ord);
+    return evals_total;
+}
+
+/*
+ * Single ray against a single primitive (FP64), for pin tests.
+ * out = {ok, linear, t, x, y, z_on_surface, E, G, A, B, C, n_cam[3] (flipped)}.
+ */
+void oracle_ray_hit(const double *c, const double *q, const double *s, const double *l,
+                    const double *cam, const double *dcam, const double *opts, double *out)
+{
+    const double delta[M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1};
+    oprim P;
+    setup_prim(c, q, s, l, 1.0, (const double[3]){0, 0, 0}, cam, cam + 9, &P);
+    ohit H;
+    ray_hit(&P, dcam, opts, delta, &H);
+    for (int i = 0; i < 14; ++i) out[i] = 0.0;
+    out[0] = H.ok;
+    out[1] = H.linear;
+    out[8] = H.A;
+    out[9] = H.B;
+    out[10] = P.C;
+    if (!H.ok) return;
+    out[2] = H.t; out[3] = H.x; out[4] = H.y;
+    out[5] = P.o[2] + H.t * H.d[2];
+    out[6] = H.E;
+    out[7] = exp(-0.5 * H.E);
+    double nl[3], flip, vlen;
+    hit_normal(&P, &H, nl, &flip, &vlen);
+    for (int i = 0; i < 3; ++i)
+        out[11 + i] = flip * (P.Rc[3 * i] * nl[0] + P.Rc[3 * i + 1] * nl[1] + P.Rc[3 * i + 2] * nl[2]);
+}
