@@ -546,3 +546,49 @@ def test_bin_sort_is_stable_key_sort():
         s, e = ranges[t]
         assert np.all(tile[s:e] == t)
         assert (e - s) == np.count_nonzero(tile == t)
+
+
+def _head_on_stack(depths, opac, rgbs):
+    """Planar primitives facing the camera on its principal ray."""
+    n = len(depths)
+    c = np.zeros((n, 3), np.float32)
+    c[:, 2] = depths
+    q = np.tile(np.array([[0, 1, 0, 0]], np.float32), (n, 1))
+    return Scene(center=c, quat=q, scale=np.full((n, 2), 0.3, np.float32), curv=np.zeros((n, 2), np.float32),
+                 opacity=np.asarray(opac, np.float32), rgb=np.asarray(rgbs, np.float32))
+
+
+def test_stop_before_blending_when_T_drops_below_eps():
+    # o = 0.8 per layer: T = 0.2^k; the sixth layer would take T to 6.4e-5 < 1e-4,
+    # so the pixel stops with five layers blended and T_final = 0.2^5
+    depths = np.arange(8, dtype=np.float32) * 0.5 + 1.0
+    rgbs = np.random.default_rng(4).uniform(0, 1, (8, 3))
+    sc = _head_on_stack(depths, [0.8] * 8, rgbs)
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=16, height=16, f=16)
+    cam.cx, cam.cy = 8.5, 8.5
+    r = oracle.render(sc, cam, nthreads=1)
+    a = float(np.float32(0.8))
+    assert r["n_blend"][8, 8] == 5
+    assert abs(r["T_final"][8, 8] - (1 - a) ** 5) < 1e-15
+    exp_c = sum(a * (1 - a) ** k * sc.rgb[k].astype(float) for k in range(5))
+    assert np.allclose(r["color"][:, 8, 8], exp_c, rtol=0, atol=1e-14)
+    exp_d = sum(a * (1 - a) ** k * float(depths[k]) for k in range(5))
+    assert abs(r["depth"][8, 8] - exp_d) < 1e-13
+
+
+def test_equal_depth_ties_follow_primitive_index():
+    # two coincident planes at the same depth: the lower index is in front
+    sc = _head_on_stack([2.0, 2.0], [0.6, 0.5], [[1, 0, 0], [0, 1, 0]])
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=16, height=16, f=16)
+    cam.cx, cam.cy = 8.5, 8.5
+    r = oracle.render(sc, cam, nthreads=1)
+    a0, a1 = float(np.float32(0.6)), float(np.float32(0.5))
+    assert np.allclose(r["color"][:, 8, 8], [a0, (1 - a0) * a1, 0.0], rtol=0, atol=1e-14)
+    # and the key sort keeps emission order for equal keys
+    ks = oracle.keys(sc, cam)
+    assert ks["depth_bits"][0] == ks["depth_bits"][1]
+    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+    for t in range(cam.tiles_x * cam.tiles_y):
+        s, e = ranges[t]
+        if e - s == 2:
+            assert list(prims[s:e]) == [0, 1]
