@@ -1,0 +1,241 @@
+/*
+ * qgs.h -- C ABI of libqgs, a differentiable tile rasterizer for quadric
+ * (paraboloid) Gaussian primitives on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Quadratic Gaussian Splatting (arXiv 2411.16392).  A primitive is a
+ * Gaussian defined on a paraboloid patch: centre c, orientation R (a unit
+ * quaternion), two tangent-plane standard deviations sigma_1, sigma_2, two
+ * curvature coefficients lambda_1, lambda_2 of the explicit height
+ * z = lambda_1 x^2 + lambda_2 y^2 in the local frame (Sec. 3.2, the explicit
+ * form of the paraboloid and the curvature paragraph, lambda_i =
+ * sign(s_i) s_3 / s_i^2), an opacity and an RGB colour.  A pixel's ray meets the
+ * patch where the ray equals the paraboloid (supplement, ray-splat
+ * intersection); the density at the hit is exp(-l^2 / (2 sigma(theta)^2)) with l
+ * the arc length of the normal section through the vertex (Sec. 3.2, geodesic
+ * and sigma(theta) equations); colour, depth and normal are alpha-composited
+ * front to back (Eq. 1 and the normal/curvature render equation).
+ *
+ * Conventions for every entry point
+ *  - All array pointers are DEVICE pointers unless stated otherwise, row-major,
+ *    FP32 unless stated otherwise.  The caller owns every buffer; the library
+ *    never frees caller memory and allocates nothing on these calls.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) unless stated otherwise, and returns a qgs_status (0 = OK,
+ *    negative = error).  Arguments are validated on the host before anything is
+ *    launched; on an argument error nothing is enqueued.
+ *  - Invalid primitives (non-finite parameters, sigma <= 0, zero quaternion,
+ *    centre at or behind the near plane) are culled, not errors.
+ *  - Calls on one stream are ordered; concurrent calls on different streams may
+ *    run together if they do not share output buffers.
+ */
+#ifndef QGS_H
+#define QGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qgs_status;
+#define QGS_OK               0
+#define QGS_ERR_INVALID_ARG (-1) /* null pointer, n < 0, tile != 16, bad size */
+#define QGS_ERR_WORKSPACE   (-2) /* workspace smaller than qgs_workspace_query says */
+#define QGS_ERR_CAPACITY    (-3) /* more tile|primitive pairs than the list capacity */
+#define QGS_ERR_BUDGET      (-4) /* serving: request can never fit the memory budget */
+#define QGS_ERR_HIP         (-5) /* a HIP runtime call failed; see qgs_last_hip_error */
+#define QGS_ERR_NOT_FOUND   (-6) /* serving: unknown request id */
+#define QGS_ERR_STATE       (-7) /* serving: server stopped or request already finished */
+
+typedef void *qgs_stream_t; /* hipStream_t */
+
+/* Bytes of one preprocessed primitive record (see qgs_prim_buf). */
+#define QGS_RECORD_BYTES 128
+
+/* Primitive parameters (Sec. 3.2), structure of arrays, n primitives. */
+typedef struct qgs_scene {
+    const float *center;  /* [n][3] world-space centre c */
+    const float *quat;    /* [n][4] orientation (w, x, y, z), any norm > 0; normalised internally */
+    const float *scale;   /* [n][2] sigma_1, sigma_2 > 0: standard deviations along local x, y */
+    const float *curv;    /* [n][2] lambda_1, lambda_2: local height z = lambda_1 x^2 + lambda_2 y^2 */
+    const float *opacity; /* [n]    opacity in [0, 1] */
+    const float *rgb;     /* [n][3] colour */
+    int64_t n;
+} qgs_scene;
+
+/* Pinhole camera (host memory).  R, t map world to camera: x_cam = R x + t,
+   OpenCV axes (x right, y down, z forward).  Pixel (u, v) looks along the ray
+   through ((u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy, 1). */
+typedef struct qgs_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} qgs_camera;
+
+/* Rendering options (host memory).  Defaults: qgs_default_opts(). */
+typedef struct qgs_render_opts {
+    float near_plane; /* 0.2: centres and hits must have camera depth above it */
+    float k_sigma;    /* 3: a hit is kept when l <= k_sigma * sigma(theta) (Sec. 3.2.1) */
+    float alpha_min;  /* 1/255: hits with smaller alpha are skipped */
+    float alpha_max;  /* 0.99: alpha = min(alpha_max, opacity * G) */
+    float T_eps;      /* 1e-4: a pixel stops before blending a hit that would take T below it */
+    float A_eps;      /* 1e-6: |A| below it (unit ray) takes the tangent-plane root -C/B (supplement) */
+    float bg[3];      /* background colour, added with the final transmittance */
+    int32_t tile;     /* must be 16 (16 x 16 tiles) */
+    uint32_t flags;   /* QGS_* flags below */
+} qgs_render_opts;
+
+#define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */
+#define QGS_ACCUMULATE_GRADS  2u /* backward: add into qgs_scene_grads instead of overwriting */
+#define QGS_COUNT_EVALS       4u /* forward: count evaluated list entries into counters[2] */
+
+/*
+ * Per-primitive preprocess output (device memory, caller-allocated, n entries).
+ *  records     n * QGS_RECORD_BYTES, 128-byte aligned.  Layout of record p as
+ *              32 x 32-bit words: [0..3] pixel rectangle x0, x1, y0, y1 (int32,
+ *              inclusive; x0 > x1 when empty), [4..7] projected centre split as
+ *              U, 0.5 - frac(u_c), V, 0.5 - frac(v_c) (U, V integral floats),
+ *              [8..11] Zc / fx, Zc / fy, Zc, lambda_1, [12..15] lambda_2,
+ *              1/sigma_1^2, 1/sigma_2^2, opacity, [16..24] camera-from-local
+ *              rotation row-major, [25..27] rgb, [28..31] unused.
+ *  depth_key   [n] FP32 bit pattern of the centre's camera-space depth (0 if culled)
+ *  rect        [n][4] tile rectangle tx0, ty0, tx1, ty1 inclusive; (0, 0, -1, -1) if empty
+ *  tiles       [n] number of tiles in rect (0 if culled or off screen)
+ *  pair_offset [n] written by qgs_bin_sort: index of the primitive's first pair
+ *              in emission order (pairs of one primitive are contiguous there)
+ */
+typedef struct qgs_prim_buf {
+    void *records;
+    uint32_t *depth_key;
+    int32_t *rect;
+    uint32_t *tiles;
+    uint32_t *pair_offset;
+    int64_t n;
+} qgs_prim_buf;
+
+/*
+ * Sorted tile lists (device memory, caller-allocated).
+ *  pair_tile, pair_prim  [capacity] tile id and primitive index of each pair,
+ *                        sorted by (tile, depth key, primitive index)
+ *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
+ *  counters              [4] uint32: [0] number of pairs, [1] overflow flag
+ *                        (1 when [0] > capacity: lists and ranges are then empty
+ *                        and the caller must grow and call again), [2] evaluated
+ *                        entries (QGS_COUNT_EVALS), [3] reserved
+ */
+typedef struct qgs_tile_lists {
+    uint32_t *pair_tile;
+    uint32_t *pair_prim;
+    uint32_t *ranges;
+    uint32_t *counters;
+    uint64_t capacity;
+} qgs_tile_lists;
+
+/* Forward outputs, planar, [c][height][width]. */
+typedef struct qgs_images {
+    float *color;    /* [3][H][W] sum w rgb + T_final bg */
+    float *depth;    /* [H][W] sum w t, t along the unit ray */
+    float *normal;   /* [3][H][W] sum w n, camera-space unit normals facing the camera */
+    float *T_final;  /* [H][W] final transmittance */
+    uint32_t *last;  /* [H][W] 1 + position in the tile list of the last blended entry (0: none) */
+} qgs_images;
+
+/* Upstream gradients, same layouts; a NULL plane means zero. */
+typedef struct qgs_image_grads {
+    const float *dcolor;
+    const float *ddepth;
+    const float *dnormal;
+} qgs_image_grads;
+
+/* Parameter gradients, same shapes as qgs_scene. */
+typedef struct qgs_scene_grads {
+    float *center;
+    float *quat;
+    float *scale;
+    float *curv;
+    float *opacity;
+    float *rgb;
+} qgs_scene_grads;
+
+/* Human-readable text for a status code (static storage). */
+const char *qgs_status_string(qgs_status status);
+
+/* Last HIP error code seen by this thread (0 if none). */
+int32_t qgs_last_hip_error(void);
+
+/* Fill *opts with the defaults listed in qgs_render_opts. Host only. */
+void qgs_default_opts(qgs_render_opts *opts);
+
+/*
+ * Host-only size query.  For n primitives, a camera and a pair capacity:
+ *  sort_ws_bytes  workspace of qgs_bin_sort
+ *  bwd_ws_bytes   workspace of qgs_render_bwd for `flags` (QGS_DETERMINISTIC_BWD
+ *                 adds capacity * 64 bytes)
+ * Any output pointer may be NULL.
+ */
+qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t pair_capacity, uint32_t flags,
+                               size_t *sort_ws_bytes, size_t *bwd_ws_bytes);
+
+/*
+ * Projection, culling and conservative screen bounds, one thread per primitive
+ * (Sec. 3.2 congruent transform; supplement, bounding boxes).  Writes records,
+ * depth_key, rect and tiles of `out`.  The rectangle bounds every pixel whose ray
+ * can meet the primitive inside k_sigma: since the arc-length factor is >= 1, an
+ * accepted hit has |x| <= k sigma_1, |y| <= k sigma_2 and a height between the
+ * extremes of lambda_1 x^2 + lambda_2 y^2 over that ellipse, so the projection
+ * of this (slightly inflated) local box is used.  Errors: QGS_ERR_INVALID_ARG.
+ */
+qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const qgs_render_opts *opts,
+                          qgs_prim_buf *out, qgs_stream_t stream);
+
+/*
+ * Tile|depth key lists (supplement, per-tile sorting: one global sort keyed by
+ * tile and depth).  Produces, for every tile, the primitives whose rectangle
+ * covers it, ordered by depth key and then primitive index, bit-identical to a
+ * stable sort of the 64-bit keys (tile << 32 | depth_key) emitted primitive by
+ * primitive, tiles row-major within each rectangle.  Integer-only: a radix sort
+ * of the depth keys, emission in that order, then a stable radix sort by tile.
+ * Also writes prims->pair_offset and lists->counters.
+ * host_num_pairs: if non-NULL the call synchronises `stream` once and stores the
+ * pair count there, and returns QGS_ERR_CAPACITY if it exceeds the capacity; if
+ * NULL the call never synchronises and the overflow is reported on the device
+ * (counters[1]).  Errors: QGS_ERR_INVALID_ARG, QGS_ERR_WORKSPACE, QGS_ERR_CAPACITY.
+ */
+qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_render_opts *opts,
+                        qgs_tile_lists *lists, void *ws, size_t ws_bytes, uint64_t *host_num_pairs,
+                        qgs_stream_t stream);
+
+/*
+ * Forward rasterizer: one 256-thread workgroup per 16 x 16 tile, primitive
+ * records staged in LDS in batches, per-pixel ray-paraboloid intersection with
+ * near/far root selection and the k_sigma geodesic cut-off, geodesic Gaussian
+ * density, front-to-back compositing with stop once T would fall below T_eps.
+ * Writes all planes of `out`.  Errors: QGS_ERR_INVALID_ARG.
+ */
+qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists, const qgs_camera *cam,
+                          const qgs_render_opts *opts, qgs_images *out, qgs_stream_t stream);
+
+/*
+ * Backward: adjoint of qgs_render_fwd and qgs_preprocess.  Each tile's list is
+ * walked back to front from each pixel's `last` entry, recomputing
+ * transmittance by division (supplement, back-to-front adjoint), with
+ * per-primitive gradients reduced across the tile's pixels in LDS before one
+ * global atomic per field per (tile, primitive); QGS_DETERMINISTIC_BWD instead
+ * stores one partial per pair and sums each primitive's partials in a fixed
+ * order.  Then the chain rule to the scene parameters, one thread per
+ * primitive.  `fwd` must hold T_final and last from the matching forward.
+ * ws: at least bwd_ws_bytes from qgs_workspace_query.
+ * Errors: QGS_ERR_INVALID_ARG, QGS_ERR_WORKSPACE.
+ */
+qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
+                          const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
+                          const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
+                          qgs_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QGS_H */

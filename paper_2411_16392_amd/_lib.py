@@ -1,0 +1,168 @@
+"""ctypes binding of libqgs (include/qgs.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and raises
+QgsError on a non-zero status.  Loading fails loudly when the library has not
+been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqgs.so")
+
+c_void_p, c_int32, c_uint32, c_int64, c_uint64, c_float = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                                            ctypes.c_int64, ctypes.c_uint64, ctypes.c_float)
+
+QGS_OK = 0
+QGS_ERR_INVALID_ARG = -1
+QGS_ERR_WORKSPACE = -2
+QGS_ERR_CAPACITY = -3
+QGS_ERR_BUDGET = -4
+QGS_ERR_HIP = -5
+QGS_ERR_NOT_FOUND = -6
+QGS_ERR_STATE = -7
+
+QGS_RECORD_BYTES = 128
+QGS_DETERMINISTIC_BWD = 1
+QGS_ACCUMULATE_GRADS = 2
+QGS_COUNT_EVALS = 4
+
+
+class QgsScene(ctypes.Structure):
+    _fields_ = [("center", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("curv", c_void_p),
+                ("opacity", c_void_p), ("rgb", c_void_p), ("n", c_int64)]
+
+
+class QgsCamera(ctypes.Structure):
+    _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float), ("cx", c_float),
+                ("cy", c_float), ("width", c_int32), ("height", c_int32)]
+
+
+class QgsRenderOpts(ctypes.Structure):
+    _fields_ = [("near_plane", c_float), ("k_sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
+                ("T_eps", c_float), ("A_eps", c_float), ("bg", c_float * 3), ("tile", c_int32), ("flags", c_uint32)]
+
+
+class QgsPrimBuf(ctypes.Structure):
+    _fields_ = [("records", c_void_p), ("depth_key", c_void_p), ("rect", c_void_p), ("tiles", c_void_p),
+                ("pair_offset", c_void_p), ("n", c_int64)]
+
+
+class QgsTileLists(ctypes.Structure):
+    _fields_ = [("pair_tile", c_void_p), ("pair_prim", c_void_p), ("ranges", c_void_p), ("counters", c_void_p),
+                ("capacity", c_uint64)]
+
+
+class QgsImages(ctypes.Structure):
+    _fields_ = [("color", c_void_p), ("depth", c_void_p), ("normal", c_void_p), ("T_final", c_void_p),
+                ("last", c_void_p)]
+
+
+class QgsImageGrads(ctypes.Structure):
+    _fields_ = [("dcolor", c_void_p), ("ddepth", c_void_p), ("dnormal", c_void_p)]
+
+
+class QgsSceneGrads(ctypes.Structure):
+    _fields_ = [("center", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("curv", c_void_p),
+                ("opacity", c_void_p), ("rgb", c_void_p)]
+
+
+class QgsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().qgs_status_string(status).decode()
+        if status == QGS_ERR_HIP:
+            msg += f" (hipError {lib().qgs_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+
+
+_handle = None
+
+# name -> (argtypes, restype)
+_SIGS = {
+    "qgs_status_string": ([c_int32], ctypes.c_char_p),
+    "qgs_last_hip_error": ([], c_int32),
+    "qgs_default_opts": ([ctypes.POINTER(QgsRenderOpts)], None),
+    "qgs_workspace_query": ([c_int64, ctypes.POINTER(QgsCamera), c_uint64, c_uint32,
+                             ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "qgs_preprocess": ([ctypes.POINTER(QgsScene), ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts),
+                        ctypes.POINTER(QgsPrimBuf), c_void_p], c_int32),
+    "qgs_bin_sort": ([ctypes.POINTER(QgsPrimBuf), ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts),
+                      ctypes.POINTER(QgsTileLists), c_void_p, ctypes.c_size_t, ctypes.POINTER(c_uint64),
+                      c_void_p], c_int32),
+    "qgs_render_fwd": ([ctypes.POINTER(QgsPrimBuf), ctypes.POINTER(QgsTileLists), ctypes.POINTER(QgsCamera),
+                        ctypes.POINTER(QgsRenderOpts), ctypes.POINTER(QgsImages), c_void_p], c_int32),
+    "qgs_render_bwd": ([ctypes.POINTER(QgsScene), ctypes.POINTER(QgsPrimBuf), ctypes.POINTER(QgsTileLists),
+                        ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts), ctypes.POINTER(QgsImages),
+                        ctypes.POINTER(QgsImageGrads), ctypes.POINTER(QgsSceneGrads), c_void_p, ctypes.c_size_t,
+                        c_void_p], c_int32),
+}
+
+
+def lib():
+    """The loaded libqgs.so; raises if it has not been built."""
+    global _handle
+    if _handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_16392_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _handle = L
+    return _handle
+
+
+def exported_symbols():
+    return list(_SIGS.keys())
+
+
+def _check(status: int, where: str):
+    if status != QGS_OK:
+        raise QgsError(status, where)
+
+
+def qgs_default_opts() -> QgsRenderOpts:
+    o = QgsRenderOpts()
+    lib().qgs_default_opts(ctypes.byref(o))
+    return o
+
+
+def qgs_workspace_query(n: int, cam: QgsCamera, capacity: int, flags: int = 0):
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(lib().qgs_workspace_query(n, ctypes.byref(cam), capacity, flags, ctypes.byref(a), ctypes.byref(b)),
+           "qgs_workspace_query")
+    return a.value, b.value
+
+
+def qgs_preprocess(scene: QgsScene, cam: QgsCamera, opts: QgsRenderOpts, out: QgsPrimBuf, stream=None):
+    _check(lib().qgs_preprocess(ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(out),
+                                stream), "qgs_preprocess")
+
+
+def qgs_bin_sort(prims: QgsPrimBuf, cam: QgsCamera, opts: QgsRenderOpts, lists: QgsTileLists, ws: int,
+                 ws_bytes: int, want_count: bool = True, stream=None, raise_on_capacity: bool = True):
+    """Returns (status, num_pairs or None)."""
+    cnt = c_uint64(0)
+    st = lib().qgs_bin_sort(ctypes.byref(prims), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(lists), ws,
+                            ws_bytes, ctypes.byref(cnt) if want_count else None, stream)
+    if st == QGS_ERR_CAPACITY and not raise_on_capacity:
+        return st, cnt.value
+    _check(st, "qgs_bin_sort")
+    return st, (cnt.value if want_count else None)
+
+
+def qgs_render_fwd(prims: QgsPrimBuf, lists: QgsTileLists, cam: QgsCamera, opts: QgsRenderOpts, out: QgsImages,
+                   stream=None):
+    _check(lib().qgs_render_fwd(ctypes.byref(prims), ctypes.byref(lists), ctypes.byref(cam), ctypes.byref(opts),
+                                ctypes.byref(out), stream), "qgs_render_fwd")
+
+
+def qgs_render_bwd(scene: QgsScene, prims: QgsPrimBuf, lists: QgsTileLists, cam: QgsCamera, opts: QgsRenderOpts,
+                   fwd: QgsImages, dL: QgsImageGrads, out: QgsSceneGrads, ws: int, ws_bytes: int, stream=None):
+    _check(lib().qgs_render_bwd(ctypes.byref(scene), ctypes.byref(prims), ctypes.byref(lists), ctypes.byref(cam),
+                                ctypes.byref(opts), ctypes.byref(fwd), ctypes.byref(dL), ctypes.byref(out), ws,
+                                ws_bytes, stream), "qgs_render_bwd")

@@ -1,0 +1,455 @@
+// Tile|depth key lists: integer-only, bit-exact.
+//
+// The required order is a stable sort of the 64-bit keys (tile << 32 | depth)
+// emitted primitive by primitive (tiles row-major within each rectangle).  An
+// LSD radix sort of those keys would first sort by the depth bits; since all
+// pairs of one primitive share its depth, that part is done once per
+// primitive instead of once per pair: the primitives are radix-sorted by depth
+// key (stable, so ties keep primitive order), their pairs are emitted in that
+// order, and a stable radix sort by tile id finishes the job.  The result is
+// identical to the 64-bit sort; the pair arrays move 2 passes x 8 bytes instead
+// of ceil((32 + tile bits) / 8) passes x 12 bytes.
+//
+// Radix passes are 8-bit LSD passes in three kernels: per-block digit counts,
+// a device-wide exclusive scan of the digit-major count table, and a scatter
+// that ranks each element stably inside its block (wave ballots on the digit
+// bits, then per-wave counts in LDS), stages the block's elements in LDS in
+// digit order and writes them out in contiguous runs.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qgs_internal.hpp"
+
+namespace qgs {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;  // elements per block
+constexpr int SCAN_CHUNK = 4096;
+
+static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// element count: a host bound, or the pair count on the device (0 on overflow)
+struct Count {
+    const uint32_t *counters;  // null: use n
+    uint64_t n;
+    __device__ inline uint64_t get() const
+    {
+        if (!counters) return n;
+        if (counters[1]) return 0;
+        const uint64_t c = counters[0];
+        return c < n ? c : n;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// block-wide exclusive scan of one value per thread (256 threads)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T wave_incl_scan(T v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T block_excl_scan(T v, T *s_wave /* [4] */, T &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const T inc = wave_incl_scan(v, lane);
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    T pre = 0;
+    for (int w = 0; w < wave; ++w) pre += s_wave[w];
+    total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+    return pre + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan: partial sums, scan of partials, apply
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_partials(const T *in, uint64_t n, T *part)
+{
+    __shared__ T s_wave[4];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_CHUNK;
+    T acc = 0;
+    for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
+        const uint64_t i = base + (uint64_t)k * 256 + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    T total;
+    (void)block_excl_scan(acc, s_wave, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_top(T *part, uint64_t nparts, T *grand_total)
+{
+    __shared__ T s_wave[4];
+    T carry = 0;
+    for (uint64_t base = 0; base < nparts; base += 256) {
+        const uint64_t i = base + threadIdx.x;
+        const T v = i < nparts ? part[i] : 0;
+        T total;
+        const T ex = block_excl_scan(v, s_wave, total);
+        if (i < nparts) part[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0 && grand_total) *grand_total = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_t n, const T *part)
+{
+    __shared__ T s_wave[4];
+    // blocked arrangement: thread t owns items [t*16, t*16 + 16) of the chunk
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_CHUNK + (uint64_t)threadIdx.x * (SCAN_CHUNK / 256);
+    T v[SCAN_CHUNK / 256];
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
+        const uint64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        acc += v[k];
+    }
+    T total;
+    T run = block_excl_scan(acc, s_wave, total) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
+        const uint64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}
+
+template <typename T>
+static hipError_t device_excl_scan(const T *in, T *out, uint64_t n, T *part, T *grand_total, hipStream_t stream)
+{
+    const uint64_t nb = cdiv(n, SCAN_CHUNK);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_partials<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, n, part);
+    hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(256), 0, stream, part, nb, grand_total);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, out, n, (const T *)part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// radix pass kernels (u32 keys, u32 values, 8-bit digit at `shift`)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t *keys, Count cnt, int shift, uint32_t *hist,
+                                                           uint32_t nblocks)
+{
+    __shared__ uint32_t h[4][256];
+    for (int i = threadIdx.x; i < 1024; i += RS_THREADS) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t n = cnt.get();
+    const uint64_t base = (uint64_t)blockIdx.x * RS_CHUNK;
+    const int wave = threadIdx.x >> 6;
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const uint64_t i = base + (uint64_t)k * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    hist[(uint64_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                              uint32_t *keys_out, uint32_t *vals_out, Count cnt,
+                                                              int shift, const uint32_t *hist_scan, uint32_t nblocks)
+{
+    __shared__ uint32_t s_keys[RS_CHUNK];
+    __shared__ uint32_t s_vals[RS_CHUNK];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t goff[256];
+    __shared__ uint32_t s_wave[4];
+
+    const uint64_t n = cnt.get();
+    const uint64_t base = (uint64_t)blockIdx.x * RS_CHUNK;
+    if (base >= n) return;  // uniform for the block
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = 0;
+    wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+    goff[tid] = hist_scan[(uint64_t)tid * nblocks + blockIdx.x];
+    __syncthreads();
+
+    uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+    const uint64_t lt = __lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const uint64_t i = base + (uint64_t)k * RS_THREADS + tid;
+        const bool valid = i < n;
+        const uint32_t kk = valid ? keys_in[i] : 0u;
+        const uint32_t d = (kk >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        if (!valid) peers = 0;
+        const uint32_t r_in = (uint32_t)__popcll(peers & lt);
+        if (valid && r_in == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t pre = run[d];
+        for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+        rank[k] = pre + r_in;
+        key[k] = kk;
+        val[k] = valid ? vals_in[i] : 0u;
+        __syncthreads();
+        run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+        __syncthreads();
+    }
+    uint32_t total;
+    lstart[tid] = block_excl_scan(run[tid], s_wave, total);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const uint64_t i = base + (uint64_t)k * RS_THREADS + tid;
+        if (i < n) {
+            const uint32_t d = (key[k] >> shift) & 255u;
+            const uint32_t pos = lstart[d] + rank[k];
+            s_keys[pos] = key[k];
+            s_vals[pos] = val[k];
+        }
+    }
+    __syncthreads();
+    const uint32_t m = (uint32_t)((n - base) < (uint64_t)RS_CHUNK ? (n - base) : (uint64_t)RS_CHUNK);
+    for (uint32_t i = tid; i < m; i += RS_THREADS) {
+        const uint32_t kk = s_keys[i];
+        const uint32_t d = (kk >> shift) & 255u;
+        const uint32_t dst = goff[d] + (i - lstart[d]);
+        keys_out[dst] = kk;
+        vals_out[dst] = s_vals[i];
+    }
+}
+
+// one stable 8-bit pass; grid sized for `bound` elements
+static hipError_t radix_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, Count cnt,
+                             uint64_t bound, int shift, const SortWorkspace &ws, hipStream_t stream)
+{
+    const uint64_t nb = cdiv(bound, RS_CHUNK);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, cnt, shift, ws.hist,
+                       (uint32_t)nb);
+    hipError_t e = device_excl_scan<uint32_t>(ws.hist, ws.hist, 256 * nb, reinterpret_cast<uint32_t *>(ws.part),
+                                              (uint32_t *)nullptr, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, vi, ko, vo, cnt, shift,
+                       (const uint32_t *)ws.hist, (uint32_t)nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// bin / sort stages
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_depth_init(const uint32_t *depth_key, const uint32_t *tiles, int64_t n,
+                                                    uint32_t *keys, uint32_t *vals)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    // primitives without tiles emit no pairs; they sort last
+    keys[p] = tiles[p] ? depth_key[p] : 0xFFFFFFFFu;
+    vals[p] = (uint32_t)p;
+}
+
+__global__ __launch_bounds__(256) void k_gather_tiles(const uint32_t *order, const uint32_t *tiles, int64_t n,
+                                                      uint64_t *out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    out[r] = tiles[order[r]];
+}
+
+__global__ void k_set_counters(const uint64_t *total, uint64_t capacity, uint32_t *counters)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint64_t t = *total;
+        counters[0] = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+        counters[1] = t > capacity ? 1u : 0u;
+        counters[2] = 0u;
+        counters[3] = 0u;
+    }
+}
+
+// pair_offset[p] = first emission index of primitive p
+__global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t *order, const uint64_t *off, int64_t n,
+                                                      uint32_t *pair_offset)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t o = off[r];
+    pair_offset[order[r]] = o > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)o;
+}
+
+// Each block emits the pairs of 256 consecutive primitives in depth order;
+// its threads stride over the block's pair range and find their primitive by
+// binary search of the LDS copy of the offsets.
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
+                                              int64_t n, int32_t tiles_x, const uint32_t *counters, uint32_t *out_tile,
+                                              uint32_t *out_prim)
+{
+    __shared__ uint32_t s_off[257];
+    __shared__ uint32_t s_prim[256], s_x0[256], s_y0[256], s_w[256];
+    if (counters[1]) return;  // overflow: nothing valid to emit
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    const int t = threadIdx.x;
+    const uint64_t base = off[r0];
+    const int64_t r = r0 + t;
+    if (r < n) {
+        const uint32_t p = order[r];
+        s_off[t] = (uint32_t)(off[r] - base);
+        s_prim[t] = p;
+        s_x0[t] = (uint32_t)rect[4 * p];
+        s_y0[t] = (uint32_t)rect[4 * p + 1];
+        s_w[t] = (uint32_t)(rect[4 * p + 2] - rect[4 * p] + 1);
+    } else {
+        s_off[t] = (uint32_t)(off[n] - base);
+        s_prim[t] = 0;
+        s_x0[t] = s_y0[t] = 0;
+        s_w[t] = 1;
+    }
+    if (t == 0) {
+        const int64_t re = r0 + 256 < n ? r0 + 256 : n;
+        s_off[256] = (uint32_t)(off[re] - base);
+    }
+    __syncthreads();
+    const uint32_t total = s_off[256];
+    for (uint32_t j = t; j < total; j += 256) {
+        // last k with s_off[k] <= j
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t local = j - s_off[lo];
+        const uint32_t w = s_w[lo];
+        const uint32_t ty = s_y0[lo] + local / w, tx = s_x0[lo] + local % w;
+        out_tile[base + j] = ty * (uint32_t)tiles_x + tx;
+        out_prim[base + j] = s_prim[lo];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt, uint32_t *ranges)
+{
+    const uint64_t n = cnt.get();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = tile[i];
+    if (i == 0 || tile[i - 1] != t) ranges[2 * (uint64_t)t] = (uint32_t)i;
+    if (i == n - 1 || tile[i + 1] != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, stream, p, v, n);
+    return hipGetLastError();
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
+{
+    SortWorkspace w{};
+    const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+    const uint64_t nbmax = cdiv(nn > capacity ? nn : capacity, RS_CHUNK) + 1;
+    const uint64_t nparts = cdiv(nn + 1, SCAN_CHUNK) + cdiv(256 * nbmax, SCAN_CHUNK) + 64;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return base ? (void *)((char *)base + at) : nullptr;
+    };
+    w.dkA = (uint32_t *)take(4 * nn);
+    w.dvA = (uint32_t *)take(4 * nn);
+    w.dkB = (uint32_t *)take(4 * nn);
+    w.dvB = (uint32_t *)take(4 * nn);
+    w.off = (uint64_t *)take(8 * (nn + 1));
+    w.part = (uint64_t *)take(8 * nparts);
+    w.hist = (uint32_t *)take(4 * 256 * nbmax);
+    w.tileT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
+    w.primT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
+    w.bytes = o;
+    return w;
+}
+
+hipError_t bin_sort_phase1(const BinSortArgs &a, const SortWorkspace &ws, hipStream_t stream)
+{
+    const int64_t n = a.n;
+    const unsigned pb = (unsigned)cdiv((uint64_t)(n > 0 ? n : 1), 256);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_depth_init, dim3(pb), dim3(256), 0, stream, a.depth_key, a.tiles, n, ws.dkA, ws.dvA);
+        // 4 stable passes over the 32-bit depth keys: A -> B -> A -> B -> A
+        Count c{nullptr, (uint64_t)n};
+        hipError_t e;
+        e = radix_pass(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 0, ws, stream);
+        if (e != hipSuccess) return e;
+        e = radix_pass(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 8, ws, stream);
+        if (e != hipSuccess) return e;
+        e = radix_pass(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 16, ws, stream);
+        if (e != hipSuccess) return e;
+        e = radix_pass(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 24, ws, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gather_tiles, dim3(pb), dim3(256), 0, stream, ws.dvA, a.tiles, n, ws.off);
+        e = device_excl_scan<uint64_t>(ws.off, ws.off, (uint64_t)n, ws.part, ws.off + n, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_pair_offsets, dim3(pb), dim3(256), 0, stream, ws.dvA, ws.off, n, a.pair_offset);
+    } else {
+        hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws.off), 0u, 2, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_set_counters, dim3(1), dim3(64), 0, stream, ws.off + (n > 0 ? n : 0), a.capacity,
+                       a.counters);
+    return hipGetLastError();
+}
+
+hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, hipStream_t stream)
+{
+    const int64_t n = a.n;
+    const uint64_t ntiles = (uint64_t)a.tiles_x * (uint64_t)a.tiles_y;
+    int bits = 1;
+    while ((1ull << bits) < ntiles) ++bits;
+    const int passes = (bits + 7) / 8;
+    hipError_t e = launch_fill_u32(a.ranges, 0u, 2 * ntiles, stream);
+    if (e != hipSuccess) return e;
+    if (bound > a.capacity) bound = a.capacity;
+    if (n <= 0 || bound == 0) return hipSuccess;
+    // emit into the buffer that makes the final pass land in the caller's lists
+    uint32_t *et = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
+    uint32_t *ep = (passes % 2 == 0) ? a.pair_prim : ws.primT;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA, ws.off, a.rect,
+                       n, a.tiles_x, a.counters, et, ep);
+    Count c{a.counters, bound};
+    uint32_t *ki = et, *vi = ep;
+    for (int pass = 0; pass < passes; ++pass) {
+        uint32_t *ko = (ki == a.pair_tile) ? ws.tileT : a.pair_tile;
+        uint32_t *vo = (vi == a.pair_prim) ? ws.primT : a.pair_prim;
+        e = radix_pass(ki, vi, ko, vo, c, bound, 8 * pass, ws, stream);
+        if (e != hipSuccess) return e;
+        ki = ko;
+        vi = vo;
+    }
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream, (const uint32_t *)a.pair_tile,
+                       c, a.ranges);
+    return hipGetLastError();
+}
+
+}  // namespace qgs

@@ -1,0 +1,229 @@
+// Per-primitive preprocess (projection, culling, conservative screen bounds)
+// and its backward (record gradients -> scene parameter gradients).
+//
+// The forward runs in FP64 with a fixed operation order: its discrete outputs
+// (cull flag, depth key, rectangles) must be reproducible bit for bit, and the
+// projected centre is split into integer and fractional pixel parts at full
+// precision for the rasterizer's centre-relative frame.  Contraction is off
+// for this file; fma() appears only where the order of operations is specified.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "qgs_device.hpp"
+#include "qgs_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace qgs {
+
+__device__ inline bool finite_f(float v) { return __builtin_isfinite(v); }
+
+__global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+
+    float4 *rec = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.records) + p * 128);
+    int32_t *rt = a.rect + 4 * p;
+    const float4 empty_rect = make_float4(__int_as_float(0), __int_as_float(-1), __int_as_float(0), __int_as_float(-1));
+
+    const float cf0 = a.center[3 * p], cf1 = a.center[3 * p + 1], cf2 = a.center[3 * p + 2];
+    const float qw = a.quat[4 * p], qx = a.quat[4 * p + 1], qy = a.quat[4 * p + 2], qz = a.quat[4 * p + 3];
+    const float sf1 = a.scale[2 * p], sf2 = a.scale[2 * p + 1];
+    const float lf1 = a.curv[2 * p], lf2 = a.curv[2 * p + 1];
+    const float op = a.opacity[p];
+    const float r0 = a.rgb[3 * p], r1 = a.rgb[3 * p + 1], r2 = a.rgb[3 * p + 2];
+
+    bool ok = finite_f(cf0) && finite_f(cf1) && finite_f(cf2) && finite_f(qw) && finite_f(qx) && finite_f(qy) &&
+              finite_f(qz) && finite_f(sf1) && finite_f(sf2) && finite_f(lf1) && finite_f(lf2) && finite_f(op) &&
+              finite_f(r0) && finite_f(r1) && finite_f(r2) && sf1 > 0.0f && sf2 > 0.0f;
+    const double w = qw, x = qx, y = qy, z = qz;
+    const double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+    const double qn = (ww + xx) + (yy + zz);
+    ok = ok && qn > 0.0;
+
+    double cc[3] = {0.0, 0.0, 0.0};
+    float zf = 0.0f;
+    if (ok) {
+        for (int i = 0; i < 3; ++i)
+            cc[i] = fma((double)a.cam.R[3 * i], (double)cf0,
+                        fma((double)a.cam.R[3 * i + 1], (double)cf1, fma((double)a.cam.R[3 * i + 2], (double)cf2, (double)a.cam.t[i])));
+        zf = (float)cc[2];
+        ok = zf > a.near_plane;
+    }
+    if (!ok) {
+        rec[0] = empty_rect;
+        a.depth_key[p] = 0u;
+        rt[0] = 0; rt[1] = 0; rt[2] = -1; rt[3] = -1;
+        a.tiles[p] = 0u;
+        return;
+    }
+
+    // rotation of q / |q| from the unnormalised quaternion
+    const double s = 2.0 / qn;
+    const double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+    double Rm[9];
+    Rm[0] = 1.0 - s * (yy + zz); Rm[1] = s * (xy - wz);        Rm[2] = s * (xz + wy);
+    Rm[3] = s * (xy + wz);       Rm[4] = 1.0 - s * (xx + zz);  Rm[5] = s * (yz - wx);
+    Rm[6] = s * (xz - wy);       Rm[7] = s * (yz + wx);        Rm[8] = 1.0 - s * (xx + yy);
+    double Rc[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            Rc[3 * i + j] = fma((double)a.cam.R[3 * i], Rm[j],
+                                fma((double)a.cam.R[3 * i + 1], Rm[3 + j], (double)a.cam.R[3 * i + 2] * Rm[6 + j]));
+
+    // local box of the support (see qgs_preprocess in qgs.h)
+    const double s1 = sf1, s2 = sf2, l1 = lf1, l2 = lf2;
+    const double infl = 1.0 + 1.0 / 1024.0;
+    const double k = a.k_sigma;
+    const double hx = (k * s1) * infl, hy = (k * s2) * infl;
+    const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
+    const double k2 = k * k;
+    const double smax = s1 > s2 ? s1 : s2;
+    const double zcap = k * smax;
+    double lo = 0.0, hi = 0.0;
+    lo = m1 < lo ? m1 : lo; lo = m2 < lo ? m2 : lo;
+    hi = m1 > hi ? m1 : hi; hi = m2 > hi ? m2 : hi;
+    double zlo = k2 * lo, zhi = k2 * hi;
+    if (zlo < -zcap) zlo = -zcap;
+    if (zhi > zcap) zhi = zcap;
+    const double zpad = zcap / 1024.0;
+    zlo = zlo * infl - zpad;
+    zhi = zhi * infl + zpad;
+
+    const double fx = a.cam.fx, fy = a.cam.fy, cxp = a.cam.cx, cyp = a.cam.cy;
+    const double near_d = a.near_plane;
+    bool behind = false;
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    for (int c = 0; c < 8; ++c) {
+        const double X = (c & 1) ? hx : -hx, Y = (c & 2) ? hy : -hy, Z = (c & 4) ? zhi : zlo;
+        double P[3];
+        for (int i = 0; i < 3; ++i) P[i] = fma(Rc[3 * i], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
+        if (!(P[2] > near_d)) {
+            behind = true;
+            continue;
+        }
+        const double u = fma(fx, P[0] / P[2], cxp), v = fma(fy, P[1] / P[2], cyp);
+        umin = u < umin ? u : umin;
+        umax = u > umax ? u : umax;
+        vmin = v < vmin ? v : vmin;
+        vmax = v > vmax ? v : vmax;
+    }
+    const int W = a.cam.width, H = a.cam.height;
+    int px0, px1, py0, py1;
+    bool empty = false;
+    if (behind) {
+        px0 = 0; px1 = W - 1; py0 = 0; py1 = H - 1;
+    } else {
+        const double pad_px = 1.0 / 64.0;
+        const double a0 = (umin - 0.5) - pad_px, a1 = (umax - 0.5) + pad_px;
+        const double b0 = (vmin - 0.5) - pad_px, b1 = (vmax - 0.5) + pad_px;
+        if (a1 < 0.0 || a0 > (double)(W - 1) || b1 < 0.0 || b0 > (double)(H - 1)) {
+            empty = true;
+            px0 = py0 = 0;
+            px1 = py1 = -1;
+        } else {
+            px0 = a0 <= 0.0 ? 0 : (int)ceil(a0);
+            px1 = a1 >= (double)(W - 1) ? W - 1 : (int)floor(a1);
+            py0 = b0 <= 0.0 ? 0 : (int)ceil(b0);
+            py1 = b1 >= (double)(H - 1) ? H - 1 : (int)floor(b1);
+            empty = px0 > px1 || py0 > py1;
+        }
+    }
+    a.depth_key[p] = __float_as_uint(zf);
+    if (empty) {
+        rec[0] = empty_rect;
+        rt[0] = 0; rt[1] = 0; rt[2] = -1; rt[3] = -1;
+        a.tiles[p] = 0u;
+        return;
+    }
+    const int tx0 = px0 / TILE, tx1 = px1 / TILE, ty0 = py0 / TILE, ty1 = py1 / TILE;
+    rt[0] = tx0; rt[1] = ty0; rt[2] = tx1; rt[3] = ty1;
+    a.tiles[p] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+
+    // projected centre split into integer + fraction, and the record
+    const double uc = fma(fx, cc[0] / cc[2], cxp), vc = fma(fy, cc[1] / cc[2], cyp);
+    const double U = floor(uc), V = floor(vc);
+    const float hu = (float)(0.5 - (uc - U)), hv = (float)(0.5 - (vc - V));
+    rec[0] = make_float4(__int_as_float(px0), __int_as_float(px1), __int_as_float(py0), __int_as_float(py1));
+    rec[1] = make_float4((float)U, hu, (float)V, hv);
+    rec[2] = make_float4((float)(cc[2] / fx), (float)(cc[2] / fy), zf, lf1);
+    rec[3] = make_float4(lf2, (float)(1.0 / (s1 * s1)), (float)(1.0 / (s2 * s2)), op);
+    rec[4] = make_float4((float)Rc[0], (float)Rc[1], (float)Rc[2], (float)Rc[3]);
+    rec[5] = make_float4((float)Rc[4], (float)Rc[5], (float)Rc[6], (float)Rc[7]);
+    rec[6] = make_float4((float)Rc[8], r0, r1, r2);
+    rec[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Chain rule from the record gradients (rotation as a right perturbation
+// Rc exp([phi]x), centre depth, projected centre, curvatures, inverse variances,
+// opacity, colour) to the scene parameters.
+__global__ __launch_bounds__(256) void k_preprocess_bwd(PreprocessBwdArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const float *g = a.grad_rec + 16 * p;
+    double gc[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gs[2] = {0, 0};
+    const bool active = a.tiles[p] != 0u;
+    if (active) {
+        const float cf0 = a.center[3 * p], cf1 = a.center[3 * p + 1], cf2 = a.center[3 * p + 2];
+        double cc[3];
+        for (int i = 0; i < 3; ++i)
+            cc[i] = fma((double)a.cam.R[3 * i], (double)cf0,
+                        fma((double)a.cam.R[3 * i + 1], (double)cf1, fma((double)a.cam.R[3 * i + 2], (double)cf2, (double)a.cam.t[i])));
+        const double gZ = g[G_ZC], guc = g[G_UC], gvc = g[G_VC];
+        // u_c = fx Xc / Zc + cx, v_c = fy Yc / Zc + cy
+        const double iz = 1.0 / cc[2];
+        const double dX = guc * a.cam.fx * iz;
+        const double dY = gvc * a.cam.fy * iz;
+        const double dZ = gZ - (guc * a.cam.fx * cc[0] + gvc * a.cam.fy * cc[1]) * iz * iz;
+        // c_cam = W c + t
+        for (int j = 0; j < 3; ++j)
+            gc[j] = (double)a.cam.R[j] * dX + (double)a.cam.R[3 + j] * dY + (double)a.cam.R[6 + j] * dZ;
+        // rotation: Rm(qhat) -> Rm(qhat (1, phi/2)), so dL/dqhat = (-2 g.v, 2 (w g + v x g))
+        const double q0 = a.quat[4 * p], q1 = a.quat[4 * p + 1], q2 = a.quat[4 * p + 2], q3 = a.quat[4 * p + 3];
+        const double len = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        const double w = q0 / len, vx = q1 / len, vy = q2 / len, vz = q3 / len;
+        const double f0 = g[G_PHI0], f1 = g[G_PHI1], f2 = g[G_PHI2];
+        gq[0] = -2.0 * (f0 * vx + f1 * vy + f2 * vz) / len;
+        gq[1] = 2.0 * (w * f0 + (vy * f2 - vz * f1)) / len;
+        gq[2] = 2.0 * (w * f1 + (vz * f0 - vx * f2)) / len;
+        gq[3] = 2.0 * (w * f2 + (vx * f1 - vy * f0)) / len;
+        // k_i = 1 / sigma_i^2
+        const double s1 = a.scale[2 * p], s2 = a.scale[2 * p + 1];
+        gs[0] = -2.0 * g[G_K1] / (s1 * s1 * s1);
+        gs[1] = -2.0 * g[G_K2] / (s2 * s2 * s2);
+    }
+    const float vals[15] = {(float)gc[0], (float)gc[1], (float)gc[2], (float)gq[0], (float)gq[1], (float)gq[2],
+                            (float)gq[3], (float)gs[0], (float)gs[1], active ? g[G_L1] : 0.0f, active ? g[G_L2] : 0.0f,
+                            active ? g[G_OP] : 0.0f, active ? g[G_R] : 0.0f, active ? g[G_G] : 0.0f,
+                            active ? g[G_B] : 0.0f};
+    float *dst[15] = {a.out.center + 3 * p, a.out.center + 3 * p + 1, a.out.center + 3 * p + 2,
+                      a.out.quat + 4 * p, a.out.quat + 4 * p + 1, a.out.quat + 4 * p + 2, a.out.quat + 4 * p + 3,
+                      a.out.scale + 2 * p, a.out.scale + 2 * p + 1, a.out.curv + 2 * p, a.out.curv + 2 * p + 1,
+                      a.out.opacity + p, a.out.rgb + 3 * p, a.out.rgb + 3 * p + 1, a.out.rgb + 3 * p + 2};
+    if (a.accumulate) {
+        for (int i = 0; i < 15; ++i) *dst[i] += vals[i];
+    } else {
+        for (int i = 0; i < 15; ++i) *dst[i] = vals[i];
+    }
+}
+
+hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t stream)
+{
+    if (a.n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const PreprocessBwdArgs &a, hipStream_t stream)
+{
+    if (a.n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace qgs

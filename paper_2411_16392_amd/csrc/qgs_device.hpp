@@ -1,0 +1,215 @@
+// Device-side pieces shared by the rasterizer kernels: the primitive record,
+// per-pixel ray set-up and the ray-paraboloid hit with root selection.
+//
+// Geometry is evaluated in a centre-relative frame.  With the centre at camera
+// depth Zc and the pixel ray P(z) = z (xn, yn, 1), write z = Zc + s:
+//     P - c_cam = m + s e,   m = Zc (dxp / fx, dyp / fy, 0),   e = (xn, yn, 1),
+// where dxp = u + 0.5 - u_c is the pixel's offset from the projected centre.  The
+// preprocess stores u_c as an integer plus a fraction, so dxp is exact to FP32
+// rounding of a small number, and every term above is of the size of the
+// primitive: FP32 keeps its relative precision where the camera-origin form
+// ohat + t dhat would cancel |ohat| / sigma (10^3 and more) digits away.  In the
+// local frame mhat = Rc^T m, ehat = Rc^T e, and substituting phat = mhat + s ehat
+// into z = lambda1 x^2 + lambda2 y^2 (supplement, ray-splat intersection) gives
+// A s^2 + B s + C = 0 with
+//     A = l1 e0^2 + l2 e1^2,  B = 2 (l1 m0 e0 + l2 m1 e1) - e2,  C = l1 m0^2 + l2 m1^2 - m2.
+// A is the unit-ray A of the paper scaled by |e|^2, so the small-|A| test uses
+// A_eps |e|^2; the paper's tangent-plane root t = -C/B, written in s, is
+// s = -(C - A Zc^2) / (B - 2 A Zc).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qgs_internal.hpp"
+
+namespace qgs {
+
+constexpr int TILE = 16;
+constexpr int BLOCK = 256;
+constexpr int REC_WORDS = 32;
+constexpr int NGRAD = 14;  // per-(tile, primitive) gradient fields
+
+// record word offsets (layout documented in qgs.h)
+enum : int {
+    R_PX0 = 0, R_PX1 = 1, R_PY0 = 2, R_PY1 = 3,
+    R_U = 4, R_HU = 5, R_V = 6, R_HV = 7,
+    R_KX = 8, R_KY = 9, R_ZC = 10, R_L1 = 11,
+    R_L2 = 12, R_K1 = 13, R_K2 = 14, R_OP = 15,
+    R_ROT = 16, R_RGB = 25
+};
+
+// gradient field order within a record gradient (16 floats, 14 used)
+enum : int {
+    G_PHI0 = 0, G_PHI1 = 1, G_PHI2 = 2, G_ZC = 3, G_UC = 4, G_VC = 5,
+    G_L1 = 6, G_L2 = 7, G_K1 = 8, G_K2 = 9, G_OP = 10, G_R = 11, G_G = 12, G_B = 13
+};
+
+struct PixelRay {
+    float fpx, fpy;   // integer pixel coordinates as floats
+    float xn, yn;     // normalised image coordinates of the pixel centre
+    float e2, enorm;  // |e|^2 and |e| for e = (xn, yn, 1)
+};
+
+__device__ inline PixelRay make_ray(int px, int py, const RasterParams &P)
+{
+    PixelRay r;
+    r.fpx = (float)px;
+    r.fpy = (float)py;
+    r.xn = (((float)px + 0.5f) - P.cx) / P.fx;
+    r.yn = (((float)py + 0.5f) - P.cy) / P.fy;
+    r.e2 = __builtin_fmaf(r.xn, r.xn, __builtin_fmaf(r.yn, r.yn, 1.0f));
+    r.enorm = __builtin_sqrtf(r.e2);
+    return r;
+}
+
+// Geometry of one primitive, as loaded from its record.
+struct Prim {
+    float U, hu, V, hv, kx, ky, Zc, l1, l2, k1, k2, op;
+    float R[9];  // camera-from-local rotation, row-major R[3 i + j]
+};
+
+__device__ inline void load_prim(const float *w, Prim &p)
+{
+    const float4 a = *reinterpret_cast<const float4 *>(w + 4);
+    const float4 b = *reinterpret_cast<const float4 *>(w + 8);
+    const float4 c = *reinterpret_cast<const float4 *>(w + 12);
+    const float4 d = *reinterpret_cast<const float4 *>(w + 16);
+    const float4 e = *reinterpret_cast<const float4 *>(w + 20);
+    const float f = w[24];
+    p.U = a.x; p.hu = a.y; p.V = a.z; p.hv = a.w;
+    p.kx = b.x; p.ky = b.y; p.Zc = b.z; p.l1 = b.w;
+    p.l2 = c.x; p.k1 = c.y; p.k2 = c.z; p.op = c.w;
+    p.R[0] = d.x; p.R[1] = d.y; p.R[2] = d.z; p.R[3] = d.w;
+    p.R[4] = e.x; p.R[5] = e.y; p.R[6] = e.z; p.R[7] = e.w;
+    p.R[8] = f;
+}
+
+// arc-length factor g(u) = l / rho for u = 2 |a| rho (geodesic equation, Sec.
+// 3.2) and its derivative.  Below u = 0.35 the binomial series of the
+// integrand, sum_k C(1/2, k) u^2k / (2k + 1); above, the closed form.
+__device__ inline float gfun(float u)
+{
+    if (u < 0.35f) {
+        const float v = u * u;
+        float acc = -21.0f / 13312.0f;
+        acc = __builtin_fmaf(acc, v, 7.0f / 2816.0f);
+        acc = __builtin_fmaf(acc, v, -5.0f / 1152.0f);
+        acc = __builtin_fmaf(acc, v, 1.0f / 112.0f);
+        acc = __builtin_fmaf(acc, v, -1.0f / 40.0f);
+        acc = __builtin_fmaf(acc, v, 1.0f / 6.0f);
+        return __builtin_fmaf(acc, v, 1.0f);
+    }
+    const float s = __builtin_sqrtf(__builtin_fmaf(u, u, 1.0f));
+    const float ash = __logf(u + s);
+    return (ash + u * s) * __builtin_amdgcn_rcpf(2.0f * u);
+}
+
+__device__ inline float gprime(float u)
+{
+    if (u < 0.35f) {
+        const float v = u * u;
+        float acc = -252.0f / 13312.0f;  // 2k c_k, k = 6 .. 1
+        acc = __builtin_fmaf(acc, v, 70.0f / 2816.0f);
+        acc = __builtin_fmaf(acc, v, -40.0f / 1152.0f);
+        acc = __builtin_fmaf(acc, v, 6.0f / 112.0f);
+        acc = __builtin_fmaf(acc, v, -4.0f / 40.0f);
+        acc = __builtin_fmaf(acc, v, 2.0f / 6.0f);
+        return acc * u;
+    }
+    const float s = __builtin_sqrtf(__builtin_fmaf(u, u, 1.0f));
+    const float ash = __logf(u + s);
+    return (u * s - ash) * __builtin_amdgcn_rcpf(2.0f * u * u);
+}
+
+// Intersection state of one (pixel, primitive) pair.
+struct Hit {
+    float dxp, dyp, mx, my;
+    float m0, m1, m2, e0, e1, e2;
+    float A, B, C;
+    float s, x, y, Q, rho2, h, u, g, E;
+    bool linear;
+};
+
+// Ray-paraboloid intersection with the near/far selection and the k_sigma
+// geodesic cut-off (Sec. 3.2.1).  Returns true with the accepted hit in H.
+__device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterParams &P, Hit &H)
+{
+    H.dxp = (r.fpx - p.U) + p.hu;
+    H.dyp = (r.fpy - p.V) + p.hv;
+    H.mx = p.kx * H.dxp;
+    H.my = p.ky * H.dyp;
+    H.m0 = __builtin_fmaf(p.R[0], H.mx, p.R[3] * H.my);
+    H.m1 = __builtin_fmaf(p.R[1], H.mx, p.R[4] * H.my);
+    H.m2 = __builtin_fmaf(p.R[2], H.mx, p.R[5] * H.my);
+    H.e0 = __builtin_fmaf(p.R[0], r.xn, __builtin_fmaf(p.R[3], r.yn, p.R[6]));
+    H.e1 = __builtin_fmaf(p.R[1], r.xn, __builtin_fmaf(p.R[4], r.yn, p.R[7]));
+    H.e2 = __builtin_fmaf(p.R[2], r.xn, __builtin_fmaf(p.R[5], r.yn, p.R[8]));
+    const float l1e0 = p.l1 * H.e0, l2e1 = p.l2 * H.e1;
+    H.A = __builtin_fmaf(l1e0, H.e0, l2e1 * H.e1);
+    H.B = 2.0f * __builtin_fmaf(l1e0, H.m0, l2e1 * H.m1) - H.e2;
+    H.C = __builtin_fmaf(p.l1 * H.m0, H.m0, __builtin_fmaf(p.l2 * H.m1, H.m1, -H.m2));
+
+    float cand0, cand1;
+    int nc = 0;
+    if (__builtin_fabsf(H.A) < P.A_eps * r.e2) {
+        H.linear = true;
+        const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
+        if (M != 0.0f) {
+            const float N = __builtin_fmaf(-H.A * p.Zc, p.Zc, H.C);
+            cand0 = -N / M;
+            nc = 1;
+        }
+    } else {
+        H.linear = false;
+        const float D = __builtin_fmaf(H.B, H.B, -4.0f * H.A * H.C);
+        if (D >= 0.0f) {
+            const float sq = __builtin_sqrtf(D);
+            const float q = -0.5f * (H.B + (H.B >= 0.0f ? sq : -sq));
+            float r1, r2;
+            if (q == 0.0f) {
+                r1 = r2 = 0.0f;
+            } else {
+                r1 = q / H.A;
+                r2 = H.C / q;
+            }
+            cand0 = fminf(r1, r2);
+            cand1 = fmaxf(r1, r2);
+            nc = 2;
+        }
+    }
+    for (int k = 0; k < nc; ++k) {
+        const float s = k == 0 ? cand0 : cand1;
+        const float z = p.Zc + s;
+        if (!(z > P.near_plane)) continue;
+        const float x = __builtin_fmaf(s, H.e0, H.m0);
+        const float y = __builtin_fmaf(s, H.e1, H.m1);
+        const float xx = x * x, yy = y * y;
+        const float Q = __builtin_fmaf(p.k1, xx, p.k2 * yy);
+        if (!(Q <= P.k2)) continue;  // g >= 1, so E >= Q
+        const float rho2 = xx + yy;
+        const float h = __builtin_fmaf(p.l1, xx, p.l2 * yy);
+        const float u = rho2 > 0.0f ? 2.0f * __builtin_fabsf(h) * __builtin_amdgcn_rsqf(rho2) : 0.0f;
+        const float g = gfun(u);
+        const float E = g * g * Q;
+        if (E <= P.k2) {
+            H.s = s; H.x = x; H.y = y; H.Q = Q; H.rho2 = rho2; H.h = h; H.u = u; H.g = g; H.E = E;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Unit normal of the paraboloid at the hit, (-2 l1 x, -2 l2 y, 1) normalised,
+// flipped to face the camera (n . ehat <= 0); returns the flip sign.
+__device__ inline float hit_normal(const Prim &p, const Hit &H, float nl[3], float &inv_len)
+{
+    const float v0 = -2.0f * p.l1 * H.x, v1 = -2.0f * p.l2 * H.y;
+    inv_len = __builtin_amdgcn_rsqf(__builtin_fmaf(v0, v0, __builtin_fmaf(v1, v1, 1.0f)));
+    nl[0] = v0 * inv_len;
+    nl[1] = v1 * inv_len;
+    nl[2] = inv_len;
+    const float dot = __builtin_fmaf(v0, H.e0, __builtin_fmaf(v1, H.e1, H.e2));
+    return dot > 0.0f ? -1.0f : 1.0f;
+}
+
+}  // namespace qgs

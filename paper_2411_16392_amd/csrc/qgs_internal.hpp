@@ -1,0 +1,101 @@
+// Internal launch interfaces between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qgs.h"
+
+namespace qgs {
+
+// Rasterizer constants shared by forward and backward (passed by value).
+struct RasterParams {
+    float fx, fy, cx, cy, ifx, ify;
+    int32_t width, height, tiles_x, tiles_y;
+    float near_plane, k2, alpha_min, alpha_max, T_eps, A_eps;
+    float bg[3];
+    uint32_t flags;
+};
+
+struct PreprocessArgs {
+    const float *center, *quat, *scale, *curv, *opacity, *rgb;
+    int64_t n;
+    qgs_camera cam;
+    float near_plane, k_sigma;
+    void *records;
+    uint32_t *depth_key;
+    int32_t *rect;
+    uint32_t *tiles;
+};
+
+struct PreprocessBwdArgs {
+    const float *center, *quat, *scale;
+    int64_t n;
+    qgs_camera cam;
+    const float *grad_rec;  // [n][16]
+    const uint32_t *tiles;
+    qgs_scene_grads out;
+    int accumulate;
+};
+
+hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t stream);
+hipError_t launch_preprocess_bwd(const PreprocessBwdArgs &a, hipStream_t stream);
+
+// ---- bin / sort --------------------------------------------------------------
+
+struct SortWorkspace {
+    uint32_t *dkA, *dvA, *dkB, *dvB;  // depth keys / primitive ids, ping-pong [n]
+    uint64_t *off;                    // [n + 1] pair offsets in depth order
+    uint64_t *part;                   // scan partials
+    uint32_t *hist;                   // [256][nblocks]
+    uint32_t *tileT, *primT;          // pair ping-pong [capacity]
+    size_t bytes;
+};
+
+// Layout of the bin_sort workspace inside `base` (NULL base: sizes only).
+SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity);
+
+struct BinSortArgs {
+    int64_t n;
+    const uint32_t *depth_key, *tiles;
+    const int32_t *rect;
+    uint32_t *pair_offset;
+    int32_t tiles_x, tiles_y;
+    uint32_t *pair_tile, *pair_prim, *ranges, *counters;
+    uint64_t capacity;
+};
+
+// Phase 1: depth sort, offsets, counters.  Phase 2: emission, tile sort, ranges
+// with grids sized for `n_pairs_bound` pairs (the exact count, or the capacity).
+hipError_t bin_sort_phase1(const BinSortArgs &a, const SortWorkspace &ws, hipStream_t stream);
+hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64_t n_pairs_bound,
+                           hipStream_t stream);
+
+// ---- rasterizer --------------------------------------------------------------
+
+struct RasterArgs {
+    const float *records;  // [n][32]
+    const uint32_t *pair_prim, *pair_tile, *ranges, *counters;
+    const uint32_t *pair_offset;
+    const int32_t *rect;
+    int32_t tiles_x, tiles_y;
+};
+
+struct FwdOut {
+    float *color, *depth, *normal, *T_final;
+    uint32_t *last;
+    uint32_t *eval_counter;  // may be null
+};
+
+struct BwdIn {
+    const float *T_final;
+    const uint32_t *last;
+    const float *dcolor, *ddepth, *dnormal;
+};
+
+hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream);
+hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const BwdIn &in, float *grad_rec,
+                             float *pair_scratch, int64_t n_prims, uint64_t capacity, hipStream_t stream);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stream);
+
+}  // namespace qgs

@@ -1,0 +1,480 @@
+// Tile rasterizer, forward and backward.
+//
+// One 256-thread workgroup (four wave64s) per 16 x 16 tile; wave w owns the
+// 8 x 8 quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) in it, so a
+// wave's pixels are a compact square and a primitive whose pixel rectangle
+// misses the square is skipped by the whole wave with one scalar test.  The
+// tile's list is walked in batches of records staged in LDS: 8 consecutive
+// threads copy one 128-byte record with 16-byte loads, so every global load
+// instruction moves whole, aligned 128-byte lines.
+//
+// Forward (Eq. 1, compositing front to back): a wave stops computing once
+// every lane is done (ballot), the workgroup once every wave is.
+// Backward (supplement, back-to-front adjoint): each pixel starts at its last
+// blended entry, recovers T_i = T_{i+1} / (1 - alpha_i), and keeps the suffix
+// sum S_i = sum_{j>i} w_j X_j + T_final bg, so dX/dalpha_i = T_i X_i - S_i /
+// (1 - alpha_i).  Per-primitive gradients are summed over the wave with a
+// butterfly, then over the four waves in LDS, then added to global memory with
+// one atomic per field per (tile, primitive); the deterministic variant keeps
+// per-wave partials, sums them in wave order and stores one partial per pair for
+// a fixed-order second pass.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qgs_device.hpp"
+#include "qgs_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace qgs {
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int nb, float4 *s_rec, uint32_t *s_pid)
+{
+    const int tid = threadIdx.x;
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
+#pragma unroll
+    for (int r = 0; r < BLOCK * 8 / BLOCK; ++r) {
+        const int slot = r * (BLOCK / 8) + (tid >> 3), k = tid & 7;
+        if (slot < nb) {
+            const uint32_t pid = a.pair_prim[list_begin + slot];
+            s_rec[slot * 8 + k] = recs[(size_t)pid * 8 + k];
+            if (s_pid && k == 0) s_pid[slot] = pid;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
+{
+    __shared__ float4 s_rec[BLOCK * 8];
+    const int tile = blockIdx.x;
+    const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < P.width && py < P.height;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const PixelRay ray = make_ray(px, py, P);
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
+    uint32_t last = 0, stop_pos = 0;
+    bool done = !inside;
+
+    for (uint32_t b0 = start; b0 < end; b0 += BLOCK) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int nb = (int)min((uint32_t)BLOCK, end - b0);
+        load_batch(a, b0, nb, s_rec, nullptr);
+        __syncthreads();
+        bool wave_alive = __ballot(!done) != 0ull;
+        for (int j = 0; j < nb && wave_alive; ++j) {
+            const float4 rr = s_rec[j * 8];
+            const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
+            const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
+            if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
+            if (!done && px >= x0 && px <= x1 && py >= y0 && py <= y1) {
+                Prim p;
+                load_prim(reinterpret_cast<const float *>(&s_rec[j * 8]), p);
+                Hit H;
+                if (ray_hit(p, ray, P, H)) {
+                    const float G = __expf(-0.5f * H.E);
+                    const float alpha = fminf(P.alpha_max, p.op * G);
+                    if (alpha >= P.alpha_min) {
+                        const float Tn = T * (1.0f - alpha);
+                        if (Tn < P.T_eps) {
+                            done = true;
+                            stop_pos = b0 - start + (uint32_t)j + 1u;
+                        } else {
+                            const float w = alpha * T;
+                            const float4 cr = s_rec[j * 8 + 6];
+                            c0 = __builtin_fmaf(w, cr.y, c0);
+                            c1 = __builtin_fmaf(w, cr.z, c1);
+                            c2 = __builtin_fmaf(w, cr.w, c2);
+                            dep = __builtin_fmaf(w, (p.Zc + H.s) * ray.enorm, dep);
+                            float nl[3], il;
+                            const float f = hit_normal(p, H, nl, il);
+                            const float wf = w * f;
+                            n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
+                            n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
+                            n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
+                            T = Tn;
+                            last = b0 - start + (uint32_t)j + 1u;
+                        }
+                    }
+                }
+            }
+            wave_alive = __ballot(!done) != 0ull;
+        }
+        __syncthreads();
+    }
+
+    if (inside) {
+        const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
+        o.color[pix] = c0 + T * P.bg[0];
+        o.color[hw + pix] = c1 + T * P.bg[1];
+        o.color[2 * hw + pix] = c2 + T * P.bg[2];
+        o.depth[pix] = dep;
+        o.normal[pix] = n0;
+        o.normal[hw + pix] = n1;
+        o.normal[2 * hw + pix] = n2;
+        o.T_final[pix] = T;
+        o.last[pix] = last;
+    }
+    if (o.eval_counter) {
+        // list entries processed per pixel, up to and including a stop
+        uint32_t ev = inside ? (stop_pos ? stop_pos : end - start) : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off, 64);
+        if (lane == 0 && ev) atomicAdd(o.eval_counter, ev);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+struct PixGrad {
+    float g[NGRAD];
+};
+
+// adjoint of one blended entry; adds into G (the primitive's record gradient)
+__device__ inline void entry_grad(const Prim &p, const float rgb[3], const PixelRay &ray, const RasterParams &P,
+                                  const Hit &H, float G, float dalpha, float w, const float gc[3], float gd,
+                                  const float gn[3], float *gr)
+{
+    // colour and depth outputs
+    gr[G_R] += gc[0] * w;
+    gr[G_G] += gc[1] * w;
+    gr[G_B] += gc[2] * w;
+    float dz = gd * w * ray.enorm;  // t = (Zc + s) |e|
+    float dx = 0.0f, dy = 0.0f;
+    float dphi0 = 0.0f, dphi1 = 0.0f, dphi2 = 0.0f;
+    // normal output: n_cam = f Rc nl, nl = v / |v|, v = (-2 l1 x, -2 l2 y, 1)
+    {
+        float nl[3], il;
+        const float f = hit_normal(p, H, nl, il);
+        const float g0 = gn[0] * w, g1 = gn[1] * w, g2 = gn[2] * w;
+        // Rc^T g
+        const float q0 = __builtin_fmaf(p.R[0], g0, __builtin_fmaf(p.R[3], g1, p.R[6] * g2));
+        const float q1 = __builtin_fmaf(p.R[1], g0, __builtin_fmaf(p.R[4], g1, p.R[7] * g2));
+        const float q2 = __builtin_fmaf(p.R[2], g0, __builtin_fmaf(p.R[5], g1, p.R[8] * g2));
+        // rotation: dphi += n_f x (Rc^T g), n_f = f nl
+        const float nf0 = f * nl[0], nf1 = f * nl[1], nf2 = f * nl[2];
+        dphi0 += nf1 * q2 - nf2 * q1;
+        dphi1 += nf2 * q0 - nf0 * q2;
+        dphi2 += nf0 * q1 - nf1 * q0;
+        // through the normalisation
+        const float d0 = f * q0, d1 = f * q1, d2 = f * q2;
+        const float dot = nl[0] * d0 + nl[1] * d1 + nl[2] * d2;
+        const float dv0 = (d0 - nl[0] * dot) * il, dv1 = (d1 - nl[1] * dot) * il;
+        gr[G_L1] += -2.0f * H.x * dv0;
+        gr[G_L2] += -2.0f * H.y * dv1;
+        dx += -2.0f * p.l1 * dv0;
+        dy += -2.0f * p.l2 * dv1;
+    }
+    // alpha = min(alpha_max, op G), G = exp(-E / 2), E = g(u)^2 Q
+    float dG = 0.0f;
+    if (p.op * G < P.alpha_max) {
+        gr[G_OP] += dalpha * G;
+        dG = dalpha * p.op;
+    }
+    const float dE = -0.5f * G * dG;
+    const float dQ = H.g * H.g * dE;
+    const float du = 2.0f * H.g * gprime(H.u) * H.Q * dE;
+    const float xx = H.x * H.x, yy = H.y * H.y;
+    dx += 2.0f * p.k1 * H.x * dQ;
+    dy += 2.0f * p.k2 * H.y * dQ;
+    gr[G_K1] += xx * dQ;
+    gr[G_K2] += yy * dQ;
+    // u = 2 |h| / rho, h = l1 x^2 + l2 y^2
+    if (H.rho2 > 0.0f && du != 0.0f) {
+        const float irho = __builtin_amdgcn_rsqf(H.rho2);
+        const float sg = H.h > 0.0f ? 1.0f : (H.h < 0.0f ? -1.0f : 0.0f);
+        const float dh = du * 2.0f * sg * irho;
+        const float drho = -du * 2.0f * __builtin_fabsf(H.h) * irho * irho;
+        gr[G_L1] += xx * dh;
+        gr[G_L2] += yy * dh;
+        dx += (2.0f * p.l1 * dh + drho * irho) * H.x;
+        dy += (2.0f * p.l2 * dh + drho * irho) * H.y;
+    }
+    // x = m0 + s e0, y = m1 + s e1, z = Zc + s
+    float dm0 = dx, dm1 = dy, dm2 = 0.0f;
+    float de0 = H.s * dx, de1 = H.s * dy, de2 = 0.0f;
+    float ds = __builtin_fmaf(H.e0, dx, __builtin_fmaf(H.e1, dy, dz));
+    float dZc = dz;
+    float dA, dB, dC;
+    if (H.linear) {
+        // s = -(C - A Zc^2) / (B - 2 A Zc)
+        const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
+        const float iM = 1.0f / M;
+        const float dN = -ds * iM;
+        const float dM = -H.s * iM * ds;
+        dC = dN;
+        dA = -p.Zc * p.Zc * dN - 2.0f * p.Zc * dM;
+        dB = dM;
+        dZc += -2.0f * H.A * p.Zc * dN - 2.0f * H.A * dM;
+    } else {
+        const float iF = 1.0f / __builtin_fmaf(2.0f * H.A, H.s, H.B);
+        dA = -H.s * H.s * iF * ds;
+        dB = -H.s * iF * ds;
+        dC = -iF * ds;
+    }
+    // A = l1 e0^2 + l2 e1^2
+    gr[G_L1] += H.e0 * H.e0 * dA;
+    gr[G_L2] += H.e1 * H.e1 * dA;
+    de0 += 2.0f * p.l1 * H.e0 * dA;
+    de1 += 2.0f * p.l2 * H.e1 * dA;
+    // B = 2 (l1 m0 e0 + l2 m1 e1) - e2
+    gr[G_L1] += 2.0f * H.m0 * H.e0 * dB;
+    gr[G_L2] += 2.0f * H.m1 * H.e1 * dB;
+    dm0 += 2.0f * p.l1 * H.e0 * dB;
+    dm1 += 2.0f * p.l2 * H.e1 * dB;
+    de0 += 2.0f * p.l1 * H.m0 * dB;
+    de1 += 2.0f * p.l2 * H.m1 * dB;
+    de2 -= dB;
+    // C = l1 m0^2 + l2 m1^2 - m2
+    gr[G_L1] += H.m0 * H.m0 * dC;
+    gr[G_L2] += H.m1 * H.m1 * dC;
+    dm0 += 2.0f * p.l1 * H.m0 * dC;
+    dm1 += 2.0f * p.l2 * H.m1 * dC;
+    dm2 -= dC;
+    // mhat = Rc^T m, ehat = Rc^T e: dphi += dm x m + de x e
+    dphi0 += dm1 * H.m2 - dm2 * H.m1 + de1 * H.e2 - de2 * H.e1;
+    dphi1 += dm2 * H.m0 - dm0 * H.m2 + de2 * H.e0 - de0 * H.e2;
+    dphi2 += dm0 * H.m1 - dm1 * H.m0 + de0 * H.e1 - de1 * H.e0;
+    // m = (kx dxp, ky dyp, 0), kx = Zc / fx, dxp = u + 0.5 - u_c
+    const float dmx = __builtin_fmaf(p.R[0], dm0, __builtin_fmaf(p.R[1], dm1, p.R[2] * dm2));
+    const float dmy = __builtin_fmaf(p.R[3], dm0, __builtin_fmaf(p.R[4], dm1, p.R[5] * dm2));
+    dZc += dmx * H.dxp * P.ifx + dmy * H.dyp * P.ify;
+    gr[G_UC] += -dmx * p.kx;
+    gr[G_VC] += -dmy * p.ky;
+    gr[G_ZC] += dZc;
+    gr[G_PHI0] += dphi0;
+    gr[G_PHI1] += dphi1;
+    gr[G_PHI2] += dphi2;
+}
+
+template <bool DET>
+__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in, float *grad_rec,
+                                                      float *pair_scratch)
+{
+    constexpr int NB = DET ? 64 : BLOCK;
+    constexpr int NACC = DET ? 4 : 1;
+    __shared__ float4 s_rec[NB * 8];
+    __shared__ uint32_t s_pid[NB];
+    __shared__ float s_acc[NACC][NB][NGRAD];
+    __shared__ uint32_t s_maxlast;
+
+    const int tile = blockIdx.x;
+    const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < P.width && py < P.height;
+    const uint32_t start = a.ranges[2 * tile], list_len = a.ranges[2 * tile + 1] - start;
+    const PixelRay ray = make_ray(px, py, P);
+
+    const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
+    float T = 1.0f, gc[3] = {0, 0, 0}, gd = 0.0f, gn[3] = {0, 0, 0};
+    uint32_t last = 0;
+    if (inside) {
+        T = in.T_final[pix];
+        last = in.last[pix];
+        if (in.dcolor) {
+            gc[0] = in.dcolor[pix];
+            gc[1] = in.dcolor[hw + pix];
+            gc[2] = in.dcolor[2 * hw + pix];
+        }
+        if (in.ddepth) gd = in.ddepth[pix];
+        if (in.dnormal) {
+            gn[0] = in.dnormal[pix];
+            gn[1] = in.dnormal[hw + pix];
+            gn[2] = in.dnormal[2 * hw + pix];
+        }
+    }
+    // suffix sums S (colour starts with the background term)
+    float S[7] = {T * P.bg[0], T * P.bg[1], T * P.bg[2], 0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t wmax = wave_max_u32(last);
+    if (tid == 0) s_maxlast = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_maxlast, wmax);
+    __syncthreads();
+    // never walk past the tile's list, whatever `last` holds
+    const uint32_t nmax = s_maxlast < list_len ? s_maxlast : list_len;
+
+    for (int32_t hi = (int32_t)nmax; hi > 0; hi -= NB) {
+        const int32_t lo = hi - NB > 0 ? hi - NB : 0;
+        const int nb = hi - lo;
+        // stage records and clear accumulators
+#pragma unroll
+        for (int r = 0; r < (NB * 8 + BLOCK - 1) / BLOCK; ++r) {
+            const int slot = r * (BLOCK / 8) + (tid >> 3), k = tid & 7;
+            if (slot < nb) {
+                const uint32_t pid = a.pair_prim[start + lo + slot];
+                s_rec[slot * 8 + k] = reinterpret_cast<const float4 *>(a.records)[(size_t)pid * 8 + k];
+                if (k == 0) s_pid[slot] = pid;
+            }
+        }
+        for (int i = tid; i < NACC * NB * NGRAD; i += BLOCK) (&s_acc[0][0][0])[i] = 0.0f;
+        __syncthreads();
+
+        for (int j = nb - 1; j >= 0; --j) {
+            const uint32_t pos = (uint32_t)(lo + j);
+            if (pos >= wmax) continue;
+            const float4 rr = s_rec[j * 8];
+            const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
+            const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
+            if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
+            float gr[NGRAD];
+#pragma unroll
+            for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
+            bool contrib = false;
+            if (pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1) {
+                Prim p;
+                load_prim(reinterpret_cast<const float *>(&s_rec[j * 8]), p);
+                Hit H;
+                if (ray_hit(p, ray, P, H)) {
+                    const float G = __expf(-0.5f * H.E);
+                    const float alpha = fminf(P.alpha_max, p.op * G);
+                    if (alpha >= P.alpha_min) {
+                        contrib = true;
+                        const float4 cr = s_rec[j * 8 + 6];
+                        const float rgb[3] = {cr.y, cr.z, cr.w};
+                        const float om = 1.0f - alpha;
+                        const float iom = 1.0f / om;
+                        const float Ti = T * iom;
+                        const float w = alpha * Ti;
+                        float X[7];
+                        X[0] = rgb[0];
+                        X[1] = rgb[1];
+                        X[2] = rgb[2];
+                        X[3] = (p.Zc + H.s) * ray.enorm;
+                        float nl[3], il;
+                        const float f = hit_normal(p, H, nl, il);
+                        X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
+                        X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
+                        X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
+                        const float g7[7] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+                        float dalpha = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) dalpha += g7[c] * (Ti * X[c] - S[c] * iom);
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
+                        T = Ti;
+                        entry_grad(p, rgb, ray, P, H, G, dalpha, w, gc, gd, gn, gr);
+                    }
+                }
+            }
+            if (__ballot(contrib) != 0ull) {
+#pragma unroll
+                for (int f = 0; f < NGRAD; ++f) gr[f] = wave_sum(gr[f]);
+                if (lane == 0) {
+                    if (DET) {
+#pragma unroll
+                        for (int f = 0; f < NGRAD; ++f) s_acc[DET ? wave : 0][j][f] = gr[f];
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < NGRAD; ++f)
+                            if (gr[f] != 0.0f) atomicAdd(&s_acc[0][j][f], gr[f]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // one global update per field per (tile, primitive)
+        for (int slot = tid; slot < nb; slot += BLOCK) {
+            const uint32_t pid = s_pid[slot];
+            if (DET) {
+                const int32_t *rc = a.rect + 4 * (size_t)pid;
+                const uint32_t local = (uint32_t)(ty - rc[1]) * (uint32_t)(rc[2] - rc[0] + 1) + (uint32_t)(tx - rc[0]);
+                float *dst = pair_scratch + ((size_t)a.pair_offset[pid] + local) * 16;
+#pragma unroll
+                for (int f = 0; f < NGRAD; ++f) {
+                    float v = s_acc[0][slot][f];
+                    for (int w = 1; w < NACC; ++w) v += s_acc[w][slot][f];
+                    dst[f] = v;
+                }
+            } else {
+                float *dst = grad_rec + (size_t)pid * 16;
+#pragma unroll
+                for (int f = 0; f < NGRAD; ++f) {
+                    const float v = s_acc[0][slot][f];
+                    if (v != 0.0f) unsafeAtomicAdd(dst + f, v);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// deterministic second pass: sum each primitive's per-pair partials in
+// emission order
+__global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, const uint32_t *pair_offset,
+                                                    const int32_t *rect, int64_t n, float *grad_rec)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t *rc = rect + 4 * p;
+    float acc[NGRAD];
+#pragma unroll
+    for (int f = 0; f < NGRAD; ++f) acc[f] = 0.0f;
+    if (rc[2] >= rc[0] && rc[3] >= rc[1]) {
+        const uint32_t cnt = (uint32_t)((rc[2] - rc[0] + 1) * (rc[3] - rc[1] + 1));
+        const float *src = pair_scratch + (size_t)pair_offset[p] * 16;
+        for (uint32_t k = 0; k < cnt; ++k) {
+#pragma unroll
+            for (int f = 0; f < NGRAD; ++f) acc[f] += src[(size_t)k * 16 + f];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NGRAD; ++f) grad_rec[16 * p + f] = acc[f];
+    grad_rec[16 * p + 14] = 0.0f;
+    grad_rec[16 * p + 15] = 0.0f;
+}
+
+hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream)
+{
+    const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render_fwd, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const BwdIn &in, float *grad_rec,
+                             float *pair_scratch, int64_t n_prims, uint64_t capacity, hipStream_t stream)
+{
+    const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grad_rec), 0u, (uint64_t)n_prims * 16, stream);
+    if (e != hipSuccess) return e;
+    if (ntiles == 0) return hipSuccess;
+    if (pair_scratch) {
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 16, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
+        if (n_prims > 0)
+            hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
+                               (const float *)pair_scratch, a.pair_offset, a.rect, n_prims, grad_rec);
+    } else {
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qgs

@@ -1,0 +1,246 @@
+"""Torch-facing wrapper of libqgs: device buffers, streams and autograd.
+
+PyTorch provides memory and the current HIP stream; every step of the
+rendering runs in the HIP kernels behind the C ABI (see include/qgs.h).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+SCENE_KEYS = ("center", "quat", "scale", "curv", "opacity", "rgb")
+SCENE_SHAPES = {"center": 3, "quat": 4, "scale": 2, "curv": 2, "opacity": 0, "rgb": 3}
+
+
+def make_camera(cam) -> L.QgsCamera:
+    """QgsCamera from an object with R (3x3), t (3), fx, fy, cx, cy, width, height."""
+    c = L.QgsCamera()
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    t = np.asarray(cam.t, np.float32).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def make_opts(**kw) -> L.QgsRenderOpts:
+    o = L.qgs_default_opts()
+    for k, v in kw.items():
+        if k == "bg":
+            for i in range(3):
+                o.bg[i] = float(v[i])
+        elif k == "flags":
+            o.flags = int(v)
+        else:
+            setattr(o, k, float(v))
+    return o
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def scene_to_device(scene, device="cuda") -> dict:
+    """Dict of contiguous FP32 device tensors from a scenes.Scene."""
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k), np.float32)).to(device) for k in SCENE_KEYS}
+
+
+def _scene_struct(t: dict) -> L.QgsScene:
+    s = L.QgsScene()
+    for k in SCENE_KEYS:
+        x = t[k]
+        if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError(f"scene tensor {k} must be contiguous float32 on the GPU")
+        setattr(s, k, x.data_ptr())
+    s.n = int(t["center"].shape[0])
+    return s
+
+
+@dataclass
+class FrameState:
+    """Device buffers of one rendered view, kept for the backward pass."""
+    n: int
+    cam: L.QgsCamera
+    records: torch.Tensor
+    depth_key: torch.Tensor
+    rect: torch.Tensor
+    tiles: torch.Tensor
+    pair_offset: torch.Tensor
+    pair_tile: torch.Tensor
+    pair_prim: torch.Tensor
+    ranges: torch.Tensor
+    counters: torch.Tensor
+    capacity: int
+    num_pairs: int | None
+    color: torch.Tensor
+    depth: torch.Tensor
+    normal: torch.Tensor
+    T_final: torch.Tensor
+    last: torch.Tensor
+
+    def prim_buf(self) -> L.QgsPrimBuf:
+        p = L.QgsPrimBuf()
+        p.records, p.depth_key, p.rect = _ptr(self.records), _ptr(self.depth_key), _ptr(self.rect)
+        p.tiles, p.pair_offset, p.n = _ptr(self.tiles), _ptr(self.pair_offset), self.n
+        return p
+
+    def lists(self) -> L.QgsTileLists:
+        l = L.QgsTileLists()
+        l.pair_tile, l.pair_prim = _ptr(self.pair_tile), _ptr(self.pair_prim)
+        l.ranges, l.counters, l.capacity = _ptr(self.ranges), _ptr(self.counters), self.capacity
+        return l
+
+    def images(self) -> L.QgsImages:
+        im = L.QgsImages()
+        im.color, im.depth, im.normal = _ptr(self.color), _ptr(self.depth), _ptr(self.normal)
+        im.T_final, im.last = _ptr(self.T_final), _ptr(self.last)
+        return im
+
+
+class Renderer:
+    """Renders views of a scene through libqgs.
+
+    capacity: pair-list capacity to start from; grown on demand (exact mode) or
+    fixed (exact=False, no host synchronisation; overflow is then reported in
+    counters[1]).
+    """
+
+    def __init__(self, device="cuda", opts: L.QgsRenderOpts | None = None, capacity: int = 1 << 20,
+                 growth: float = 1.25):
+        self.device = torch.device(device)
+        self.opts = opts if opts is not None else make_opts()
+        self.capacity = int(capacity)
+        self.growth = growth
+        self._sort_ws = None
+        self._bwd_ws = None
+
+    def _workspace(self, attr, nbytes):
+        buf = getattr(self, attr)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            setattr(self, attr, buf)
+        return buf
+
+    def _alloc_lists(self, st: FrameState, cap: int):
+        st.capacity = int(cap)
+        st.pair_tile = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        st.pair_prim = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+
+    def preprocess(self, scene_t: dict, cam) -> FrameState:
+        n = int(scene_t["center"].shape[0])
+        c = cam if isinstance(cam, L.QgsCamera) else make_camera(cam)
+        dev = self.device
+        H, W = c.height, c.width
+        ntiles = ((W + 15) // 16) * ((H + 15) // 16)
+        st = FrameState(
+            n=n, cam=c,
+            records=torch.empty(max(n, 1) * 32, dtype=torch.float32, device=dev),
+            depth_key=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            rect=torch.empty(max(n, 1) * 4, dtype=torch.int32, device=dev),
+            tiles=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            pair_offset=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            pair_tile=None, pair_prim=None,
+            ranges=torch.empty(2 * ntiles, dtype=torch.int32, device=dev),
+            counters=torch.zeros(4, dtype=torch.int32, device=dev),
+            capacity=0, num_pairs=None,
+            color=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+            depth=torch.empty((H, W), dtype=torch.float32, device=dev),
+            normal=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+            T_final=torch.empty((H, W), dtype=torch.float32, device=dev),
+            last=torch.empty((H, W), dtype=torch.int32, device=dev),
+        )
+        L.qgs_preprocess(_scene_struct(scene_t), c, self.opts, st.prim_buf(), _stream())
+        return st
+
+    def bin_sort(self, st: FrameState, exact: bool = True):
+        self._alloc_lists(st, self.capacity)
+        while True:
+            sort_bytes, _ = L.qgs_workspace_query(st.n, st.cam, st.capacity, self.opts.flags)
+            ws = self._workspace("_sort_ws", sort_bytes)
+            status, cnt = L.qgs_bin_sort(st.prim_buf(), st.cam, self.opts, st.lists(), ws.data_ptr(), ws.numel(),
+                                         want_count=exact, stream=_stream(), raise_on_capacity=False)
+            st.num_pairs = cnt
+            if status == L.QGS_ERR_CAPACITY:
+                self.capacity = max(int(cnt * self.growth) + 1024, self.capacity)
+                self._alloc_lists(st, self.capacity)
+                continue
+            return st
+
+    def render_fwd(self, st: FrameState):
+        L.qgs_render_fwd(st.prim_buf(), st.lists(), st.cam, self.opts, st.images(), _stream())
+        return st
+
+    def forward(self, scene_t: dict, cam, exact: bool = True) -> FrameState:
+        st = self.preprocess(scene_t, cam)
+        self.bin_sort(st, exact=exact)
+        return self.render_fwd(st)
+
+    def backward(self, scene_t: dict, st: FrameState, dcolor=None, ddepth=None, dnormal=None,
+                 out: dict | None = None, accumulate: bool = False) -> dict:
+        if out is None:
+            out = {k: torch.empty_like(scene_t[k]) for k in SCENE_KEYS}
+        g = L.QgsSceneGrads()
+        for k in SCENE_KEYS:
+            setattr(g, k, out[k].data_ptr())
+        dl = L.QgsImageGrads()
+        keep = []
+        for name, t in (("dcolor", dcolor), ("ddepth", ddepth), ("dnormal", dnormal)):
+            if t is not None:
+                t = t.contiguous().float()
+                keep.append(t)
+                setattr(dl, name, t.data_ptr())
+        opts = L.QgsRenderOpts.from_buffer_copy(self.opts)
+        if accumulate:
+            opts.flags |= L.QGS_ACCUMULATE_GRADS
+        _, bwd_bytes = L.qgs_workspace_query(st.n, st.cam, st.capacity, opts.flags)
+        ws = self._workspace("_bwd_ws", bwd_bytes)
+        L.qgs_render_bwd(_scene_struct(scene_t), st.prim_buf(), st.lists(), st.cam, opts, st.images(), dl, g,
+                         ws.data_ptr(), ws.numel(), _stream())
+        return out
+
+
+class QGSRasterize(torch.autograd.Function):
+    """colour, depth, normal = QGSRasterize.apply(center, quat, scale, curv,
+    opacity, rgb, renderer, camera)."""
+
+    @staticmethod
+    def forward(ctx, center, quat, scale, curv, opacity, rgb, renderer: Renderer, cam):
+        scene_t = dict(center=center.contiguous(), quat=quat.contiguous(), scale=scale.contiguous(),
+                       curv=curv.contiguous(), opacity=opacity.contiguous(), rgb=rgb.contiguous())
+        st = renderer.forward(scene_t, cam)
+        ctx.renderer = renderer
+        ctx.state = st
+        ctx.save_for_backward(*[scene_t[k] for k in SCENE_KEYS])
+        return st.color, st.depth, st.normal
+
+    @staticmethod
+    def backward(ctx, dcolor, ddepth, dnormal):
+        scene_t = dict(zip(SCENE_KEYS, ctx.saved_tensors))
+        g = ctx.renderer.backward(scene_t, ctx.state, dcolor, ddepth, dnormal)
+        return (g["center"], g["quat"], g["scale"], g["curv"], g["opacity"], g["rgb"], None, None)
+
+
+def render(scene_t: dict, cam, renderer: Renderer | None = None):
+    """Differentiable render of one view: (colour [3,H,W], depth [H,W], normal [3,H,W])."""
+    r = renderer if renderer is not None else Renderer(device=scene_t["center"].device)
+    return QGSRasterize.apply(scene_t["center"], scene_t["quat"], scene_t["scale"], scene_t["curv"],
+                              scene_t["opacity"], scene_t["rgb"], r, cam)
+
+
+def signed_scale_to_params(s1, s2, s3):
+    """The paper's signed scales (s1, s2, s3) -> (sigma, lambda) of this API:
+    sigma_i = |s_i|, lambda_i = sign(s_i) s3 / s_i^2 (Sec. 3.2, curvature paragraph)."""
+    sigma = torch.stack([s1.abs(), s2.abs()], -1)
+    lam = torch.stack([torch.sign(s1) * s3 / (s1 * s1), torch.sign(s2) * s3 / (s2 * s2)], -1)
+    return sigma, lam

@@ -1,0 +1,73 @@
+"""CPU checks of the boundary: the library loads and exports every entry point
+the header declares; host-only calls behave as documented."""
+import re
+import os
+
+import pytest
+
+from paper_2411_16392_amd import _lib as L
+from paper_2411_16392_amd import render as R
+from paper_2411_16392_amd import scenes
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qgs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qgs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("qgs_preprocess", "qgs_bin_sort", "qgs_render_fwd", "qgs_render_bwd"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(L.exported_symbols())
+
+
+def test_status_strings_and_defaults():
+    lib = L.lib()
+    assert lib.qgs_status_string(L.QGS_ERR_CAPACITY) == b"tile list capacity exceeded"
+    assert lib.qgs_status_string(12345) == b"unknown status"
+    o = L.qgs_default_opts()
+    assert o.tile == 16 and abs(o.near_plane - 0.2) < 1e-7 and abs(o.k_sigma - 3) < 1e-7
+    assert abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7
+    assert abs(o.T_eps - 1e-4) < 1e-10 and abs(o.A_eps - 1e-6) < 1e-12
+
+
+def test_workspace_query_host_only():
+    cam = R.make_camera(scenes.look_at((0, 0, -3), width=1600, height=1200, f=1600))
+    s0, b0 = L.qgs_workspace_query(500_000, cam, 10_000_000, 0)
+    s1, b1 = L.qgs_workspace_query(500_000, cam, 20_000_000, L.QGS_DETERMINISTIC_BWD)
+    assert s1 > s0 and b1 >= b0 + 20_000_000 * 64
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_workspace_query(-1, cam, 10, 0)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    bad = R.make_camera(scenes.look_at((0, 0, -3), width=16, height=16, f=16))
+    bad.width = 0
+    with pytest.raises(L.QgsError):
+        L.qgs_workspace_query(10, bad, 10, 0)
+
+
+def test_invalid_arguments_rejected_before_launch():
+    # null scene pointers with n > 0: rejected on the host, nothing launched
+    cam = R.make_camera(scenes.look_at((0, 0, -3), width=16, height=16, f=16))
+    sc = L.QgsScene()
+    sc.n = 10
+    pb = L.QgsPrimBuf()
+    pb.n = 10
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_preprocess(sc, cam, L.qgs_default_opts(), pb)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    o = L.qgs_default_opts()
+    o.tile = 32
+    sc.n = 0
+    pb.n = 0
+    with pytest.raises(L.QgsError):
+        L.qgs_preprocess(sc, cam, o, pb)

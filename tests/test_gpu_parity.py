@@ -1,0 +1,361 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Keys, rectangles and sorted lists: bit-exact.  Colour / normal within 1e-4,
+depth within 1e-4 relative to max(1, depth), on pixels whose oracle margin to
+every discrete decision is at least its scale.  Gradients within 1e-3 relative
+(floor 1e-2 of the tensor's largest entry) with the upstream gradient zeroed
+on low-margin pixels for both sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_16392_amd import _lib as L
+from paper_2411_16392_amd import render as R
+from paper_2411_16392_amd import scenes
+from paper_2411_16392_amd.scenes import Scene
+
+from gpu_helpers import (compare_forward, gpu_forward, grad_errors, masked_dL, oracle_margin_full, to_np,
+                         window_of)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+_CFG_CACHE = {}
+
+
+def cfg(i, **kw):
+    key = (i, tuple(sorted(kw.items())))
+    if key not in _CFG_CACHE:
+        _CFG_CACHE[key] = scenes.make_config(i, **kw)
+    return _CFG_CACHE[key]
+
+
+def check_keys(scene, cam, st):
+    ks = oracle.keys(scene, cam)
+    n = scene.n
+    dk = to_np(st.depth_key).view(np.uint32)[:n]
+    assert np.array_equal(dk, ks["depth_bits"]), "depth keys"
+    rect = to_np(st.rect).reshape(-1, 4)[:n]
+    assert np.array_equal(rect, ks["rect_tile"]), "tile rects"
+    tiles = to_np(st.tiles).view(np.uint32)[:n]
+    assert np.array_equal(tiles, ks["tiles"]), "tiles"
+    rec = to_np(st.records).view(np.int32).reshape(-1, 32)[:n]
+    live = ks["rect_px"][:, 2] >= ks["rect_px"][:, 0]
+    px = np.stack([rec[:, 0], rec[:, 2], rec[:, 1], rec[:, 3]], 1)  # x0, y0, x1, y1
+    assert np.array_equal(px[live], ks["rect_px"][live]), "pixel rects"
+    return ks
+
+
+def check_lists(ks, cam, st):
+    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+    npairs = len(prims)
+    assert st.num_pairs is None or st.num_pairs == npairs
+    cnt = to_np(st.counters).view(np.uint32)
+    assert cnt[0] == npairs and cnt[1] == 0
+    assert np.array_equal(to_np(st.pair_prim).view(np.uint32)[:npairs], prims), "sorted primitive ids"
+    assert np.array_equal(to_np(st.pair_tile).view(np.uint32)[:npairs], (keys_ >> np.uint64(32)).astype(np.uint32))
+    assert np.array_equal(to_np(st.ranges).view(np.uint32).reshape(-1, 2), ranges), "tile ranges"
+    return npairs
+
+
+# ---------------------------------------------------------------------------
+# key stage: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ci", [0, 1])
+def test_keys_and_lists_bitexact_small(ci):
+    c = cfg(ci)
+    cam = c.cameras[0]
+    r, st = gpu_forward(c.scene, cam)
+    ks = check_keys(c.scene, cam, st)
+    check_lists(ks, cam, st)
+
+
+def test_keys_and_lists_bitexact_headline_size():
+    # 500K quadrics, 1600 x 1200 (the timed configuration), two ring views
+    c = cfg(2, n_views=64)
+    for v in (0, 21):
+        cam = c.cameras[v]
+        r, st = gpu_forward(c.scene, cam)
+        ks = check_keys(c.scene, cam, st)
+        n = check_lists(ks, cam, st)
+        assert n > 1_000_000
+
+
+def test_keys_and_lists_bitexact_unbounded():
+    # cameras inside the scene: primitives straddling the near plane get full-screen rects
+    c = cfg(3, n_override=300_000, n_views=2)
+    for cam in c.cameras:
+        r, st = gpu_forward(c.scene, cam)
+        ks = check_keys(c.scene, cam, st)
+        check_lists(ks, cam, st)
+
+
+def test_capacity_mode_and_overflow():
+    c = cfg(1)
+    cam = c.cameras[0]
+    # capacity mode with enough room: no host sync, same lists
+    r = R.Renderer(capacity=4_000_000)
+    st = r.forward(R.scene_to_device(c.scene), cam, exact=False)
+    torch.cuda.synchronize()
+    ks = oracle.keys(c.scene, cam)
+    check_lists(ks, cam, st)
+    # too small: status, device flag, empty ranges
+    r2 = R.Renderer(capacity=1000)
+    st2 = r2.preprocess(R.scene_to_device(c.scene), cam)
+    r2._alloc_lists(st2, 1000)
+    sort_b, _ = L.qgs_workspace_query(st2.n, st2.cam, 1000, 0)
+    ws = torch.empty(sort_b, dtype=torch.uint8, device="cuda")
+    status, cnt = L.qgs_bin_sort(st2.prim_buf(), st2.cam, r2.opts, st2.lists(), ws.data_ptr(), ws.numel(),
+                                 want_count=True, stream=R._stream(), raise_on_capacity=False)
+    assert status == L.QGS_ERR_CAPACITY and cnt > 1000
+    status, cnt2 = L.qgs_bin_sort(st2.prim_buf(), st2.cam, r2.opts, st2.lists(), ws.data_ptr(), ws.numel(),
+                                  want_count=False, stream=R._stream(), raise_on_capacity=False)
+    torch.cuda.synchronize()
+    assert status == L.QGS_OK
+    cn = to_np(st2.counters).view(np.uint32)
+    assert cn[0] == cnt and cn[1] == 1
+    assert np.all(to_np(st2.ranges) == 0)
+    # the forward on overflowed lists renders background only
+    r2.render_fwd(st2)
+    torch.cuda.synchronize()
+    assert np.all(to_np(st2.T_final) == 1.0)
+
+
+def test_invalid_arguments_are_rejected():
+    c = cfg(0)
+    cam = R.make_camera(c.cameras[0])
+    opts = R.make_opts()
+    opts.tile = 8
+    sc = R.scene_to_device(c.scene)
+    r = R.Renderer()
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_preprocess(R._scene_struct(sc), cam, opts, r.preprocess(sc, c.cameras[0]).prim_buf())
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    st = r.forward(sc, c.cameras[0])
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_bin_sort(st.prim_buf(), st.cam, r.opts, st.lists(), st.records.data_ptr(), 16)
+    assert e.value.status == L.QGS_ERR_WORKSPACE
+
+
+# ---------------------------------------------------------------------------
+# forward parity
+# ---------------------------------------------------------------------------
+
+def test_forward_parity_config0_full_frame():
+    c = cfg(0)
+    cam = c.cameras[0]
+    _, st = gpu_forward(c.scene, cam)
+    o = oracle.render(c.scene, cam)
+    g = window_of(st, (0, 0, cam.width, cam.height))
+    res = compare_forward(g, o, o["margin"] >= 1.0, "cfg0")
+    assert res["excluded"] < 0.01
+    print("cfg0", res)
+
+
+def test_forward_parity_config1_full_frame():
+    c = cfg(1)
+    cam = c.cameras[0]
+    _, st = gpu_forward(c.scene, cam)
+    o = oracle.render(c.scene, cam)
+    g = window_of(st, (0, 0, cam.width, cam.height))
+    res = compare_forward(g, o, o["margin"] >= 1.0, "cfg1")
+    assert res["excluded"] < 0.01
+    print("cfg1", res)
+
+
+@pytest.mark.parametrize("view", [0, 37])
+def test_forward_parity_headline_crops(view):
+    # 500K quadrics at 1600 x 1200: crops the oracle evaluates pixel by pixel,
+    # placed across tile boundaries
+    c = cfg(2, n_views=64)
+    cam = c.cameras[view]
+    _, st = gpu_forward(c.scene, cam)
+    ks = oracle.keys(c.scene, cam)
+    for win in [(760, 560, 80, 72), (405, 333, 64, 64), (1100, 700, 48, 56), (1536, 1136, 64, 64)]:
+        o = oracle.render(c.scene, cam, window=win, key_stage=ks)
+        res = compare_forward(window_of(st, win), o, o["margin"] >= 1.0, f"cfg2 v{view} {win}")
+        print("cfg2", view, win, res)
+
+
+def test_forward_parity_unbounded_crops():
+    c = cfg(3, n_override=400_000, n_views=2)
+    for cam in c.cameras:
+        _, st = gpu_forward(c.scene, cam)
+        ks = oracle.keys(c.scene, cam)
+        for win in [(cam.width // 2 - 40, cam.height // 2 - 40, 80, 80), (0, 0, 48, 48),
+                    (cam.width - 50, cam.height - 37, 50, 37)]:
+            o = oracle.render(c.scene, cam, window=win, key_stage=ks)
+            res = compare_forward(window_of(st, win), o, o["margin"] >= 1.0, f"cfg3 {win}")
+            print("cfg3", win, res)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def _tiny_scene(n, seed=0):
+    return scenes.scene_uniform_cube(n, seed, scale_range=(0.05, 0.3), curv_lim=3.0)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (17, 5), (33, 47), (130, 70)])
+def test_ragged_image_sizes(wh):
+    sc = _tiny_scene(300, 3)
+    cam = scenes.look_at((0.1, -0.2, -3.0), width=wh[0], height=wh[1], f=max(wh))
+    _, st = gpu_forward(sc, cam)
+    ks = check_keys(sc, cam, st)
+    check_lists(ks, cam, st)
+    o = oracle.render(sc, cam)
+    compare_forward(window_of(st, (0, 0, cam.width, cam.height)), o, o["margin"] >= 1.0, f"ragged {wh}")
+
+
+def test_empty_and_fully_culled_scenes():
+    cam = scenes.look_at((0, 0, -3.0), width=40, height=24, f=40)
+    empty = _tiny_scene(0)
+    _, st = gpu_forward(empty, cam, opts=dict(bg=(0.1, 0.2, 0.3)))
+    col = to_np(st.color)
+    assert np.allclose(col[0], 0.1) and np.allclose(col[1], 0.2) and np.allclose(col[2], 0.3)
+    assert np.all(to_np(st.T_final) == 1.0) and np.all(to_np(st.last) == 0)
+    # every primitive behind the camera or invalid
+    sc = _tiny_scene(50, 4)
+    sc.center[:, 2] = -5.0
+    sc.scale[:5] = -1.0
+    sc.quat[5:10] = 0.0
+    sc.curv[10:12, 0] = np.nan
+    _, st = gpu_forward(sc, cam)
+    assert st.num_pairs == 0
+    assert np.all(to_np(st.T_final) == 1.0)
+    ks = check_keys(sc, cam, st)
+    assert ks["culled"].all()
+
+
+def test_single_primitive_and_deep_stack():
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=32, height=32, f=32)
+    n = 40
+    sc = Scene(center=np.stack([np.zeros(n), np.zeros(n), 1.0 + 0.05 * np.arange(n)], 1).astype(np.float32),
+               quat=np.tile(np.array([[0, 1, 0, 0]], np.float32), (n, 1)),
+               scale=np.full((n, 2), 0.4, np.float32), curv=np.zeros((n, 2), np.float32),
+               opacity=np.full(n, 0.6, np.float32),
+               rgb=np.random.default_rng(1).uniform(0, 1, (n, 3)).astype(np.float32))
+    _, st = gpu_forward(sc, cam)
+    o = oracle.render(sc, cam)
+    compare_forward(window_of(st, (0, 0, 32, 32)), o, o["margin"] >= 1.0, "stack")
+    # the stop rule fired at the centre
+    assert o["n_blend"][16, 16] < n
+    one = sc.subset([3])
+    _, st1 = gpu_forward(one, cam)
+    o1 = oracle.render(one, cam)
+    compare_forward(window_of(st1, (0, 0, 32, 32)), o1, o1["margin"] >= 1.0, "single")
+
+
+def test_forward_is_repeatable_bitwise():
+    c = cfg(1)
+    cam = c.cameras[0]
+    r, st = gpu_forward(c.scene, cam)
+    a = to_np(st.color).copy()
+    for _ in range(3):
+        _, st2 = gpu_forward(c.scene, cam, renderer=r)
+        assert np.array_equal(to_np(st2.color), a)
+
+
+# ---------------------------------------------------------------------------
+# backward parity
+# ---------------------------------------------------------------------------
+
+def _bwd_case(scene, cam, window, seed, flags=0, renderer=None):
+    dL = scenes.upstream_grads(seed, cam.height, cam.width, crop=window)
+    ks = oracle.keys(scene, cam)
+    margin_full, _ = oracle_margin_full(scene, cam, window, ks)
+    dLm = masked_dL(dL, margin_full)
+    o = oracle.render(scene, cam, window=window, dL=dLm, key_stage=ks)
+    r = renderer or R.Renderer(opts=R.make_opts(flags=flags))
+    sc_t = R.scene_to_device(scene)
+    st = r.forward(sc_t, cam)
+    g = r.backward(sc_t, st, *(torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dLm))
+    torch.cuda.synchronize()
+    return {k: to_np(v) for k, v in g.items()}, o["grads"], float((margin_full[window[1]:window[1] + window[3],
+                                                                               window[0]:window[0] + window[2]] < 1).mean())
+
+
+def test_backward_parity_config0():
+    c = cfg(0)
+    cam = c.cameras[0]
+    g, o, excl = _bwd_case(c.scene, cam, (0, 0, 128, 128), 7)
+    worst = grad_errors(g, o)
+    print("bwd cfg0 worst", worst, "excluded", excl)
+
+
+def test_backward_parity_config1_crop():
+    # upstream gradients N(0,1) on the centre 64 x 64 crop, zero elsewhere
+    c = cfg(1)
+    cam = c.cameras[0]
+    g, o, excl = _bwd_case(c.scene, cam, (368, 268, 64, 64), 8)
+    worst = grad_errors(g, o)
+    print("bwd cfg1 worst", worst, "excluded", excl)
+
+
+def test_backward_parity_headline_crop():
+    c = cfg(2, n_views=64)
+    cam = c.cameras[5]
+    g, o, excl = _bwd_case(c.scene, cam, (768, 568, 64, 64), 9)
+    worst = grad_errors(g, o)
+    print("bwd cfg2 worst", worst, "excluded", excl)
+
+
+def test_deterministic_backward():
+    c = cfg(1)
+    cam = c.cameras[0]
+    win = (368, 268, 64, 64)
+    g_det, o, _ = _bwd_case(c.scene, cam, win, 8, flags=L.QGS_DETERMINISTIC_BWD)
+    grad_errors(g_det, o)
+    # bit-identical across runs
+    g_det2, _, _ = _bwd_case(c.scene, cam, win, 8, flags=L.QGS_DETERMINISTIC_BWD)
+    for k in g_det:
+        assert np.array_equal(g_det[k], g_det2[k]), k
+    # atomic mode agrees to rounding
+    g_at, _, _ = _bwd_case(c.scene, cam, win, 8)
+    for k in g_det:
+        scale = np.abs(g_det[k]).max() + 1e-30
+        assert np.max(np.abs(g_at[k] - g_det[k])) <= 1e-5 * scale, k
+
+
+def test_autograd_function_matches_direct_backward():
+    c = cfg(0)
+    cam = c.cameras[0]
+    sc_t = {k: v.clone().requires_grad_(True) for k, v in R.scene_to_device(c.scene).items()}
+    rend = R.Renderer()
+    col, dep, nrm = R.render(sc_t, cam, rend)
+    rng = np.random.default_rng(3)
+    w = [torch.from_numpy(rng.standard_normal(t.shape).astype(np.float32)).cuda() for t in (col, dep, nrm)]
+    loss = (col * w[0]).sum() + (dep * w[1]).sum() + (nrm * w[2]).sum()
+    loss.backward()
+    st = rend.forward({k: v.detach() for k, v in sc_t.items()}, cam)
+    g = rend.backward({k: v.detach() for k, v in sc_t.items()}, st, *w)
+    torch.cuda.synchronize()
+    for k in R.SCENE_KEYS:
+        a, b = to_np(sc_t[k].grad), to_np(g[k])
+        assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * (np.abs(b).max() + 1e-12)), k
+
+
+def test_accumulate_flag_adds():
+    c = cfg(0)
+    cam = c.cameras[0]
+    r = R.Renderer()
+    sc_t = R.scene_to_device(c.scene)
+    st = r.forward(sc_t, cam)
+    dc = torch.ones((3, cam.height, cam.width), device="cuda")
+    g1 = r.backward(sc_t, st, dcolor=dc)
+    g2 = {k: v.clone() for k, v in g1.items()}
+    r.backward(sc_t, st, dcolor=dc, out=g2, accumulate=True)
+    torch.cuda.synchronize()
+    for k in g1:
+        assert torch.allclose(g2[k], 2 * g1[k], rtol=1e-6, atol=1e-7), k
