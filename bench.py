@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the quadric rasterizer's training step on one MI355X.
+
+A step is one pass of the whole hot path over one view: preprocess, tile|depth
+binning and sort, forward rasterization, backward rasterization and the
+preprocess backward, with N(0,1) upstream gradients on colour, depth and
+normal.  Workload: 500,000 quadrics on the noisy union surface of 8 ellipsoids,
+64 ring views at 1600 x 1200 (f = 1600), one view per step, inputs resident in
+HBM.  Prints one JSON line: Mpix/s = steps * W * H / elapsed, plus the
+roofline of the dominant kernel and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd+bwd at 500K quadrics 1600x1200; serving frames/s + p99 ms"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3       # packed FP32 (two lanes per op)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6      # 256 CU x 64 FMA lanes x 2 flops x 2.4 GHz
+
+# Algorithmic FP32 operations per unit of rasterizer work, counted from the
+# method's formulas (each add, multiply, compare-select, square root,
+# reciprocal, exponential or logarithm counts one; see the design notes):
+#   per evaluated (pixel, primitive) pair: ray in the local frame, A, B, C,
+#   discriminant and roots, candidate point, Q, rho, u, g(u), E and the test
+FLOPS_EVAL = 69
+#   extra per blended pair in the forward: G, alpha, transmittance, colour,
+#   depth, normal (normalise, face the camera, rotate) and accumulation
+FLOPS_BLEND_FWD = 38
+#   per blended pair in the backward: T recovery, dX/dalpha over 7 channels,
+#   suffix sums and the chain rule through normal, density, arc length, root,
+#   frame and projection (re-evaluation of the pair counted by FLOPS_EVAL)
+FLOPS_BLEND_BWD = 230
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--views", type=int, default=64)
+    ap.add_argument("--cpu-rows", type=int, default=1200, help="rows of view 0 the CPU oracle renders (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU design is described in DESIGN.md and not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2411_16392_amd import _lib as L
+    from paper_2411_16392_amd import render as R
+    from paper_2411_16392_amd import scenes
+
+    L.lib()  # fails loudly without the HIP library
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    q = args.quiet
+
+    t0 = time.time()
+    cfg = scenes.make_config(2, n_views=args.views)
+    cams = cfg.cameras
+    W, H = cams[0].width, cams[0].height
+    sc_t = R.scene_to_device(cfg.scene, dev)
+    log(f"[bench] scene {cfg.scene.n} quadrics, {len(cams)} views {W}x{H}, generated in {time.time() - t0:.1f}s", q)
+
+    # size the pair capacity once, untimed, from exact counts of the views used
+    steps_total = args.warmup + args.steps
+    used = sorted({i % len(cams) for i in range(steps_total)})
+    probe = R.Renderer(device=dev)
+    max_pairs = 0
+    for v in used:
+        st = probe.preprocess(sc_t, cams[v])
+        probe.bin_sort(st, exact=True)
+        max_pairs = max(max_pairs, st.num_pairs)
+    capacity = int(max_pairs * 1.05) + 4096
+    log(f"[bench] max pairs over used views {max_pairs}, capacity {capacity}", q)
+
+    # evaluation counts (untimed): list entries processed and blended pairs
+    cnt_r = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=L.QGS_COUNT_EVALS))
+    evals_per_view = []
+    for v in used[: min(8, len(used))]:
+        st = cnt_r.forward(sc_t, cams[v], exact=False)
+        torch.cuda.synchronize()
+        evals_per_view.append(int(st.counters.cpu().numpy().view(np.uint32)[2]))
+    evals_mean = float(np.mean(evals_per_view))
+
+    rend = R.Renderer(device=dev, capacity=capacity)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2)
+    dLs = [(torch.randn((3, H, W), generator=gen, device=dev), torch.randn((H, W), generator=gen, device=dev),
+            torch.randn((3, H, W), generator=gen, device=dev)) for _ in range(4)]
+    grads = {k: torch.empty_like(v) for k, v in sc_t.items()}
+    stream = torch.cuda.current_stream()
+
+    stage_names = ("preprocess", "bin_sort", "render_fwd", "render_bwd")
+    n_ev = len(stage_names) + 1
+
+    def step(i, events=None):
+        cam = cams[i % len(cams)]
+        dl = dLs[i % len(dLs)]
+        if events is not None:
+            events[0].record(stream)
+        st = rend.preprocess(sc_t, cam)
+        if events is not None:
+            events[1].record(stream)
+        rend.bin_sort(st, exact=False)
+        if events is not None:
+            events[2].record(stream)
+        rend.render_fwd(st)
+        if events is not None:
+            events[3].record(stream)
+        rend.backward(sc_t, st, dl[0], dl[1], dl[2], out=grads)
+        if events is not None:
+            events[4].record(stream)
+        return st
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, bracketed by device synchronisation
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(args.steps)]
+    states = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        states.append(step(args.warmup + i, evs[i]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    overflow = any(int(s.counters[1].item()) != 0 for s in states)
+    if overflow:
+        print("pair capacity overflowed during the timed steps", file=sys.stderr)
+        sys.exit(3)
+    npairs = [int(s.counters[0].item()) & 0xFFFFFFFF for s in states]
+    del states
+    stage_ms = {}
+    for k, name in enumerate(stage_names):
+        stage_ms[name] = float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(args.steps)]))
+    ms_per_step = elapsed * 1e3 / args.steps
+    mpix = W * H * args.steps / elapsed / 1e6
+    log(f"[bench] {ms_per_step:.3f} ms/step, {mpix:.1f} Mpix/s, stages {stage_ms}", q)
+
+    # roofline of the dominant kernel: algorithmic FP32 operations per launch
+    # from the forward's pair counts, divided by the kernel's event time
+    evald, blended = [], []
+    for v in used[: min(8, len(used))]:
+        st = cnt_r.forward(sc_t, cams[v], exact=False)
+        torch.cuda.synchronize()
+        c = st.counters.cpu().numpy().view(np.uint32)
+        evald.append(int(c[3]))
+        blended.append(int(c[4]))
+    ev = float(np.mean(evald))
+    bl = float(np.mean(blended))
+    kern = {"render_fwd": ev * FLOPS_EVAL + bl * FLOPS_BLEND_FWD,
+            "render_bwd": bl * (FLOPS_EVAL + FLOPS_BLEND_BWD)}
+    dominant = max(stage_ms, key=stage_ms.get)
+    if dominant in kern:
+        achieved = kern[dominant] / (stage_ms[dominant] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": kern[dominant], "pairs_evaluated": ev, "pairs_blended": bl}
+    else:
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": None, "traffic": None}
+
+    result = {
+        "metric": METRIC,
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "500K quadrics on 8 noisy ellipsoids, 1600x1200 ring views (64), fwd+bwd per view, "
+                               "N(0,1) upstream gradients",
+                   "n_prims": cfg.scene.n, "width": W, "height": H, "views": len(cams)},
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "pairs_per_view": int(np.mean(npairs)),
+        "evals_per_view": int(evals_mean),
+        "evals_per_s": evals_mean / (stage_ms["render_fwd"] * 1e-3),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline and args.cpu_rows > 0:
+        import oracle
+        cam = cams[0]
+        rows = min(args.cpu_rows, H)
+        y0 = (H - rows) // 2
+        win = (0, y0, W, rows)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = min(threads, os.cpu_count() or threads)
+        dl = scenes.upstream_grads(0, H, W)
+        t = time.perf_counter()
+        ks = oracle.keys(cfg.scene, cam)
+        oracle.render(cfg.scene, cam, window=win, key_stage=ks, nthreads=threads, dL=dl)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": round(W * rows / dt / 1e6, 5), "unit": "Mpix/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"view 0, rows {y0}-{y0 + rows - 1} ({W}x{rows} px), key stage + "
+                                            f"FP64 forward + backward, {dt:.1f}s"}
+        log(f"[bench] cpu oracle {result['cpu_baseline']}", q)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

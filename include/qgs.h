@@ -89,7 +89,7 @@ typedef struct qgs_render_opts {
 
 #define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */
 #define QGS_ACCUMULATE_GRADS  2u /* backward: add into qgs_scene_grads instead of overwriting */
-#define QGS_COUNT_EVALS       4u /* forward: count evaluated list entries into counters[2] */
+#define QGS_COUNT_EVALS       4u /* forward: work counters into counters[2..4] */
 
 /*
  * Per-primitive preprocess output (device memory, caller-allocated, n entries).
@@ -120,10 +120,14 @@ typedef struct qgs_prim_buf {
  *  pair_tile, pair_prim  [capacity] tile id and primitive index of each pair,
  *                        sorted by (tile, depth key, primitive index)
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
- *  counters              [4] uint32: [0] number of pairs, [1] overflow flag
+ *  counters              [8] uint32: [0] number of pairs, [1] overflow flag
  *                        (1 when [0] > capacity: lists and ranges are then empty
- *                        and the caller must grow and call again), [2] evaluated
- *                        entries (QGS_COUNT_EVALS), [3] reserved
+ *                        and the caller must grow and call again); with
+ *                        QGS_COUNT_EVALS the forward adds [2] list entries
+ *                        processed per pixel up to and including a stop, summed
+ *                        over pixels, [3] (pixel, primitive) pairs whose
+ *                        intersection was evaluated, [4] pairs blended; [5..7]
+ *                        reserved.  qgs_bin_sort resets [2..7] to zero.
  */
 typedef struct qgs_tile_lists {
     uint32_t *pair_tile;

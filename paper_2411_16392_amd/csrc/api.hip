@@ -231,7 +231,7 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     o.normal = out->normal;
     o.T_final = out->T_final;
     o.last = out->last;
-    o.eval_counter = (opts->flags & QGS_COUNT_EVALS) ? lists->counters + 2 : nullptr;
+    o.counters = (opts->flags & QGS_COUNT_EVALS) ? lists->counters : nullptr;
     return hip_status(launch_render_fwd(raster_args(prims, lists, cam), raster_params(cam, opts), o,
                                         (hipStream_t)stream));
 }

@@ -277,8 +277,7 @@ __global__ void k_set_counters(const uint64_t *total, uint64_t capacity, uint32_
         const uint64_t t = *total;
         counters[0] = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
         counters[1] = t > capacity ? 1u : 0u;
-        counters[2] = 0u;
-        counters[3] = 0u;
+        for (int i = 2; i < 8; ++i) counters[i] = 0u;
     }
 }
 

@@ -83,7 +83,7 @@ struct RasterArgs {
 struct FwdOut {
     float *color, *depth, *normal, *T_final;
     uint32_t *last;
-    uint32_t *eval_counter;  // may be null
+    uint32_t *counters;  // counters[2..4] of the tile lists, or null
 };
 
 struct BwdIn {

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     const PixelRay ray = make_ray(px, py, P);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
-    uint32_t last = 0, stop_pos = 0;
+    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
     bool done = !inside;
 
     for (uint32_t b0 = start; b0 < end; b0 += BLOCK) {
@@ -94,6 +94,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                 Prim p;
                 load_prim(reinterpret_cast<const float *>(&s_rec[j * 8]), p);
                 Hit H;
+                ++n_eval;
                 if (ray_hit(p, ray, P, H)) {
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                             n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
                             T = Tn;
                             last = b0 - start + (uint32_t)j + 1u;
+                            ++n_blend;
                         }
                     }
                 }
@@ -138,12 +140,17 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         o.T_final[pix] = T;
         o.last[pix] = last;
     }
-    if (o.eval_counter) {
-        // list entries processed per pixel, up to and including a stop
-        uint32_t ev = inside ? (stop_pos ? stop_pos : end - start) : 0u;
+    if (o.counters) {
+        // list entries processed per pixel (up to and including a stop),
+        // intersections evaluated, pairs blended
+        uint32_t c[3] = {inside ? (stop_pos ? stop_pos : end - start) : 0u, n_eval, n_blend};
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off, 64);
-        if (lane == 0 && ev) atomicAdd(o.eval_counter, ev);
+        for (int k = 0; k < 3; ++k) {
+            uint32_t v = c[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && v) atomicAdd(o.counters + 2 + k, v);
+        }
     }
 }
 

@@ -152,7 +152,7 @@ class Renderer:
             pair_offset=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
             pair_tile=None, pair_prim=None,
             ranges=torch.empty(2 * ntiles, dtype=torch.int32, device=dev),
-            counters=torch.zeros(4, dtype=torch.int32, device=dev),
+            counters=torch.zeros(8, dtype=torch.int32, device=dev),
             capacity=0, num_pairs=None,
             color=torch.empty((3, H, W), dtype=torch.float32, device=dev),
             depth=torch.empty((H, W), dtype=torch.float32, device=dev),

@@ -357,5 +357,7 @@ def test_accumulate_flag_adds():
     g2 = {k: v.clone() for k, v in g1.items()}
     r.backward(sc_t, st, dcolor=dc, out=g2, accumulate=True)
     torch.cuda.synchronize()
+    # two atomic-mode passes sum in different orders: compare to rounding
     for k in g1:
-        assert torch.allclose(g2[k], 2 * g1[k], rtol=1e-6, atol=1e-7), k
+        scale = float(g1[k].abs().max()) + 1e-30
+        assert float((g2[k] - 2 * g1[k]).abs().max()) <= 1e-5 * scale, k
