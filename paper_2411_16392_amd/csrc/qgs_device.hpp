@@ -58,7 +58,7 @@ __device__ inline PixelRay make_ray(int px, int py, const RasterParams &P)
     r.xn = (((float)px + 0.5f) - P.cx) / P.fx;
     r.yn = (((float)py + 0.5f) - P.cy) / P.fy;
     r.e2 = __builtin_fmaf(r.xn, r.xn, __builtin_fmaf(r.yn, r.yn, 1.0f));
-    r.enorm = __builtin_sqrtf(r.e2);
+    r.enorm = __builtin_amdgcn_sqrtf(r.e2);
     return r;
 }
 
@@ -99,7 +99,7 @@ __device__ inline float gfun(float u)
         acc = __builtin_fmaf(acc, v, 1.0f / 6.0f);
         return __builtin_fmaf(acc, v, 1.0f);
     }
-    const float s = __builtin_sqrtf(__builtin_fmaf(u, u, 1.0f));
+    const float s = __builtin_amdgcn_sqrtf(__builtin_fmaf(u, u, 1.0f));
     const float ash = __logf(u + s);
     return (ash + u * s) * __builtin_amdgcn_rcpf(2.0f * u);
 }
@@ -116,10 +116,14 @@ __device__ inline float gprime(float u)
         acc = __builtin_fmaf(acc, v, 2.0f / 6.0f);
         return acc * u;
     }
-    const float s = __builtin_sqrtf(__builtin_fmaf(u, u, 1.0f));
+    const float s = __builtin_amdgcn_sqrtf(__builtin_fmaf(u, u, 1.0f));
     const float ash = __logf(u + s);
     return (u * s - ash) * __builtin_amdgcn_rcpf(2.0f * u * u);
 }
+
+// Hardware reciprocal and square root (about 1 ulp) are used throughout the
+// rasterizer; forward and backward share this code, so both take the same
+// decisions from the same values.
 
 // Intersection state of one (pixel, primitive) pair.
 struct Hit {
@@ -156,21 +160,21 @@ __device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterPar
         const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
         if (M != 0.0f) {
             const float N = __builtin_fmaf(-H.A * p.Zc, p.Zc, H.C);
-            cand0 = -N / M;
+            cand0 = -N * __builtin_amdgcn_rcpf(M);
             nc = 1;
         }
     } else {
         H.linear = false;
         const float D = __builtin_fmaf(H.B, H.B, -4.0f * H.A * H.C);
         if (D >= 0.0f) {
-            const float sq = __builtin_sqrtf(D);
+            const float sq = __builtin_amdgcn_sqrtf(D);
             const float q = -0.5f * (H.B + (H.B >= 0.0f ? sq : -sq));
             float r1, r2;
             if (q == 0.0f) {
                 r1 = r2 = 0.0f;
             } else {
-                r1 = q / H.A;
-                r2 = H.C / q;
+                r1 = q * __builtin_amdgcn_rcpf(H.A);
+                r2 = H.C * __builtin_amdgcn_rcpf(q);
             }
             cand0 = fminf(r1, r2);
             cand1 = fmaxf(r1, r2);

@@ -28,10 +28,24 @@
 
 namespace qgs {
 
-__device__ inline float wave_sum(float v)
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline float dpp_f(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    // lanes whose source is outside the row read 0; rows outside ROW_MASK keep 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over the wave with DPP: shifts within each 16-lane row, then the row
+// broadcasts 15 and 31; the total lands in lane 63.  Fixed order, so the result
+// is reproducible.
+__device__ inline float wave_sum_to_lane63(float v)
+{
+    v += dpp_f<0x111>(v);        // row_shr:1
+    v += dpp_f<0x112>(v);        // row_shr:2
+    v += dpp_f<0x114>(v);        // row_shr:4
+    v += dpp_f<0x118>(v);        // row_shr:8
+    v += dpp_f<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -230,7 +244,7 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     if (H.linear) {
         // s = -(C - A Zc^2) / (B - 2 A Zc)
         const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
-        const float iM = 1.0f / M;
+        const float iM = __builtin_amdgcn_rcpf(M);
         const float dN = -ds * iM;
         const float dM = -H.s * iM * ds;
         dC = dN;
@@ -238,7 +252,7 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
         dB = dM;
         dZc += -2.0f * H.A * p.Zc * dN - 2.0f * H.A * dM;
     } else {
-        const float iF = 1.0f / __builtin_fmaf(2.0f * H.A, H.s, H.B);
+        const float iF = __builtin_amdgcn_rcpf(__builtin_fmaf(2.0f * H.A, H.s, H.B));
         dA = -H.s * H.s * iF * ds;
         dB = -H.s * iF * ds;
         dC = -iF * ds;
@@ -365,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                         const float4 cr = s_rec[j * 8 + 6];
                         const float rgb[3] = {cr.y, cr.z, cr.w};
                         const float om = 1.0f - alpha;
-                        const float iom = 1.0f / om;
+                        const float iom = __builtin_amdgcn_rcpf(om);
                         const float Ti = T * iom;
                         const float w = alpha * Ti;
                         float X[7];
@@ -391,8 +405,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
             }
             if (__ballot(contrib) != 0ull) {
 #pragma unroll
-                for (int f = 0; f < NGRAD; ++f) gr[f] = wave_sum(gr[f]);
-                if (lane == 0) {
+                for (int f = 0; f < NGRAD; ++f) gr[f] = wave_sum_to_lane63(gr[f]);
+                if (lane == 63) {
                     if (DET) {
 #pragma unroll
                         for (int f = 0; f < NGRAD; ++f) s_acc[DET ? wave : 0][j][f] = gr[f];
