@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=1200, help="rows of view 0 the CPU oracle renders (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
     return ap.parse_args()
 
 
@@ -235,7 +238,49 @@ def main():
                                             f"FP64 forward + backward, {dt:.1f}s"}
         log(f"[bench] cpu oracle {result['cpu_baseline']}", q)
 
+    if not args.no_serve and args.serve_requests > 0:
+        result["serving"] = bench_serving(args, dev, q)
+
     print(json.dumps(result), flush=True)
+
+
+def bench_serving(args, dev, q):
+    """Config 4: a resident 1M-quadric scene, Poisson arrivals at 500/s of
+    views at 256x256, 512x384, 1280x720 or 1920x1080; continuous batching
+    under an 8 GiB tile-list budget vs one view at a time on the same trace."""
+    import numpy as np
+    import torch
+
+    from paper_2411_16392_amd import render as R
+    from paper_2411_16392_amd import scenes
+    from paper_2411_16392_amd import serve
+
+    cfg = scenes.make_config(4)
+    sc_t = R.scene_to_device(cfg.scene, dev)
+    n_req, n_warm = args.serve_requests, args.serve_warmup
+    trace = scenes.serve_trace(n_req + n_warm, rate_hz=500.0, seed=4)
+    budget = 8 << 30
+    with serve.Server(sc_t, budget_bytes=budget, max_slots=8, n_streams=4) as srv:
+        res = serve.run_trace(srv, trace)
+    ok = res["state"][n_warm:] == 0
+    lat = res["latency"][n_warm:]
+    st = res["stats"]
+    s_b = serve.latency_summary(lat)
+    log(f"[bench] serving: {res['frames_per_s']:.1f} frames/s, {s_b}", q)
+    seq = serve.run_sequential(sc_t, trace)
+    s_s = serve.latency_summary(seq["latency"][n_warm:])
+    log(f"[bench] one at a time: {seq['frames_per_s']:.1f} frames/s, {s_s}", q)
+    torch.cuda.synchronize()
+    return {"workload": "1M quadrics (shells + background ball), Poisson 500/s, views 256x256 / 512x384 / "
+                        "1280x720 / 1920x1080, colour only",
+            "requests": n_req, "warmup": n_warm, "rate_hz": 500.0,
+            "frames_per_s": round(res["frames_per_s"], 2), "p50_ms": round(s_b["p50_ms"], 3),
+            "p99_ms": round(s_b["p99_ms"], 3), "mean_ms": round(s_b["mean_ms"], 3),
+            "all_done": bool(ok.all()), "budget_gib": budget / 2 ** 30,
+            "peak_in_flight": int(st.peak_in_flight), "peak_pool_gib": round(st.peak_pool_bytes / 2 ** 30, 3),
+            "mean_pairs": float(np.mean(res["pairs"])),
+            "one_at_a_time": {"frames_per_s": round(seq["frames_per_s"], 2), "p50_ms": round(s_s["p50_ms"], 3),
+                              "p99_ms": round(s_s["p99_ms"], 3), "mean_ms": round(s_s["mean_ms"], 3)}}
 
 
 if __name__ == "__main__":

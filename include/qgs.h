@@ -238,6 +238,81 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
                           const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
                           qgs_stream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of novel-view render requests               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A server keeps a scene resident in HBM and renders colour images of
+ * requested views as they arrive.  Each request runs a count pass (preprocess,
+ * depth sort, pair offsets) and is then admitted for rendering once the exact
+ * memory its tile lists need is free in a pool of `budget_bytes`; requests are
+ * admitted in arrival order as slots and memory free up, while earlier ones are
+ * still on the device, and the requests in flight are spread over `n_streams`
+ * HIP streams so their kernels overlap.  One scheduler thread owns all device
+ * work.  qgs_serve_create and qgs_serve_destroy allocate and free the server's
+ * pools; submit, poll and cancel only touch host queues and may be called from
+ * any one client thread.
+ */
+typedef struct qgs_server qgs_server;
+
+typedef struct qgs_serve_config {
+    int64_t budget_bytes;            /* device bytes for per-request tile lists and sort temporaries */
+    int32_t max_slots;               /* requests in flight (count pass or rendering) */
+    int32_t max_width, max_height;   /* largest view accepted */
+    int32_t n_streams;               /* HIP streams used by the scheduler (default priority) */
+    int32_t device;                  /* HIP device ordinal */
+    qgs_render_opts opts;
+} qgs_serve_config;
+
+#define QGS_REQ_DONE      0
+#define QGS_REQ_CANCELLED 1
+#define QGS_REQ_FAILED    2
+
+typedef struct qgs_completion {
+    uint64_t req_id;
+    int32_t state;     /* QGS_REQ_* */
+    int32_t status;    /* qgs_status of a failed request (QGS_ERR_BUDGET: can never fit) */
+    double t_submit;   /* seconds on the server clock (qgs_serve_clock) */
+    double t_admit;    /* rendering admitted (memory reserved) */
+    double t_done;     /* result complete in the caller's buffer */
+    uint64_t num_pairs;
+} qgs_completion;
+
+typedef struct qgs_serve_stats {
+    uint64_t submitted, completed, cancelled, failed;
+    uint64_t peak_pool_bytes;   /* high-water mark of reserved list memory */
+    int32_t peak_in_flight;     /* most requests on the device at once */
+    int32_t pad;
+} qgs_serve_stats;
+
+/* scene: device arrays that must outlive the server.  Errors:
+   QGS_ERR_INVALID_ARG, QGS_ERR_HIP (allocation failed). */
+qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg, qgs_server **out);
+
+/* Queue a request; the colour image [3][height][width] FP32 is written to
+   out_rgb (device, caller-owned, must stay valid until its completion is
+   polled).  Errors: QGS_ERR_INVALID_ARG (bad camera or larger than max view),
+   QGS_ERR_STATE (server stopping). */
+qgs_status qgs_serve_submit(qgs_server *srv, const qgs_camera *cam, float *out_rgb, uint64_t *req_id);
+
+/* Up to `max` completions in completion order; waits up to timeout_us for the
+   first one (0: no wait). */
+qgs_status qgs_serve_poll(qgs_server *srv, qgs_completion *out, int32_t max, int32_t *n, int32_t timeout_us);
+
+/* Cancel a request that has not been admitted for rendering; its completion
+   reports QGS_REQ_CANCELLED.  QGS_ERR_NOT_FOUND if unknown or already done,
+   QGS_ERR_STATE if already rendering. */
+qgs_status qgs_serve_cancel(qgs_server *srv, uint64_t req_id);
+
+qgs_status qgs_serve_stats_get(qgs_server *srv, qgs_serve_stats *out);
+
+/* Seconds on the server's steady clock. */
+double qgs_serve_clock(qgs_server *srv);
+
+/* Finishes the work in flight, stops the scheduler, frees the pools. */
+qgs_status qgs_serve_destroy(qgs_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,26 @@ class QgsSceneGrads(ctypes.Structure):
                 ("opacity", c_void_p), ("rgb", c_void_p)]
 
 
+class QgsServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", c_int64), ("max_slots", c_int32), ("max_width", c_int32), ("max_height", c_int32),
+                ("n_streams", c_int32), ("device", c_int32), ("opts", QgsRenderOpts)]
+
+
+class QgsCompletion(ctypes.Structure):
+    _fields_ = [("req_id", c_uint64), ("state", c_int32), ("status", c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("num_pairs", c_uint64)]
+
+
+class QgsServeStats(ctypes.Structure):
+    _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("cancelled", c_uint64), ("failed", c_uint64),
+                ("peak_pool_bytes", c_uint64), ("peak_in_flight", c_int32), ("pad", c_int32)]
+
+
+QGS_REQ_DONE = 0
+QGS_REQ_CANCELLED = 1
+QGS_REQ_FAILED = 2
+
+
 class QgsError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -98,6 +118,15 @@ _SIGS = {
                         ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts), ctypes.POINTER(QgsImages),
                         ctypes.POINTER(QgsImageGrads), ctypes.POINTER(QgsSceneGrads), c_void_p, ctypes.c_size_t,
                         c_void_p], c_int32),
+    "qgs_serve_create": ([ctypes.POINTER(QgsScene), ctypes.POINTER(QgsServeConfig), ctypes.POINTER(c_void_p)],
+                         c_int32),
+    "qgs_serve_submit": ([c_void_p, ctypes.POINTER(QgsCamera), c_void_p, ctypes.POINTER(c_uint64)], c_int32),
+    "qgs_serve_poll": ([c_void_p, ctypes.POINTER(QgsCompletion), c_int32, ctypes.POINTER(c_int32), c_int32],
+                       c_int32),
+    "qgs_serve_cancel": ([c_void_p, c_uint64], c_int32),
+    "qgs_serve_stats_get": ([c_void_p, ctypes.POINTER(QgsServeStats)], c_int32),
+    "qgs_serve_clock": ([c_void_p], ctypes.c_double),
+    "qgs_serve_destroy": ([c_void_p], c_int32),
 }
 
 
@@ -166,3 +195,41 @@ def qgs_render_bwd(scene: QgsScene, prims: QgsPrimBuf, lists: QgsTileLists, cam:
     _check(lib().qgs_render_bwd(ctypes.byref(scene), ctypes.byref(prims), ctypes.byref(lists), ctypes.byref(cam),
                                 ctypes.byref(opts), ctypes.byref(fwd), ctypes.byref(dL), ctypes.byref(out), ws,
                                 ws_bytes, stream), "qgs_render_bwd")
+
+
+def qgs_serve_create(scene: QgsScene, cfg: QgsServeConfig) -> int:
+    h = c_void_p(0)
+    _check(lib().qgs_serve_create(ctypes.byref(scene), ctypes.byref(cfg), ctypes.byref(h)), "qgs_serve_create")
+    return h.value
+
+
+def qgs_serve_submit(srv: int, cam: QgsCamera, out_rgb: int) -> int:
+    rid = c_uint64(0)
+    _check(lib().qgs_serve_submit(srv, ctypes.byref(cam), out_rgb, ctypes.byref(rid)), "qgs_serve_submit")
+    return rid.value
+
+
+def qgs_serve_poll(srv: int, max_n: int = 64, timeout_us: int = 0):
+    buf = (QgsCompletion * max_n)()
+    n = c_int32(0)
+    _check(lib().qgs_serve_poll(srv, buf, max_n, ctypes.byref(n), timeout_us), "qgs_serve_poll")
+    return [buf[i] for i in range(n.value)]
+
+
+def qgs_serve_cancel(srv: int, req_id: int) -> int:
+    """Returns the status (QGS_OK, QGS_ERR_NOT_FOUND, QGS_ERR_STATE)."""
+    return lib().qgs_serve_cancel(srv, req_id)
+
+
+def qgs_serve_stats_get(srv: int) -> QgsServeStats:
+    st = QgsServeStats()
+    _check(lib().qgs_serve_stats_get(srv, ctypes.byref(st)), "qgs_serve_stats_get")
+    return st
+
+
+def qgs_serve_clock(srv: int) -> float:
+    return lib().qgs_serve_clock(srv)
+
+
+def qgs_serve_destroy(srv: int):
+    _check(lib().qgs_serve_destroy(srv), "qgs_serve_destroy")
