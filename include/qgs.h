@@ -97,12 +97,20 @@ typedef struct qgs_render_opts {
  *              32 x 32-bit words: [0..3] pixel rectangle x0, x1, y0, y1 (int32,
  *              inclusive; x0 > x1 when empty), [4..7] projected centre split as
  *              U, 0.5 - frac(u_c), V, 0.5 - frac(v_c) (U, V integral floats),
- *              [8..11] Zc / fx, Zc / fy, Zc, lambda_1, [12..15] lambda_2,
- *              1/sigma_1^2, 1/sigma_2^2, opacity, [16..24] camera-from-local
- *              rotation row-major, [25..27] rgb, [28..31] unused.
+ *              [8..11] Zc, lambda_1, lambda_2, opacity, [12..13] 1/sigma_1^2,
+ *              1/sigma_2^2, [14..15] and [28..30] the screen conic a, b, c, d, e
+ *              of the enclosing ellipsoid (below) in pixels relative to the
+ *              projected centre, f = a dx^2 + b dx dy + c dy^2 + d dx + e dy - 1,
+ *              [16..24] camera-from-local rotation row-major, [25..27] rgb,
+ *              [31] unused.
+ *  conic       [n][8] FP64: the image of an ellipsoid enclosing the support
+ *              (c00, c01, c11, c02, c12, c22 in normalised camera coordinates),
+ *              [6] 1 when it bounds the support on screen (ellipsoid in front of
+ *              the near plane), [7] unused.  Tiles of the rectangle that miss it
+ *              are not emitted.
  *  depth_key   [n] FP32 bit pattern of the centre's camera-space depth (0 if culled)
  *  rect        [n][4] tile rectangle tx0, ty0, tx1, ty1 inclusive; (0, 0, -1, -1) if empty
- *  tiles       [n] number of tiles in rect (0 if culled or off screen)
+ *  tiles       [n] number of tiles emitted (0 if culled or off screen)
  *  pair_offset [n] written by qgs_bin_sort: index of the primitive's first pair
  *              in emission order (pairs of one primitive are contiguous there)
  */
@@ -112,6 +120,7 @@ typedef struct qgs_prim_buf {
     int32_t *rect;
     uint32_t *tiles;
     uint32_t *pair_offset;
+    double *conic;
     int64_t n;
 } qgs_prim_buf;
 
@@ -119,6 +128,9 @@ typedef struct qgs_prim_buf {
  * Sorted tile lists (device memory, caller-allocated).
  *  pair_tile, pair_prim  [capacity] tile id and primitive index of each pair,
  *                        sorted by (tile, depth key, primitive index)
+ *  emit_to_sorted        [capacity] position in the sorted list of each pair,
+ *                        indexed by emission order (primitive p's pairs are
+ *                        pair_offset[p] ... pair_offset[p] + tiles[p] - 1)
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
  *  counters              [8] uint32: [0] number of pairs, [1] overflow flag
  *                        (1 when [0] > capacity: lists and ranges are then empty
@@ -132,6 +144,7 @@ typedef struct qgs_prim_buf {
 typedef struct qgs_tile_lists {
     uint32_t *pair_tile;
     uint32_t *pair_prim;
+    uint32_t *emit_to_sorted;
     uint32_t *ranges;
     uint32_t *counters;
     uint64_t capacity;
@@ -185,11 +198,13 @@ qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t pair_c
 /*
  * Projection, culling and conservative screen bounds, one thread per primitive
  * (Sec. 3.2 congruent transform; supplement, bounding boxes).  Writes records,
- * depth_key, rect and tiles of `out`.  The rectangle bounds every pixel whose ray
- * can meet the primitive inside k_sigma: since the arc-length factor is >= 1, an
- * accepted hit has |x| <= k sigma_1, |y| <= k sigma_2 and a height between the
- * extremes of lambda_1 x^2 + lambda_2 y^2 over that ellipse, so the projection
- * of this (slightly inflated) local box is used.  Errors: QGS_ERR_INVALID_ARG.
+ * depth_key, rect, tiles and conic of `out`.  The bounds hold every pixel whose
+ * ray can meet the primitive inside k_sigma: since the arc-length factor is
+ * >= 1, an accepted hit has |x| <= k sigma_1, |y| <= k sigma_2 and a height
+ * between the extremes of lambda_1 x^2 + lambda_2 y^2 over that ellipse.  The
+ * rectangle is the projection of this (slightly inflated) local box; tiles of
+ * it are kept only if they meet the projection of an ellipsoid enclosing the
+ * box's elliptic cylinder.  Errors: QGS_ERR_INVALID_ARG.
  */
 qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const qgs_render_opts *opts,
                           qgs_prim_buf *out, qgs_stream_t stream);

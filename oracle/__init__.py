@@ -50,9 +50,9 @@ def _lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
-        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P]
+        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P]
         L.oracle_keys.restype = None
-        L.oracle_bin_sort.argtypes = [i64, P, P, P, i32, i32, i64, P, P, P]
+        L.oracle_bin_sort.argtypes = [i64, P, P, P, P, P, P, i32, i32, i32, i32, i64, P, P, P, P]
         L.oracle_bin_sort.restype = i64
         L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                     i32, i32, i32, i32, i32,
@@ -124,27 +124,35 @@ def keys(scene, cam, opts=None):
     rect_px = np.zeros((n, 4), np.int32)
     rect_tile = np.zeros((n, 4), np.int32)
     tiles = np.zeros(n, np.uint32)
+    conic = np.zeros((n, 6), np.float64)
+    conic_ok = np.zeros(n, np.uint8)
     arrs = [_f32(a) for a in scene.arrays()]
     camv = cam_array(cam)
     _lib().oracle_keys(n, *[_ptr(a) for a in arrs], _ptr(camv), cam.width, cam.height,
                        ctypes.c_float(o[0]), ctypes.c_float(o[1]),
-                       _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles))
-    return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles)
+                       _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles),
+                       _ptr(conic), _ptr(conic_ok))
+    return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles,
+                conic=conic, conic_ok=conic_ok, cam=camv, width=cam.width, height=cam.height)
 
 
-def bin_sort(k, cam):
-    """Sorted tile|depth key list and per-tile ranges from the key stage."""
+def bin_sort(k, cam, with_seq=False):
+    """Sorted tile|depth key list and per-tile ranges from the key stage
+    (with_seq: also the emission index of every sorted pair)."""
     n = k["culled"].shape[0]
     tx, ty = cam.tiles_x, cam.tiles_y
     ranges = np.zeros((tx * ty, 2), np.uint32)
     L = _lib()
-    total = L.oracle_bin_sort(n, _ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), tx, ty,
-                              0, None, None, _ptr(ranges))
+    args = (_ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), _ptr(k["conic"]), _ptr(k["conic_ok"]),
+            _ptr(k["cam"]), k["width"], k["height"], tx, ty)
+    total = L.oracle_bin_sort(n, *args, 0, None, None, None, _ptr(ranges))
     keys_out = np.zeros(max(total, 1), np.uint64)
     prims = np.zeros(max(total, 1), np.uint32)
-    total2 = L.oracle_bin_sort(n, _ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), tx, ty,
-                               total, _ptr(keys_out), _ptr(prims), _ptr(ranges))
+    seq = np.zeros(max(total, 1), np.uint32)
+    total2 = L.oracle_bin_sort(n, *args, total, _ptr(keys_out), _ptr(prims), _ptr(seq), _ptr(ranges))
     assert total2 == total
+    if with_seq:
+        return keys_out[:total], prims[:total], ranges, seq[:total]
     return keys_out[:total], prims[:total], ranges
 
 

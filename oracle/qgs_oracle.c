@@ -82,11 +82,49 @@ static double max3(double a, double b, double c) { double m = a > b ? a : b; ret
  * cam = {R[9] (world->camera, row-major), t[3], fx, fy, cx, cy} as FP32.
  * rect_px / rect_tile: {x0, y0, x1, y1} inclusive; empty = {0, 0, -1, -1}.
  */
+/*
+ * Conic test of one tile.  C = {c00, c01, c11, c02, c12, c22} is the image of
+ * the enclosing ellipsoid in normalised camera coordinates (x, y) =
+ * ((u - cx) / fx, (v - cy) / fy): f(x, y) = c00 x^2 + 2 c01 x y + c11 y^2 +
+ * 2 c02 x + 2 c12 y + c22 <= 0 inside.  The tile's pixel centres, widened by
+ * 1/64 pixel, span a rectangle; f is a convex quadratic, so it meets the
+ * interior iff f's minimiser lies in the rectangle or the minimum of f along
+ * one of its edges is <= 0.
+ */
+static double conic_f(const double *C, double x, double y)
+{
+    return ((C[0] * x + 2.0 * C[1] * y + 2.0 * C[3]) * x + (C[2] * y + 2.0 * C[4]) * y) + C[5];
+}
+
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static int oracle_tile_hit(const double *C, int tx, int ty, const float *cam, int width, int height)
+{
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const double pad_px = 1.0 / 64.0;
+    const int ux0 = tx * OT, ux1 = (tx * OT + OT - 1) < width - 1 ? tx * OT + OT - 1 : width - 1;
+    const int vy0 = ty * OT, vy1 = (ty * OT + OT - 1) < height - 1 ? ty * OT + OT - 1 : height - 1;
+    const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) / fx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) / fx;
+    const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) / fy, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) / fy;
+    const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
+    const double det = a * c - b * b;
+    const double mx = (b * e - c * d) / det, my = (b * d - a * e) / det;
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 1;
+    const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    for (int k = 0; k < 2; ++k) {
+        const double y = clampd(-(b * xs[k] + e) / c, y0, y1);
+        if (conic_f(C, xs[k], y) <= 0.0) return 1;
+        const double x = clampd(-(b * ys[k] + d) / a, x0, x1);
+        if (conic_f(C, x, ys[k]) <= 0.0) return 1;
+    }
+    return 0;
+}
+
 void oracle_keys(int64_t n, const float *center, const float *quat, const float *scale,
                  const float *curv, const float *opac, const float *rgb,
                  const float *cam, int32_t width, int32_t height, float near_f, float k_sigma,
                  uint8_t *culled, uint32_t *depth_bits, int32_t *rect_px, int32_t *rect_tile,
-                 uint32_t *tiles)
+                 uint32_t *tiles, double *conic, uint8_t *conic_ok)
 {
     double W[9], T[3];
     for (int i = 0; i < 9; ++i) W[i] = cam[i];
@@ -103,6 +141,8 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
         tiles[p] = 0;
         depth_bits[p] = 0;
         culled[p] = 1;
+        conic_ok[p] = 0;
+        for (int i = 0; i < 6; ++i) conic[6 * p + i] = 0.0;
 
         const float *cf = center + 3 * p, *qf = quat + 4 * p, *sf = scale + 2 * p, *lf = curv + 2 * p;
         if (!finite_f(cf, 3) || !finite_f(qf, 4) || !finite_f(sf, 2) || !finite_f(lf, 2) ||
@@ -186,7 +226,42 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
         if (px0 > px1 || py0 > py1) continue;
         rp[0] = px0; rp[1] = py0; rp[2] = px1; rp[3] = py1;
         rt[0] = px0 / OT; rt[1] = py0 / OT; rt[2] = px1 / OT; rt[3] = py1 / OT;
-        tiles[p] = (uint32_t)((rt[2] - rt[0] + 1) * (rt[3] - rt[1] + 1));
+
+        /* Ellipsoid enclosing the box's elliptic cylinder {x^2/hx^2 + y^2/hy^2
+           <= 1, z in [zlo, zhi]}: squared semi-axes hx^2/(1-t), hy^2/(1-t),
+           hz^2/t about the mid-height zm (a point of the cylinder satisfies
+           (1-t) + t = 1), with t = hz / (hz + min(hx, hy)). */
+        double *Cq = conic + 6 * p;
+        if (!behind) {
+            const double hz = 0.5 * (zhi - zlo), zm = 0.5 * (zlo + zhi);
+            const double mxy = hx < hy ? hx : hy;
+            const double t = hz / (hz + mxy);
+            const double q[3] = {(hx * hx) / (1.0 - t), (hy * hy) / (1.0 - t), (hz * hz) / t};
+            const double iq[3] = {1.0 / q[0], 1.0 / q[1], 1.0 / q[2]};
+            double ce[3];
+            for (int i = 0; i < 3; ++i) ce[i] = fma(Rc[3 * i + 2], zm, cc[i]);
+            /* A = Rc diag(1/q) Rc^T, symmetric: A[i][j] */
+            double A[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    A[i][j] = fma(Rc[3 * i] * iq[0], Rc[3 * j],
+                                  fma(Rc[3 * i + 1] * iq[1], Rc[3 * j + 1], (Rc[3 * i + 2] * iq[2]) * Rc[3 * j + 2]));
+            double w[3];
+            for (int i = 0; i < 3; ++i) w[i] = fma(A[i][0], ce[0], fma(A[i][1], ce[1], A[i][2] * ce[2]));
+            const double gm1 = fma(ce[0], w[0], fma(ce[1], w[1], ce[2] * w[2])) - 1.0;
+            /* ray d = (x, y, 1) meets the ellipsoid iff d^T [(gamma-1) A - w w^T] d <= 0 */
+            const int ii[6] = {0, 0, 1, 0, 1, 2}, jj[6] = {0, 1, 1, 2, 2, 2};
+            for (int k = 0; k < 6; ++k) Cq[k] = fma(gm1, A[ii[k]][jj[k]], -(w[ii[k]] * w[jj[k]]));
+            /* the conic is a bounded ellipse when the ellipsoid lies in front of the near plane */
+            const double S33 = fma(q[0] * Rc[6], Rc[6], fma(q[1] * Rc[7], Rc[7], (q[2] * Rc[8]) * Rc[8]));
+            const double dz = ce[2] - near_d;
+            conic_ok[p] = (dz > 0.0 && dz * dz > S33) ? 1 : 0;
+        }
+        uint32_t cnt = 0;
+        for (int ty = rt[1]; ty <= rt[3]; ++ty)
+            for (int tx = rt[0]; tx <= rt[2]; ++tx)
+                cnt += (!conic_ok[p] || oracle_tile_hit(Cq, tx, ty, cam, width, height)) ? 1u : 0u;
+        tiles[p] = cnt;
     }
 }
 
@@ -205,20 +280,24 @@ static int cmp_pair(const void *a, const void *b)
 }
 
 /*
- * Emits one (key, primitive) pair per tile of every rectangle, in primitive
- * order and row-major within a rectangle, and sorts by key with ties kept in
- * emission order.  Returns the pair count; writes outputs only if it fits cap.
- * ranges[2t], ranges[2t+1] = [start, end) of tile t in the sorted list.
+ * Emits one (key, primitive) pair per tile of every rectangle that passes the
+ * conic test, in primitive order and row-major within a rectangle, and sorts
+ * by key with ties kept in emission order.  Returns the pair count; writes
+ * outputs only if it fits cap.  ranges[2t], ranges[2t+1] = [start, end) of
+ * tile t in the sorted list; out_seq = emission index of each sorted pair.
  */
 int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_bits,
-                        const int32_t *rect_tile, int32_t tiles_x, int32_t tiles_y,
-                        int64_t cap, uint64_t *out_keys, uint32_t *out_prim, uint32_t *ranges)
+                        const int32_t *rect_tile, const double *conic, const uint8_t *conic_ok,
+                        const float *cam, int32_t width, int32_t height, int32_t tiles_x, int32_t tiles_y,
+                        int64_t cap, uint64_t *out_keys, uint32_t *out_prim, uint32_t *out_seq, uint32_t *ranges)
 {
     int64_t total = 0;
     for (int64_t p = 0; p < n; ++p) {
         const int32_t *r = rect_tile + 4 * p;
         if (culled[p] || r[2] < r[0] || r[3] < r[1]) continue;
-        total += (int64_t)(r[2] - r[0] + 1) * (r[3] - r[1] + 1);
+        for (int ty = r[1]; ty <= r[3]; ++ty)
+            for (int tx = r[0]; tx <= r[2]; ++tx)
+                total += (!conic_ok[p] || oracle_tile_hit(conic + 6 * p, tx, ty, cam, width, height)) ? 1 : 0;
     }
     if (total > cap) return total;
     opair *pairs = (opair *)malloc(sizeof(opair) * (size_t)(total > 0 ? total : 1));
@@ -228,6 +307,7 @@ int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_
         if (culled[p] || r[2] < r[0] || r[3] < r[1]) continue;
         for (int ty = r[1]; ty <= r[3]; ++ty)
             for (int tx = r[0]; tx <= r[2]; ++tx) {
+                if (conic_ok[p] && !oracle_tile_hit(conic + 6 * p, tx, ty, cam, width, height)) continue;
                 pairs[k].key = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | depth_bits[p];
                 pairs[k].seq = (uint64_t)k;
                 pairs[k].prim = (uint32_t)p;
@@ -240,6 +320,7 @@ int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_
     for (int64_t i = 0; i < total; ++i) {
         out_keys[i] = pairs[i].key;
         out_prim[i] = pairs[i].prim;
+        out_seq[i] = (uint32_t)pairs[i].seq;
         const uint32_t t = (uint32_t)(pairs[i].key >> 32);
         if (i == 0 || (uint32_t)(pairs[i - 1].key >> 32) != t) ranges[2 * t] = (uint32_t)i;
         if (i == total - 1 || (uint32_t)(pairs[i + 1].key >> 32) != t) ranges[2 * t + 1] = (uint32_t)(i + 1);

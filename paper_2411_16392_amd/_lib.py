@@ -47,12 +47,12 @@ class QgsRenderOpts(ctypes.Structure):
 
 class QgsPrimBuf(ctypes.Structure):
     _fields_ = [("records", c_void_p), ("depth_key", c_void_p), ("rect", c_void_p), ("tiles", c_void_p),
-                ("pair_offset", c_void_p), ("n", c_int64)]
+                ("pair_offset", c_void_p), ("conic", c_void_p), ("n", c_int64)]
 
 
 class QgsTileLists(ctypes.Structure):
-    _fields_ = [("pair_tile", c_void_p), ("pair_prim", c_void_p), ("ranges", c_void_p), ("counters", c_void_p),
-                ("capacity", c_uint64)]
+    _fields_ = [("pair_tile", c_void_p), ("pair_prim", c_void_p), ("emit_to_sorted", c_void_p),
+                ("ranges", c_void_p), ("counters", c_void_p), ("capacity", c_uint64)]
 
 
 class QgsImages(ctypes.Structure):

@@ -25,7 +25,7 @@ bool cam_ok(const qgs_camera *c)
     if (!c || c->width <= 0 || c->height <= 0) return false;
     if ((int64_t)c->width * c->height > (int64_t)1 << 31) return false;
     if (!(isfinite(c->fx) && isfinite(c->fy) && isfinite(c->cx) && isfinite(c->cy))) return false;
-    if (c->fx == 0.0f || c->fy == 0.0f) return false;
+    if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) return false;
     for (int i = 0; i < 9; ++i)
         if (!isfinite(c->R[i])) return false;
     for (int i = 0; i < 3; ++i)
@@ -51,14 +51,15 @@ bool prims_ok(const qgs_prim_buf *p, int64_t n)
 {
     if (!p || p->n != n) return false;
     if (n == 0) return true;
-    return p->records && ((uintptr_t)p->records % 16 == 0) && p->depth_key && p->rect && p->tiles && p->pair_offset;
+    return p->records && ((uintptr_t)p->records % 16 == 0) && p->depth_key && p->rect && p->tiles && p->pair_offset &&
+           p->conic;
 }
 
 bool lists_ok(const qgs_tile_lists *l)
 {
     if (!l || !l->ranges || !l->counters) return false;
     if (l->capacity > 0xFFFFFFFFull) return false;
-    if (l->capacity > 0 && (!l->pair_tile || !l->pair_prim)) return false;
+    if (l->capacity > 0 && (!l->pair_tile || !l->pair_prim || !l->emit_to_sorted)) return false;
     return true;
 }
 
@@ -97,7 +98,8 @@ RasterArgs raster_args(const qgs_prim_buf *prims, const qgs_tile_lists *lists, c
     a.ranges = lists->ranges;
     a.counters = lists->counters;
     a.pair_offset = prims->pair_offset;
-    a.rect = prims->rect;
+    a.tiles = prims->tiles;
+    a.emit_to_sorted = lists->emit_to_sorted;
     a.tiles_x = (c->width + 15) / 16;
     a.tiles_y = (c->height + 15) / 16;
     return a;
@@ -174,6 +176,7 @@ qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const q
     a.depth_key = out->depth_key;
     a.rect = out->rect;
     a.tiles = out->tiles;
+    a.conic = out->conic;
     return hip_status(launch_preprocess(a, (hipStream_t)stream));
 }
 
@@ -191,11 +194,14 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
     a.depth_key = prims->depth_key;
     a.tiles = prims->tiles;
     a.rect = prims->rect;
+    a.conic = prims->conic;
+    a.cam = *cam;
     a.pair_offset = prims->pair_offset;
     a.tiles_x = (cam->width + 15) / 16;
     a.tiles_y = (cam->height + 15) / 16;
     a.pair_tile = lists->pair_tile;
     a.pair_prim = lists->pair_prim;
+    a.emit_to_sorted = lists->emit_to_sorted;
     a.ranges = lists->ranges;
     a.counters = lists->counters;
     a.capacity = lists->capacity;

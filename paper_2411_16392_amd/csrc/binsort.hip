@@ -1,4 +1,5 @@
-// Tile|depth key lists: integer-only, bit-exact.
+// Tile|depth key lists: integer-only, bit-exact (the tile test is the FP64
+// conic test of qgs_keys.hpp, with the same decisions as the preprocess).
 //
 // The required order is a stable sort of the 64-bit keys (tile << 32 | depth)
 // emitted primitive by primitive (tiles row-major within each rectangle).  An
@@ -19,6 +20,7 @@
 #include <stdint.h>
 
 #include "qgs_internal.hpp"
+#include "qgs_keys.hpp"
 
 namespace qgs {
 
@@ -291,53 +293,49 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t *order, con
     pair_offset[order[r]] = o > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)o;
 }
 
-// Each block emits the pairs of 256 consecutive primitives in depth order;
-// its threads stride over the block's pair range and find their primitive by
-// binary search of the LDS copy of the offsets.
+// One thread per primitive, in depth order: emits the (tile, emission index)
+// pairs of the tiles of its rectangle that pass the conic test, row-major,
+// at its offset, and records each pair's primitive.  The decisions are those
+// the preprocess counted with the same test.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
-                                              int64_t n, int32_t tiles_x, const uint32_t *counters, uint32_t *out_tile,
-                                              uint32_t *out_prim)
+                                              const double *conic, int64_t n, qgs_camera cam, int32_t tiles_x,
+                                              const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
+                                              uint32_t *emit_prim)
 {
-    __shared__ uint32_t s_off[257];
-    __shared__ uint32_t s_prim[256], s_x0[256], s_y0[256], s_w[256];
-    if (counters[1]) return;  // overflow: nothing valid to emit
-    const int64_t r0 = (int64_t)blockIdx.x * 256;
-    const int t = threadIdx.x;
-    const uint64_t base = off[r0];
-    const int64_t r = r0 + t;
-    if (r < n) {
-        const uint32_t p = order[r];
-        s_off[t] = (uint32_t)(off[r] - base);
-        s_prim[t] = p;
-        s_x0[t] = (uint32_t)rect[4 * p];
-        s_y0[t] = (uint32_t)rect[4 * p + 1];
-        s_w[t] = (uint32_t)(rect[4 * p + 2] - rect[4 * p] + 1);
-    } else {
-        s_off[t] = (uint32_t)(off[n] - base);
-        s_prim[t] = 0;
-        s_x0[t] = s_y0[t] = 0;
-        s_w[t] = 1;
-    }
-    if (t == 0) {
-        const int64_t re = r0 + 256 < n ? r0 + 256 : n;
-        s_off[256] = (uint32_t)(off[re] - base);
-    }
-    __syncthreads();
-    const uint32_t total = s_off[256];
-    for (uint32_t j = t; j < total; j += 256) {
-        // last k with s_off[k] <= j
-        int lo = 0, hi = 255;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= j) lo = mid;
-            else hi = mid - 1;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || counters[1]) return;
+    const uint64_t base = off[r], cnt = off[r + 1] - base;
+    if (cnt == 0) return;
+    const uint32_t p = order[r];
+    const int32_t *rc = rect + 4 * (size_t)p;
+    const double *C = conic + 8 * (size_t)p;
+    const bool cok = C[6] != 0.0;
+    uint64_t k = 0;
+    for (int ty = rc[1]; ty <= rc[3]; ++ty)
+        for (int tx = rc[0]; tx <= rc[2]; ++tx) {
+            if (cok && !conic_tile_hit(C, tx, ty, cam)) continue;
+            if (k < cnt) {
+                const uint64_t e = base + k;
+                out_tile[e] = (uint32_t)(ty * tiles_x + tx);
+                out_emit[e] = (uint32_t)e;
+                emit_prim[e] = p;
+            }
+            ++k;
         }
-        const uint32_t local = j - s_off[lo];
-        const uint32_t w = s_w[lo];
-        const uint32_t ty = s_y0[lo] + local / w, tx = s_x0[lo] + local % w;
-        out_tile[base + j] = ty * (uint32_t)tiles_x + tx;
-        out_prim[base + j] = s_prim[lo];
-    }
+}
+
+// After the sort the values are emission indices: replace them by primitive
+// ids and record where each emitted pair landed.
+__global__ __launch_bounds__(256) void k_gather_prims(const uint32_t *emit_prim, Count cnt, uint32_t *pair_prim,
+                                                      uint32_t *emit_to_sorted)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = cnt.get();
+    if (i >= n) return;
+    const uint32_t e = pair_prim[i];
+    if (e >= n) return;  // cannot happen for lists built here
+    pair_prim[i] = emit_prim[e];
+    emit_to_sorted[e] = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
@@ -346,12 +344,13 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint6
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt, uint32_t *ranges)
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt, uint32_t *ranges, uint32_t ntiles)
 {
     const uint64_t n = cnt.get();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t t = tile[i];
+    if (t >= ntiles) return;  // cannot happen for lists built here
     if (i == 0 || tile[i - 1] != t) ranges[2 * (uint64_t)t] = (uint32_t)i;
     if (i == n - 1 || tile[i + 1] != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
 }
@@ -386,6 +385,7 @@ SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
     w.hist = (uint32_t *)take(4 * 256 * nbmax);
     w.tileT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.primT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
+    w.emit_prim = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.bytes = o;
     return w;
 }
@@ -435,7 +435,7 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
     uint32_t *et = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
     uint32_t *ep = (passes % 2 == 0) ? a.pair_prim : ws.primT;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA, ws.off, a.rect,
-                       n, a.tiles_x, a.counters, et, ep);
+                       a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
     Count c{a.counters, bound};
     uint32_t *ki = et, *vi = ep;
     for (int pass = 0; pass < passes; ++pass) {
@@ -446,8 +446,10 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
         ki = ko;
         vi = vo;
     }
+    hipLaunchKernelGGL(k_gather_prims, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream,
+                       (const uint32_t *)ws.emit_prim, c, a.pair_prim, a.emit_to_sorted);
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream, (const uint32_t *)a.pair_tile,
-                       c, a.ranges);
+                       c, a.ranges, (uint32_t)ntiles);
     return hipGetLastError();
 }
 

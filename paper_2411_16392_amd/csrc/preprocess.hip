@@ -12,6 +12,7 @@
 
 #include "qgs_device.hpp"
 #include "qgs_internal.hpp"
+#include "qgs_keys.hpp"
 
 #pragma clang fp contract(off)
 
@@ -52,6 +53,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
         zf = (float)cc[2];
         ok = zf > a.near_plane;
     }
+    double *cq = a.conic + 8 * p;
+    for (int i = 0; i < 8; ++i) cq[i] = 0.0;
     if (!ok) {
         rec[0] = empty_rect;
         a.depth_key[p] = 0u;
@@ -140,20 +143,70 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
     }
     const int tx0 = px0 / TILE, tx1 = px1 / TILE, ty0 = py0 / TILE, ty1 = py1 / TILE;
     rt[0] = tx0; rt[1] = ty0; rt[2] = tx1; rt[3] = ty1;
-    a.tiles[p] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+
+    // Ellipsoid enclosing the box's elliptic cylinder {x^2/hx^2 + y^2/hy^2 <= 1,
+    // z in [zlo, zhi]}: squared semi-axes hx^2/(1-t), hy^2/(1-t), hz^2/t about
+    // the mid-height, t = hz / (hz + min(hx, hy)); its image in the camera is
+    // the conic (gamma - 1) A - w w^T with A = Rc diag(1/q) Rc^T, w = A c_e,
+    // gamma = c_e^T w.
+    double C[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool cok = false;
+    if (!behind) {
+        const double hz = 0.5 * (zhi - zlo), zm = 0.5 * (zlo + zhi);
+        const double mxy = hx < hy ? hx : hy;
+        const double t = hz / (hz + mxy);
+        const double q[3] = {(hx * hx) / (1.0 - t), (hy * hy) / (1.0 - t), (hz * hz) / t};
+        const double iq[3] = {1.0 / q[0], 1.0 / q[1], 1.0 / q[2]};
+        double ce[3];
+        for (int i = 0; i < 3; ++i) ce[i] = fma(Rc[3 * i + 2], zm, cc[i]);
+        double A[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                A[i][j] = fma(Rc[3 * i] * iq[0], Rc[3 * j],
+                              fma(Rc[3 * i + 1] * iq[1], Rc[3 * j + 1], (Rc[3 * i + 2] * iq[2]) * Rc[3 * j + 2]));
+        double w3[3];
+        for (int i = 0; i < 3; ++i) w3[i] = fma(A[i][0], ce[0], fma(A[i][1], ce[1], A[i][2] * ce[2]));
+        const double gm1 = fma(ce[0], w3[0], fma(ce[1], w3[1], ce[2] * w3[2])) - 1.0;
+        const int ii[6] = {0, 0, 1, 0, 1, 2}, jj[6] = {0, 1, 1, 2, 2, 2};
+        for (int k = 0; k < 6; ++k) C[k] = fma(gm1, A[ii[k]][jj[k]], -(w3[ii[k]] * w3[jj[k]]));
+        const double S33 = fma(q[0] * Rc[6], Rc[6], fma(q[1] * Rc[7], Rc[7], (q[2] * Rc[8]) * Rc[8]));
+        const double dz = ce[2] - near_d;
+        cok = dz > 0.0 && dz * dz > S33;
+    }
+    for (int i = 0; i < 6; ++i) cq[i] = C[i];
+    cq[6] = cok ? 1.0 : 0.0;
+    uint32_t cnt = 0;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) cnt += (!cok || conic_tile_hit(C, tx, ty, a.cam)) ? 1u : 0u;
+    a.tiles[p] = cnt;
 
     // projected centre split into integer + fraction, and the record
     const double uc = fma(fx, cc[0] / cc[2], cxp), vc = fma(fy, cc[1] / cc[2], cyp);
     const double U = floor(uc), V = floor(vc);
     const float hu = (float)(0.5 - (uc - U)), hv = (float)(0.5 - (vc - V));
+    // the conic in pixels relative to the projected centre, scaled so that
+    // f = -1 at the centre (which is inside: the local origin is in the box)
+    float cA = 0.0f, cB = 0.0f, cC = 0.0f, cD = 0.0f, cE = 0.0f;
+    if (cok) {
+        const double xi = (uc - cxp) / fx, eta = (vc - cyp) / fy;
+        const double f0 = conic_eval(C, xi, eta);
+        if (f0 < 0.0) {
+            const double sc = -1.0 / f0, ifx = 1.0 / fx, ify = 1.0 / fy;
+            cA = (float)(C[0] * ifx * ifx * sc);
+            cB = (float)(2.0 * C[1] * ifx * ify * sc);
+            cC = (float)(C[2] * ify * ify * sc);
+            cD = (float)(2.0 * (C[0] * xi + C[1] * eta + C[3]) * ifx * sc);
+            cE = (float)(2.0 * (C[1] * xi + C[2] * eta + C[4]) * ify * sc);
+        }
+    }
     rec[0] = make_float4(__int_as_float(px0), __int_as_float(px1), __int_as_float(py0), __int_as_float(py1));
     rec[1] = make_float4((float)U, hu, (float)V, hv);
-    rec[2] = make_float4((float)(cc[2] / fx), (float)(cc[2] / fy), zf, lf1);
-    rec[3] = make_float4(lf2, (float)(1.0 / (s1 * s1)), (float)(1.0 / (s2 * s2)), op);
+    rec[2] = make_float4(zf, lf1, lf2, op);
+    rec[3] = make_float4((float)(1.0 / (s1 * s1)), (float)(1.0 / (s2 * s2)), cA, cB);
     rec[4] = make_float4((float)Rc[0], (float)Rc[1], (float)Rc[2], (float)Rc[3]);
     rec[5] = make_float4((float)Rc[4], (float)Rc[5], (float)Rc[6], (float)Rc[7]);
     rec[6] = make_float4((float)Rc[8], r0, r1, r2);
-    rec[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    rec[7] = make_float4(cC, cD, cE, 0.0f);
 }
 
 // Chain rule from the record gradients (rotation as a right perturbation

@@ -33,10 +33,15 @@ constexpr int NGRAD = 14;  // per-(tile, primitive) gradient fields
 enum : int {
     R_PX0 = 0, R_PX1 = 1, R_PY0 = 2, R_PY1 = 3,
     R_U = 4, R_HU = 5, R_V = 6, R_HV = 7,
-    R_KX = 8, R_KY = 9, R_ZC = 10, R_L1 = 11,
-    R_L2 = 12, R_K1 = 13, R_K2 = 14, R_OP = 15,
-    R_ROT = 16, R_RGB = 25
+    R_ZC = 8, R_L1 = 9, R_L2 = 10, R_OP = 11,
+    R_K1 = 12, R_K2 = 13, R_CA = 14, R_CB = 15,
+    R_ROT = 16, R_RGB = 25, R_CC = 28, R_CD = 29, R_CE = 30
 };
+
+// slack of the FP32 conic pre-test (the conic is normalised to -1 at the
+// projected centre and 0 on its boundary, and encloses the support with a
+// relative margin of 2^-10)
+constexpr float CONIC_SLACK = 1e-3f;
 
 // gradient field order within a record gradient (16 floats, 14 used)
 enum : int {
@@ -64,24 +69,43 @@ __device__ inline PixelRay make_ray(int px, int py, const RasterParams &P)
 
 // Geometry of one primitive, as loaded from its record.
 struct Prim {
-    float U, hu, V, hv, kx, ky, Zc, l1, l2, k1, k2, op;
+    float U, hu, V, hv, Zc, l1, l2, op, k1, k2, kx, ky;
     float R[9];  // camera-from-local rotation, row-major R[3 i + j]
 };
 
-__device__ inline void load_prim(const float *w, Prim &p)
+__device__ inline void load_prim(const float *w, const RasterParams &P, Prim &p)
 {
     const float4 a = *reinterpret_cast<const float4 *>(w + 4);
     const float4 b = *reinterpret_cast<const float4 *>(w + 8);
-    const float4 c = *reinterpret_cast<const float4 *>(w + 12);
+    const float2 c = *reinterpret_cast<const float2 *>(w + 12);
     const float4 d = *reinterpret_cast<const float4 *>(w + 16);
     const float4 e = *reinterpret_cast<const float4 *>(w + 20);
     const float f = w[24];
     p.U = a.x; p.hu = a.y; p.V = a.z; p.hv = a.w;
-    p.kx = b.x; p.ky = b.y; p.Zc = b.z; p.l1 = b.w;
-    p.l2 = c.x; p.k1 = c.y; p.k2 = c.z; p.op = c.w;
+    p.Zc = b.x; p.l1 = b.y; p.l2 = b.z; p.op = b.w;
+    p.k1 = c.x; p.k2 = c.y;
+    p.kx = p.Zc * P.ifx;
+    p.ky = p.Zc * P.ify;
     p.R[0] = d.x; p.R[1] = d.y; p.R[2] = d.z; p.R[3] = d.w;
     p.R[4] = e.x; p.R[5] = e.y; p.R[6] = e.z; p.R[7] = e.w;
     p.R[8] = f;
+}
+
+// Offset of the pixel centre from the projected centre, dxp = u + 0.5 - u_c,
+// from the integer + fraction split of u_c (exact to the rounding of a small
+// number), and the conic pre-test: false means the pixel's ray misses the
+// ellipsoid that encloses the support.
+__device__ inline bool conic_offsets(const float *w, const PixelRay &r, float &dxp, float &dyp)
+{
+    const float4 a = *reinterpret_cast<const float4 *>(w + 4);
+    dxp = (r.fpx - a.x) + a.y;
+    dyp = (r.fpy - a.z) + a.w;
+    const float2 c1 = *reinterpret_cast<const float2 *>(w + 14);
+    const float4 c2 = *reinterpret_cast<const float4 *>(w + 28);
+    const float fx_ = __builtin_fmaf(c1.x, dxp, __builtin_fmaf(c1.y, dyp, c2.y));
+    const float fy_ = __builtin_fmaf(c2.x, dyp, c2.z);
+    const float f = __builtin_fmaf(fx_, dxp, __builtin_fmaf(fy_, dyp, -1.0f));
+    return f <= CONIC_SLACK;
 }
 
 // arc-length factor g(u) = l / rho for u = 2 |a| rho (geodesic equation, Sec.
@@ -135,11 +159,12 @@ struct Hit {
 };
 
 // Ray-paraboloid intersection with the near/far selection and the k_sigma
-// geodesic cut-off (Sec. 3.2.1).  Returns true with the accepted hit in H.
-__device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterParams &P, Hit &H)
+// geodesic cut-off (Sec. 3.2.1), from the pixel offsets of conic_offsets.
+// Returns true with the accepted hit in H.
+__device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterParams &P, float dxp, float dyp, Hit &H)
 {
-    H.dxp = (r.fpx - p.U) + p.hu;
-    H.dyp = (r.fpy - p.V) + p.hv;
+    H.dxp = dxp;
+    H.dyp = dyp;
     H.mx = p.kx * H.dxp;
     H.my = p.ky * H.dyp;
     H.m0 = __builtin_fmaf(p.R[0], H.mx, p.R[3] * H.my);

@@ -25,6 +25,7 @@ struct PreprocessArgs {
     uint32_t *depth_key;
     int32_t *rect;
     uint32_t *tiles;
+    double *conic;
 };
 
 struct PreprocessBwdArgs {
@@ -48,6 +49,7 @@ struct SortWorkspace {
     uint64_t *part;                   // scan partials
     uint32_t *hist;                   // [256][nblocks]
     uint32_t *tileT, *primT;          // pair ping-pong [capacity]
+    uint32_t *emit_prim;              // primitive of each emitted pair [capacity]
     size_t bytes;
 };
 
@@ -58,9 +60,11 @@ struct BinSortArgs {
     int64_t n;
     const uint32_t *depth_key, *tiles;
     const int32_t *rect;
+    const double *conic;
+    qgs_camera cam;
     uint32_t *pair_offset;
     int32_t tiles_x, tiles_y;
-    uint32_t *pair_tile, *pair_prim, *ranges, *counters;
+    uint32_t *pair_tile, *pair_prim, *emit_to_sorted, *ranges, *counters;
     uint64_t capacity;
 };
 
@@ -75,8 +79,7 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
 struct RasterArgs {
     const float *records;  // [n][32]
     const uint32_t *pair_prim, *pair_tile, *ranges, *counters;
-    const uint32_t *pair_offset;
-    const int32_t *rect;
+    const uint32_t *pair_offset, *tiles, *emit_to_sorted;
     int32_t tiles_x, tiles_y;
 };
 

@@ -104,12 +104,16 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
             const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
             if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
-            if (!done && px >= x0 && px <= x1 && py >= y0 && py <= y1) {
+            const float *w = reinterpret_cast<const float *>(&s_rec[j * 8]);
+            float dxp, dyp;
+            const bool lane_on = !done && px >= x0 && px <= x1 && py >= y0 && py <= y1 && conic_offsets(w, ray, dxp, dyp);
+            if (__ballot(lane_on) == 0ull) continue;
+            if (lane_on) {
                 Prim p;
-                load_prim(reinterpret_cast<const float *>(&s_rec[j * 8]), p);
+                load_prim(w, P, p);
                 Hit H;
                 ++n_eval;
-                if (ray_hit(p, ray, P, H)) {
+                if (ray_hit(p, ray, P, dxp, dyp, H)) {
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
@@ -363,15 +367,20 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
             const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
             const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
             if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
+            const float *wr = reinterpret_cast<const float *>(&s_rec[j * 8]);
+            float dxp, dyp;
+            const bool lane_on = pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
+                                 conic_offsets(wr, ray, dxp, dyp);
+            if (__ballot(lane_on) == 0ull) continue;
             float gr[NGRAD];
 #pragma unroll
             for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
             bool contrib = false;
-            if (pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1) {
+            if (lane_on) {
                 Prim p;
-                load_prim(reinterpret_cast<const float *>(&s_rec[j * 8]), p);
+                load_prim(wr, P, p);
                 Hit H;
-                if (ray_hit(p, ray, P, H)) {
+                if (ray_hit(p, ray, P, dxp, dyp, H)) {
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
@@ -423,9 +432,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
         for (int slot = tid; slot < nb; slot += BLOCK) {
             const uint32_t pid = s_pid[slot];
             if (DET) {
-                const int32_t *rc = a.rect + 4 * (size_t)pid;
-                const uint32_t local = (uint32_t)(ty - rc[1]) * (uint32_t)(rc[2] - rc[0] + 1) + (uint32_t)(tx - rc[0]);
-                float *dst = pair_scratch + ((size_t)a.pair_offset[pid] + local) * 16;
+                float *dst = pair_scratch + ((size_t)start + lo + slot) * 16;
 #pragma unroll
                 for (int f = 0; f < NGRAD; ++f) {
                     float v = s_acc[0][slot][f];
@@ -446,23 +453,21 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
 }
 
 // deterministic second pass: sum each primitive's per-pair partials in
-// emission order
+// emission order (its pairs are pair_offset[p] ... + tiles[p] - 1 there)
 __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, const uint32_t *pair_offset,
-                                                    const int32_t *rect, int64_t n, float *grad_rec)
+                                                    const uint32_t *tiles, const uint32_t *emit_to_sorted, int64_t n,
+                                                    float *grad_rec)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int32_t *rc = rect + 4 * p;
     float acc[NGRAD];
 #pragma unroll
     for (int f = 0; f < NGRAD; ++f) acc[f] = 0.0f;
-    if (rc[2] >= rc[0] && rc[3] >= rc[1]) {
-        const uint32_t cnt = (uint32_t)((rc[2] - rc[0] + 1) * (rc[3] - rc[1] + 1));
-        const float *src = pair_scratch + (size_t)pair_offset[p] * 16;
-        for (uint32_t k = 0; k < cnt; ++k) {
+    const uint32_t cnt = tiles[p], e0 = pair_offset[p];
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const float *src = pair_scratch + (size_t)emit_to_sorted[e0 + k] * 16;
 #pragma unroll
-            for (int f = 0; f < NGRAD; ++f) acc[f] += src[(size_t)k * 16 + f];
-        }
+        for (int f = 0; f < NGRAD; ++f) acc[f] += src[f];
     }
 #pragma unroll
     for (int f = 0; f < NGRAD; ++f) grad_rec[16 * p + f] = acc[f];
@@ -491,7 +496,8 @@ hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const B
         hipLaunchKernelGGL(k_render_bwd<true>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
         if (n_prims > 0)
             hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
-                               (const float *)pair_scratch, a.pair_offset, a.rect, n_prims, grad_rec);
+                               (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
+                               grad_rec);
     } else {
         hipLaunchKernelGGL(k_render_bwd<false>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
     }

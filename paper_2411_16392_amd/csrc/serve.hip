@@ -26,11 +26,12 @@
 
 #include "qgs.h"
 #include "qgs_internal.hpp"
+#include "serve_pool.hpp"
 
 namespace qgs {
 namespace {
 
-size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t a256(size_t x) { return pool_align(x); }
 uint64_t cdiv64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // bytes one request's lists and tile-sort temporaries take in the pool
@@ -38,54 +39,8 @@ size_t list_bytes(uint64_t pairs)
 {
     const uint64_t c = pairs > 0 ? pairs : 1;
     const uint64_t nb = cdiv64(c, 4096) + 1;
-    return 4 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, 4096) + 64));
+    return 6 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, 4096) + 64));
 }
-
-// first-fit allocator over [0, size)
-struct Pool {
-    std::map<size_t, size_t> free_;  // offset -> length
-    size_t size = 0, used = 0, peak = 0;
-    void init(size_t n)
-    {
-        size = n;
-        free_.clear();
-        free_[0] = n;
-    }
-    bool alloc(size_t bytes, size_t &off)
-    {
-        bytes = a256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                off = it->first;
-                const size_t rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                used += bytes;
-                if (used > peak) peak = used;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = a256(bytes);
-        used -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 enum Phase { IDLE = 0, COUNTING = 1, WAITING = 2, RENDERING = 3 };
 
@@ -105,6 +60,7 @@ struct Slot {
     void *records = nullptr;
     uint32_t *depth_key = nullptr, *tiles = nullptr, *pair_offset = nullptr;
     int32_t *rect = nullptr;
+    double *conic = nullptr;
     uint32_t *dkA = nullptr, *dvA = nullptr, *dkB = nullptr, *dvB = nullptr, *hist = nullptr;
     uint64_t *off = nullptr, *part = nullptr;
     uint32_t *ranges = nullptr, *counters = nullptr, *counters_host = nullptr;
@@ -175,6 +131,8 @@ BinSortArgs sort_args(qgs_server *s, Slot &sl, const qgs_camera &cam)
     a.depth_key = sl.depth_key;
     a.tiles = sl.tiles;
     a.rect = sl.rect;
+    a.conic = sl.conic;
+    a.cam = cam;
     a.pair_offset = sl.pair_offset;
     a.tiles_x = (cam.width + 15) / 16;
     a.tiles_y = (cam.height + 15) / 16;
@@ -202,6 +160,7 @@ hipError_t issue_count(qgs_server *s, Slot &sl)
     pa.near_plane = s->cfg.opts.near_plane;
     pa.k_sigma = s->cfg.opts.k_sigma;
     pa.records = sl.records; pa.depth_key = sl.depth_key; pa.rect = sl.rect; pa.tiles = sl.tiles;
+    pa.conic = sl.conic;
     hipError_t e = launch_preprocess(pa, sl.stream);
     if (e != hipSuccess) return e;
     BinSortArgs a = sort_args(s, sl, r.cam);
@@ -227,14 +186,17 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     };
     uint32_t *pair_tile = (uint32_t *)take(4 * c);
     uint32_t *pair_prim = (uint32_t *)take(4 * c);
+    uint32_t *emit_to_sorted = (uint32_t *)take(4 * c);
     SortWorkspace w = fixed_ws(sl);
     w.tileT = (uint32_t *)take(4 * c);
     w.primT = (uint32_t *)take(4 * c);
+    w.emit_prim = (uint32_t *)take(4 * c);
     w.hist = (uint32_t *)take(4 * 256 * nb);
     w.part = (uint64_t *)take(8 * (cdiv64(256 * nb, 4096) + 64));
     BinSortArgs a = sort_args(s, sl, r.cam);
     a.pair_tile = pair_tile;
     a.pair_prim = pair_prim;
+    a.emit_to_sorted = emit_to_sorted;
     a.capacity = c;
     hipError_t e = bin_sort_phase2(a, w, r.pairs, sl.stream);
     if (e != hipSuccess) return e;
@@ -242,7 +204,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     ra.records = (const float *)sl.records;
     ra.pair_prim = pair_prim; ra.pair_tile = pair_tile;
     ra.ranges = sl.ranges; ra.counters = sl.counters;
-    ra.pair_offset = sl.pair_offset; ra.rect = sl.rect;
+    ra.pair_offset = sl.pair_offset; ra.tiles = sl.tiles; ra.emit_to_sorted = emit_to_sorted;
     ra.tiles_x = a.tiles_x; ra.tiles_y = a.tiles_y;
     FwdOut fo{};
     fo.color = r.out; fo.depth = sl.depth; fo.normal = sl.normal; fo.T_final = sl.T; fo.last = sl.last;
@@ -427,6 +389,8 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
         sl.depth_key = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 16 * n)) != hipSuccess) break;
         sl.rect = (int32_t *)p;
+        if ((e = dev_alloc(s, &p, 64 * n)) != hipSuccess) break;
+        sl.conic = (double *)p;
         if ((e = dev_alloc(s, &p, 4 * n)) != hipSuccess) break;
         sl.tiles = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 4 * n)) != hipSuccess) break;
@@ -468,7 +432,7 @@ qgs_status qgs_serve_submit(qgs_server *s, const qgs_camera *cam, float *out_rgb
 {
     if (!s || !cam || !out_rgb) return QGS_ERR_INVALID_ARG;
     if (cam->width <= 0 || cam->height <= 0 || cam->width > s->cfg.max_width || cam->height > s->cfg.max_height ||
-        cam->fx == 0.0f || cam->fy == 0.0f)
+        !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
         return QGS_ERR_INVALID_ARG;
     auto r = std::make_shared<Req>();
     r->cam = *cam;

@@ -77,8 +77,10 @@ class FrameState:
     rect: torch.Tensor
     tiles: torch.Tensor
     pair_offset: torch.Tensor
+    conic: torch.Tensor
     pair_tile: torch.Tensor
     pair_prim: torch.Tensor
+    emit_to_sorted: torch.Tensor
     ranges: torch.Tensor
     counters: torch.Tensor
     capacity: int
@@ -93,11 +95,13 @@ class FrameState:
         p = L.QgsPrimBuf()
         p.records, p.depth_key, p.rect = _ptr(self.records), _ptr(self.depth_key), _ptr(self.rect)
         p.tiles, p.pair_offset, p.n = _ptr(self.tiles), _ptr(self.pair_offset), self.n
+        p.conic = _ptr(self.conic)
         return p
 
     def lists(self) -> L.QgsTileLists:
         l = L.QgsTileLists()
         l.pair_tile, l.pair_prim = _ptr(self.pair_tile), _ptr(self.pair_prim)
+        l.emit_to_sorted = _ptr(self.emit_to_sorted)
         l.ranges, l.counters, l.capacity = _ptr(self.ranges), _ptr(self.counters), self.capacity
         return l
 
@@ -136,6 +140,7 @@ class Renderer:
         st.capacity = int(cap)
         st.pair_tile = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
         st.pair_prim = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        st.emit_to_sorted = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
 
     def preprocess(self, scene_t: dict, cam) -> FrameState:
         n = int(scene_t["center"].shape[0])
@@ -150,7 +155,8 @@ class Renderer:
             rect=torch.empty(max(n, 1) * 4, dtype=torch.int32, device=dev),
             tiles=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
             pair_offset=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
-            pair_tile=None, pair_prim=None,
+            conic=torch.empty(max(n, 1) * 8, dtype=torch.float64, device=dev),
+            pair_tile=None, pair_prim=None, emit_to_sorted=None,
             ranges=torch.empty(2 * ntiles, dtype=torch.int32, device=dev),
             counters=torch.zeros(8, dtype=torch.int32, device=dev),
             capacity=0, num_pairs=None,

@@ -52,12 +52,17 @@ def check_keys(scene, cam, st):
     live = ks["rect_px"][:, 2] >= ks["rect_px"][:, 0]
     px = np.stack([rec[:, 0], rec[:, 2], rec[:, 1], rec[:, 3]], 1)  # x0, y0, x1, y1
     assert np.array_equal(px[live], ks["rect_px"][live]), "pixel rects"
+    conic = to_np(st.conic).reshape(-1, 8)[:n]
+    assert np.array_equal(conic[:, :6].view(np.uint64), ks["conic"].view(np.uint64)), "conic coefficients"
+    assert np.array_equal(conic[:, 6] != 0, ks["conic_ok"] != 0), "conic validity"
     return ks
 
 
 def check_lists(ks, cam, st):
-    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+    keys_, prims, ranges, seq = oracle.bin_sort(ks, cam, with_seq=True)
     npairs = len(prims)
+    e2s = to_np(st.emit_to_sorted).view(np.uint32)[:npairs]
+    assert np.array_equal(e2s[seq], np.arange(npairs, dtype=np.uint32)), "emission -> sorted positions"
     assert st.num_pairs is None or st.num_pairs == npairs
     cnt = to_np(st.counters).view(np.uint32)
     assert cnt[0] == npairs and cnt[1] == 0

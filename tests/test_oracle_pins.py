@@ -473,9 +473,20 @@ def test_backward_matches_finite_differences(seed):
 # key stage: conservative screen rectangles and the stable key sort
 # --------------------------------------------------------------------------
 
-def test_rectangles_contain_the_support():
+PER_PRIM = ("culled", "depth_bits", "rect_px", "rect_tile", "tiles", "conic", "conic_ok")
+
+
+def _subset_keys(ks, idx):
+    out = dict(ks)
+    for key in PER_PRIM:
+        out[key] = ks[key][idx]
+    return out
+
+
+def test_emitted_tiles_contain_the_support():
     """Brute force: render every primitive alone (every accepted hit blended)
-    and check that each touched pixel lies in its rectangle."""
+    and check that each touched pixel lies in its pixel rectangle and in one of
+    the tiles emitted for it."""
     rng = np.random.default_rng(21)
     n = 160
     sc = scenes.scene_uniform_cube(n, 21, scale_range=(0.02, 0.4), curv_lim=5.0)
@@ -484,13 +495,18 @@ def test_rectangles_contain_the_support():
     sc.center[10:20, 0] = rng.uniform(1.5, 2.5, 10)
     cam = scenes.look_at((0.0, 0.0, -3.0), width=96, height=80, f=80)
     ks = oracle.keys(sc, cam)
+    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+    emitted = {}
+    for k, p in zip(keys_, prims):
+        emitted.setdefault(int(p), set()).add(int(k >> np.uint64(32)))
+    for p in range(n):
+        assert ks["tiles"][p] == len(emitted.get(p, ()))
     opts = dict(alpha_min=1e-30)
     n_checked = 0
     areas = []
     for p in range(n):
         one = sc.subset([p])
-        k1 = {key: v[[p]] for key, v in ks.items()}
-        r = oracle.render(one, cam, opts=opts, key_stage=k1, nthreads=4)
+        r = oracle.render(one, cam, opts=opts, key_stage=_subset_keys(ks, [p]), nthreads=4)
         touched = np.argwhere(r["n_blend"] > 0)
         x0, y0, x1, y1 = ks["rect_px"][p]
         if len(touched) == 0:
@@ -499,11 +515,40 @@ def test_rectangles_contain_the_support():
         n_checked += 1
         assert touched[:, 1].min() >= x0 and touched[:, 1].max() <= x1, p
         assert touched[:, 0].min() >= y0 and touched[:, 0].max() <= y1, p
-        areas.append(((x1 - x0 + 1) * (y1 - y0 + 1), len(touched)))
+        tiles_hit = {int((v // 16) * cam.tiles_x + u // 16) for v, u in touched}
+        assert tiles_hit <= emitted[p], (p, tiles_hit - emitted[p])
+        areas.append(((x1 - x0 + 1) * (y1 - y0 + 1), len(touched), len(emitted[p]), len(tiles_hit)))
     assert n_checked > 80
-    # not trivially the full screen
     a = np.array(areas)
+    # not trivially the full screen, and the conic test removes tiles
     assert np.median(a[:, 0] / a[:, 1]) < 12.0
+    assert a[:, 2].sum() < sum(((ks["rect_tile"][p, 2] - ks["rect_tile"][p, 0] + 1) *
+                                (ks["rect_tile"][p, 3] - ks["rect_tile"][p, 1] + 1)) for p in range(n)
+                               if ks["rect_tile"][p, 2] >= ks["rect_tile"][p, 0])
+
+
+def test_emitted_tiles_contain_the_support_headline_sample():
+    # 500K-quadric view: primitives sampled across the scene, each rendered
+    # alone over its pixel rectangle
+    cfg = scenes.make_config(2, n_views=1)
+    cam = cfg.cameras[0]
+    ks = oracle.keys(cfg.scene, cam)
+    live = np.nonzero((ks["culled"] == 0) & (ks["tiles"] > 0))[0]
+    rng = np.random.default_rng(5)
+    pick = rng.choice(live, 60, replace=False)
+    opts = dict(alpha_min=1e-30)
+    for p in pick:
+        one = cfg.scene.subset([p])
+        k1 = _subset_keys(ks, [p])
+        x0, y0, x1, y1 = ks["rect_px"][p]
+        win = (int(x0), int(y0), int(x1 - x0 + 1), int(y1 - y0 + 1))
+        r = oracle.render(one, cam, opts=opts, key_stage=k1, window=win, nthreads=4)
+        touched = np.argwhere(r["n_blend"] > 0)
+        _, prims1, _ = oracle.bin_sort(k1, cam)
+        keys1, _, _ = oracle.bin_sort(k1, cam)
+        emitted = {int(k >> np.uint64(32)) for k in keys1}
+        tiles_hit = {int(((v + y0) // 16) * cam.tiles_x + (u + x0) // 16) for v, u in touched}
+        assert tiles_hit <= emitted
 
 
 def test_tile_rect_matches_pixel_rect():
@@ -512,7 +557,7 @@ def test_tile_rect_matches_pixel_rect():
     rp, rt = ks["rect_px"], ks["rect_tile"]
     live = rp[:, 2] >= rp[:, 0]
     assert np.array_equal(rt[live], rp[live] // 16)
-    assert np.array_equal(ks["tiles"][live], (rt[live, 2] - rt[live, 0] + 1) * (rt[live, 3] - rt[live, 1] + 1))
+    assert np.all(ks["tiles"][live] <= (rt[live, 2] - rt[live, 0] + 1) * (rt[live, 3] - rt[live, 1] + 1))
     assert np.all(ks["tiles"][~live] == 0)
     # depth key is the FP32 camera-space depth of the centre
     cam = cfg.cameras[0]
@@ -521,12 +566,31 @@ def test_tile_rect_matches_pixel_rect():
     assert np.array_equal(ks["depth_bits"][act], z[act].view(np.uint32))
 
 
+def _py_tile_hit(C, tx, ty, cam):
+    """Minimum of the convex quadratic f over the tile's (widened) rectangle of
+    pixel centres, by brute force on a fine grid plus the exact minimiser."""
+    x0 = (max(tx * 16, 0) + 0.5 - 1 / 64 - np.float32(cam.cx)) / np.float32(cam.fx)
+    x1 = (min(tx * 16 + 15, cam.width - 1) + 0.5 + 1 / 64 - np.float32(cam.cx)) / np.float32(cam.fx)
+    y0 = (max(ty * 16, 0) + 0.5 - 1 / 64 - np.float32(cam.cy)) / np.float32(cam.fy)
+    y1 = (min(ty * 16 + 15, cam.height - 1) + 0.5 + 1 / 64 - np.float32(cam.cy)) / np.float32(cam.fy)
+    a, b, c, d, e, g = C
+    H = np.array([[a, b], [b, c]])
+    m = np.linalg.solve(H, -np.array([d, e]))
+    if x0 <= m[0] <= x1 and y0 <= m[1] <= y1:
+        return True
+    f = lambda x, y: a * x * x + 2 * b * x * y + c * y * y + 2 * d * x + 2 * e * y + g
+    ts = np.linspace(0, 1, 4001)
+    best = min(f(x0 + 0 * ts, y0 + (y1 - y0) * ts).min(), f(x1 + 0 * ts, y0 + (y1 - y0) * ts).min(),
+               f(x0 + (x1 - x0) * ts, y0 + 0 * ts).min(), f(x0 + (x1 - x0) * ts, y1 + 0 * ts).min())
+    return best <= 0
+
+
 def test_bin_sort_is_stable_key_sort():
     cfg = scenes.make_config(0)
     cam = cfg.cameras[0]
     ks = oracle.keys(cfg.scene, cam)
     keys_, prims, ranges = oracle.bin_sort(ks, cam)
-    # independent emission + numpy stable sort
+    # independent emission (the conic test re-done in Python) + numpy stable sort
     em_key, em_prim = [], []
     for p in range(cfg.scene.n):
         x0, y0, x1, y1 = ks["rect_tile"][p]
@@ -534,6 +598,8 @@ def test_bin_sort_is_stable_key_sort():
             continue
         for ty in range(y0, y1 + 1):
             for tx in range(x0, x1 + 1):
+                if ks["conic_ok"][p] and not _py_tile_hit(ks["conic"][p], tx, ty, cam):
+                    continue
                 em_key.append((ty * cam.tiles_x + tx) << 32 | int(ks["depth_bits"][p]))
                 em_prim.append(p)
     em_key = np.array(em_key, np.uint64)
