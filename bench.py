@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -86,6 +88,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     q = args.quiet
+
+    if args.copy_probe:
+        # known traffic: 256 MiB read + 256 MiB written per launch
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t0 = time.time()
     cfg = scenes.make_config(2, n_views=args.views)

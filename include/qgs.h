@@ -132,6 +132,9 @@ typedef struct qgs_prim_buf {
  *                        indexed by emission order (primitive p's pairs are
  *                        pair_offset[p] ... pair_offset[p] + tiles[p] - 1)
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
+ *  tile_order            [tiles_x * tiles_y] tiles by decreasing list length
+ *                        (log2 buckets): the order in which the rasterizer's
+ *                        workgroups take tiles, so the longest start first
  *  counters              [8] uint32: [0] number of pairs, [1] overflow flag
  *                        (1 when [0] > capacity: lists and ranges are then empty
  *                        and the caller must grow and call again); with
@@ -146,6 +149,7 @@ typedef struct qgs_tile_lists {
     uint32_t *pair_prim;
     uint32_t *emit_to_sorted;
     uint32_t *ranges;
+    uint32_t *tile_order;
     uint32_t *counters;
     uint64_t capacity;
 } qgs_tile_lists;

@@ -52,7 +52,7 @@ class QgsPrimBuf(ctypes.Structure):
 
 class QgsTileLists(ctypes.Structure):
     _fields_ = [("pair_tile", c_void_p), ("pair_prim", c_void_p), ("emit_to_sorted", c_void_p),
-                ("ranges", c_void_p), ("counters", c_void_p), ("capacity", c_uint64)]
+                ("ranges", c_void_p), ("tile_order", c_void_p), ("counters", c_void_p), ("capacity", c_uint64)]
 
 
 class QgsImages(ctypes.Structure):

@@ -96,6 +96,7 @@ RasterArgs raster_args(const qgs_prim_buf *prims, const qgs_tile_lists *lists, c
     a.pair_prim = lists->pair_prim;
     a.pair_tile = lists->pair_tile;
     a.ranges = lists->ranges;
+    a.tile_order = lists->tile_order;
     a.counters = lists->counters;
     a.pair_offset = prims->pair_offset;
     a.tiles = prims->tiles;
@@ -203,6 +204,7 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
     a.pair_prim = lists->pair_prim;
     a.emit_to_sorted = lists->emit_to_sorted;
     a.ranges = lists->ranges;
+    a.tile_order = lists->tile_order;
     a.counters = lists->counters;
     a.capacity = lists->capacity;
     hipStream_t s = (hipStream_t)stream;

@@ -355,6 +355,34 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt,
     if (i == n - 1 || tile[i + 1] != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
 }
 
+// Tiles in decreasing order of list length (buckets of floor(log2(len + 1)),
+// largest first; order inside a bucket is arbitrary): the rasterizer's
+// workgroups take tiles in this order so the longest lists start first.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *ranges, uint32_t ntiles, uint32_t *order)
+{
+    __shared__ uint32_t cnt[32], pos[32];
+    const int tid = threadIdx.x;
+    if (tid < 32) cnt[tid] = 0;
+    __syncthreads();
+    for (uint32_t t = tid; t < ntiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        atomicAdd(&cnt[__clz((int)(len + 1u))], 1u);  // 31 - floor(log2(len + 1)): longest first
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < 32; ++b) {
+            pos[b] = run;
+            run += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < ntiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        order[atomicAdd(&pos[__clz((int)(len + 1u))], 1u)] = t;
+    }
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
@@ -420,6 +448,9 @@ hipError_t bin_sort_phase1(const BinSortArgs &a, const SortWorkspace &ws, hipStr
     return hipGetLastError();
 }
 
+static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, int passes,
+                                   uint64_t ntiles, hipStream_t stream);
+
 hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, hipStream_t stream)
 {
     const int64_t n = a.n;
@@ -430,7 +461,21 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
     hipError_t e = launch_fill_u32(a.ranges, 0u, 2 * ntiles, stream);
     if (e != hipSuccess) return e;
     if (bound > a.capacity) bound = a.capacity;
-    if (n <= 0 || bound == 0) return hipSuccess;
+    if (n > 0 && bound > 0) e = emit_sort_ranges(a, ws, bound, passes, ntiles, stream);
+    if (e != hipSuccess) return e;
+    // the tile order is written on every path: the rasterizer reads it for
+    // every workgroup, also when there are no pairs
+    if (a.tile_order)
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, (const uint32_t *)a.ranges, (uint32_t)ntiles,
+                           a.tile_order);
+    return hipGetLastError();
+}
+
+static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, int passes,
+                                   uint64_t ntiles, hipStream_t stream)
+{
+    const int64_t n = a.n;
+    hipError_t e = hipSuccess;
     // emit into the buffer that makes the final pass land in the caller's lists
     uint32_t *et = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
     uint32_t *ep = (passes % 2 == 0) ? a.pair_prim : ws.primT;

@@ -64,7 +64,7 @@ struct BinSortArgs {
     qgs_camera cam;
     uint32_t *pair_offset;
     int32_t tiles_x, tiles_y;
-    uint32_t *pair_tile, *pair_prim, *emit_to_sorted, *ranges, *counters;
+    uint32_t *pair_tile, *pair_prim, *emit_to_sorted, *ranges, *tile_order, *counters;
     uint64_t capacity;
 };
 
@@ -78,7 +78,7 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
 
 struct RasterArgs {
     const float *records;  // [n][32]
-    const uint32_t *pair_prim, *pair_tile, *ranges, *counters;
+    const uint32_t *pair_prim, *pair_tile, *ranges, *tile_order, *counters;
     const uint32_t *pair_offset, *tiles, *emit_to_sorted;
     int32_t tiles_x, tiles_y;
 };

@@ -80,7 +80,8 @@ __device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int 
 __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
 {
     __shared__ float4 s_rec[BLOCK * 8];
-    const int tile = blockIdx.x;
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
@@ -307,7 +308,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     __shared__ float s_acc[NACC][NB][NGRAD];
     __shared__ uint32_t s_maxlast;
 
-    const int tile = blockIdx.x;
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;

@@ -63,7 +63,7 @@ struct Slot {
     double *conic = nullptr;
     uint32_t *dkA = nullptr, *dvA = nullptr, *dkB = nullptr, *dvB = nullptr, *hist = nullptr;
     uint64_t *off = nullptr, *part = nullptr;
-    uint32_t *ranges = nullptr, *counters = nullptr, *counters_host = nullptr;
+    uint32_t *ranges = nullptr, *tile_order = nullptr, *counters = nullptr, *counters_host = nullptr;
     float *depth = nullptr, *normal = nullptr, *T = nullptr;
     uint32_t *last = nullptr;
     std::shared_ptr<Req> req;
@@ -137,6 +137,7 @@ BinSortArgs sort_args(qgs_server *s, Slot &sl, const qgs_camera &cam)
     a.tiles_x = (cam.width + 15) / 16;
     a.tiles_y = (cam.height + 15) / 16;
     a.ranges = sl.ranges;
+    a.tile_order = sl.tile_order;
     a.counters = sl.counters;
     return a;
 }
@@ -203,7 +204,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     RasterArgs ra{};
     ra.records = (const float *)sl.records;
     ra.pair_prim = pair_prim; ra.pair_tile = pair_tile;
-    ra.ranges = sl.ranges; ra.counters = sl.counters;
+    ra.ranges = sl.ranges; ra.tile_order = sl.tile_order; ra.counters = sl.counters;
     ra.pair_offset = sl.pair_offset; ra.tiles = sl.tiles; ra.emit_to_sorted = emit_to_sorted;
     ra.tiles_x = a.tiles_x; ra.tiles_y = a.tiles_y;
     FwdOut fo{};
@@ -408,6 +409,8 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
         sl.hist = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 8 * ntiles)) != hipSuccess) break;
         sl.ranges = (uint32_t *)p;
+        if ((e = dev_alloc(s, &p, 4 * ntiles)) != hipSuccess) break;
+        sl.tile_order = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 32)) != hipSuccess) break;
         sl.counters = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 4 * 6 * px)) != hipSuccess) break;

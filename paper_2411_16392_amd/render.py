@@ -82,6 +82,7 @@ class FrameState:
     pair_prim: torch.Tensor
     emit_to_sorted: torch.Tensor
     ranges: torch.Tensor
+    tile_order: torch.Tensor
     counters: torch.Tensor
     capacity: int
     num_pairs: int | None
@@ -103,6 +104,7 @@ class FrameState:
         l.pair_tile, l.pair_prim = _ptr(self.pair_tile), _ptr(self.pair_prim)
         l.emit_to_sorted = _ptr(self.emit_to_sorted)
         l.ranges, l.counters, l.capacity = _ptr(self.ranges), _ptr(self.counters), self.capacity
+        l.tile_order = _ptr(self.tile_order)
         return l
 
     def images(self) -> L.QgsImages:
@@ -158,6 +160,7 @@ class Renderer:
             conic=torch.empty(max(n, 1) * 8, dtype=torch.float64, device=dev),
             pair_tile=None, pair_prim=None, emit_to_sorted=None,
             ranges=torch.empty(2 * ntiles, dtype=torch.int32, device=dev),
+            tile_order=torch.empty(ntiles, dtype=torch.int32, device=dev),
             counters=torch.zeros(8, dtype=torch.int32, device=dev),
             capacity=0, num_pairs=None,
             color=torch.empty((3, H, W), dtype=torch.float32, device=dev),

@@ -59,16 +59,30 @@ def check_keys(scene, cam, st):
 
 
 def check_lists(ks, cam, st):
-    keys_, prims, ranges, seq = oracle.bin_sort(ks, cam, with_seq=True)
+    keys_, prims, ranges = oracle.bin_sort(ks, cam)
     npairs = len(prims)
+    # emit_to_sorted: primitive p's pairs (row-major tiles) start at
+    # pair_offset[p] in emission order and land at its sorted positions
     e2s = to_np(st.emit_to_sorted).view(np.uint32)[:npairs]
-    assert np.array_equal(e2s[seq], np.arange(npairs, dtype=np.uint32)), "emission -> sorted positions"
+    off = to_np(st.pair_offset).view(np.uint32)[:len(ks["tiles"])]
+    tile = (keys_ >> np.uint64(32)).astype(np.int64)
+    order = np.lexsort((tile, prims.astype(np.int64)))   # by primitive, then tile
+    want = np.empty(npairs, np.uint32)
+    first = np.searchsorted(prims[order], prims[order], side="left")
+    k = np.arange(npairs) - first
+    want[(off[prims[order]].astype(np.int64) + k)] = order.astype(np.uint32)
+    assert np.array_equal(e2s, want), "emission -> sorted positions"
     assert st.num_pairs is None or st.num_pairs == npairs
     cnt = to_np(st.counters).view(np.uint32)
     assert cnt[0] == npairs and cnt[1] == 0
     assert np.array_equal(to_np(st.pair_prim).view(np.uint32)[:npairs], prims), "sorted primitive ids"
     assert np.array_equal(to_np(st.pair_tile).view(np.uint32)[:npairs], (keys_ >> np.uint64(32)).astype(np.uint32))
     assert np.array_equal(to_np(st.ranges).view(np.uint32).reshape(-1, 2), ranges), "tile ranges"
+    order = to_np(st.tile_order).view(np.uint32)
+    assert np.array_equal(np.sort(order), np.arange(len(ranges), dtype=np.uint32)), "tile order is a permutation"
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)[order]
+    bucket = np.floor(np.log2(lens + 1.0)).astype(np.int64)
+    assert np.all(np.diff(bucket) <= 0), "longest lists first"
     return npairs
 
 
