@@ -26,7 +26,26 @@
 
 #pragma clang fp contract(off)
 
+// Records staged per LDS batch (forward, backward) and the minimum number of
+// waves per SIMD the compiler is asked to fit (0: no request).
+#ifndef QGS_FWD_BATCH
+#define QGS_FWD_BATCH 256
+#endif
+#ifndef QGS_BWD_BATCH
+#define QGS_BWD_BATCH 256
+#endif
+#ifndef QGS_FWD_MIN_WAVES
+#define QGS_FWD_MIN_WAVES 0
+#endif
+#ifndef QGS_BWD_MIN_WAVES
+#define QGS_BWD_MIN_WAVES 0
+#endif
+
 namespace qgs {
+
+constexpr int FWD_BATCH = QGS_FWD_BATCH;
+constexpr int BWD_BATCH = QGS_BWD_BATCH;
+static_assert(FWD_BATCH % 32 == 0 && FWD_BATCH <= 256 && BWD_BATCH % 32 == 0 && BWD_BATCH <= 256, "batch size");
 
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ inline float dpp_f(float v)
@@ -59,12 +78,13 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
+template <int NBATCH>
 __device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int nb, float4 *s_rec, uint32_t *s_pid)
 {
     const int tid = threadIdx.x;
     const float4 *recs = reinterpret_cast<const float4 *>(a.records);
 #pragma unroll
-    for (int r = 0; r < BLOCK * 8 / BLOCK; ++r) {
+    for (int r = 0; r < NBATCH * 8 / BLOCK; ++r) {
         const int slot = r * (BLOCK / 8) + (tid >> 3), k = tid & 7;
         if (slot < nb) {
             const uint32_t pid = a.pair_prim[list_begin + slot];
@@ -77,9 +97,13 @@ __device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int 
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+#if QGS_FWD_MIN_WAVES > 0
+__global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
+#else
 __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
+#endif
 {
-    __shared__ float4 s_rec[BLOCK * 8];
+    __shared__ float4 s_rec[FWD_BATCH * 8];
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
@@ -94,10 +118,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
     bool done = !inside;
 
-    for (uint32_t b0 = start; b0 < end; b0 += BLOCK) {
+    for (uint32_t b0 = start; b0 < end; b0 += FWD_BATCH) {
         if (__syncthreads_count(!done) == 0) break;
-        const int nb = (int)min((uint32_t)BLOCK, end - b0);
-        load_batch(a, b0, nb, s_rec, nullptr);
+        const int nb = (int)min((uint32_t)FWD_BATCH, end - b0);
+        load_batch<FWD_BATCH>(a, b0, nb, s_rec, nullptr);
         __syncthreads();
         bool wave_alive = __ballot(!done) != 0ull;
         for (int j = 0; j < nb && wave_alive; ++j) {
@@ -298,10 +322,15 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
 }
 
 template <bool DET>
+#if QGS_BWD_MIN_WAVES > 0
+__global__ __launch_bounds__(BLOCK, QGS_BWD_MIN_WAVES) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
+                                                                         float *grad_rec, float *pair_scratch)
+#else
 __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in, float *grad_rec,
                                                       float *pair_scratch)
+#endif
 {
-    constexpr int NB = DET ? 64 : BLOCK;
+    constexpr int NB = DET ? 64 : BWD_BATCH;
     constexpr int NACC = DET ? 4 : 1;
     __shared__ float4 s_rec[NB * 8];
     __shared__ uint32_t s_pid[NB];
