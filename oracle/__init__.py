@@ -28,8 +28,8 @@ DEFAULT_OPTS = dict(near=0.2, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99
 # Margin scales for the discrete decisions: a pixel whose relative distance to a
 # decision boundary is below its scale is reported with margin < 1.
 DEFAULT_DELTA = dict(A=1e-3, D=1e-6, near=1e-5, E=1e-5, alpha_min=1e-4, T=1e-4,
-                     normal=1e-4, clamp=1e-4)
-_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp"]
+                     normal=1e-4, clamp=1e-4, median=1e-5)
+_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median"]
 
 
 def build() -> str:
@@ -56,7 +56,7 @@ def _lib():
         L.oracle_bin_sort.restype = i64
         L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                     i32, i32, i32, i32, i32,
-                                    P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+                                    P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.oracle_render.restype = i64
         L.oracle_gfun.argtypes = [f64]
         L.oracle_gfun.restype = f64
@@ -164,8 +164,11 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     (used for finite differences; order and culling still come from the key
     stage of the FP32 scene).  cam_vec64: optional FP64 camera vector
     {R[9], t[3], fx, fy, cx, cy} overriding the FP32 one.  dL: optional (dcolor[3,H,W], ddepth[H,W],
-    dnormal[3,H,W]) over the full view; runs the backward.
-    Returns a dict of window-sized FP64 maps and, with dL, parameter gradients.
+    dnormal[3,H,W]) or (..., dcurvature[H,W], dmedian[H,W], ddistortion[H,W]) over the full view;
+    runs the backward.
+    Returns a dict of window-sized FP64 maps (colour, depth, normal, curvature, median depth,
+    depth distortion, final transmittance, blend count, decision margin) and, with dL,
+    parameter gradients.
     """
     o = opts_array(opts)
     dv = delta_array(delta)
@@ -178,25 +181,30 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     camv = cam_array(cam, np.float64) if cam_vec64 is None else _f64(cam_vec64)
     color = np.zeros((3, h, w)); depth = np.zeros((h, w)); normal = np.zeros((3, h, w))
     T = np.zeros((h, w)); nb = np.zeros((h, w), np.int32); margin = np.zeros((h, w))
+    curvature = np.zeros((h, w)); median = np.zeros((h, w)); dist = np.zeros((h, w))
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     grads = None
-    gp = [None] * 9
+    gp = [None] * 12
     if dL is not None:
         dc = _f64(dL[0][:, y0:y0 + h, x0:x0 + w])
         dd = _f64(dL[1][y0:y0 + h, x0:x0 + w])
         dn = _f64(dL[2][:, y0:y0 + h, x0:x0 + w])
+        extra = [_f64(m[y0:y0 + h, x0:x0 + w]) if m is not None else None for m in
+                 (list(dL[3:6]) + [None] * 3)[:3]]
         grads = dict(center=np.zeros((n, 3)), quat=np.zeros((n, 4)), scale=np.zeros((n, 2)),
                      curv=np.zeros((n, 2)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
-        gp = [_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(grads[k]) for k in
-                                               ("center", "quat", "scale", "curv", "opacity", "rgb")]
+        gp = ([_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(m) if m is not None else None for m in extra] +
+              [_ptr(grads[k]) for k in ("center", "quat", "scale", "curv", "opacity", "rgb")])
     ev = _lib().oracle_render(n, *[_ptr(a) for a in arrs], _ptr(key_stage["culled"]), _ptr(key_stage["depth_bits"]),
                               _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv),
                               x0, y0, w, h, int(nthreads),
-                              _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin), *gp)
+                              _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin),
+                              _ptr(curvature), _ptr(median), _ptr(dist), *gp)
     if ev < 0:
         raise ValueError("bad window")
-    out = dict(color=color, depth=depth, normal=normal, T_final=T, n_blend=nb, margin=margin, evals=int(ev))
+    out = dict(color=color, depth=depth, normal=normal, curvature=curvature, median_depth=median,
+               distortion=dist, T_final=T, n_blend=nb, margin=margin, evals=int(ev))
     if grads is not None:
         out["grads"] = grads
     return out
@@ -204,9 +212,9 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
 
 def ray_hit(center, quat, scale, curv, cam_vec64, dcam, opts=None):
     """One ray against one primitive.  Returns a dict of the hit quantities."""
-    out = np.zeros(14)
+    out = np.zeros(15)
     o = opts_array(opts)
     _lib().oracle_ray_hit(_ptr(_f64(center)), _ptr(_f64(quat)), _ptr(_f64(scale)), _ptr(_f64(curv)),
                           _ptr(_f64(cam_vec64)), _ptr(_f64(dcam)), _ptr(o), _ptr(out))
     return dict(ok=bool(out[0]), linear=bool(out[1]), t=out[2], x=out[3], y=out[4], z=out[5], E=out[6], G=out[7],
-                A=out[8], B=out[9], C=out[10], normal=out[11:14].copy())
+                A=out[8], B=out[9], C=out[10], normal=out[11:14].copy(), K=out[14])

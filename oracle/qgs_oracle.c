@@ -339,7 +339,11 @@ double oracle_gfun(double u);
 enum { O_NEAR = 0, O_K, O_AMIN, O_AMAX, O_TEPS, O_AEPS, O_BG };
 /* margin scales: |A| vs A_eps, D vs 0, near test, E vs k^2, alpha_min, T_eps,
    normal facing, alpha clamp */
-enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_COUNT };
+enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_MED, M_COUNT };
+
+/* per-pixel channels: colour[3], depth, normal[3], curvature, median depth,
+   depth distortion */
+enum { CH_DEPTH = 3, CH_N = 4, CH_K = 7, CH_MED = 8, CH_DIST = 9, NCH = 10 };
 
 typedef struct {
     double Rc[9];  /* camera-from-local rotation: columns are the local axes */
@@ -537,13 +541,22 @@ static void pixel_ray(const double *cam, int px, int py, double d[3])
 }
 
 /* backward of one blended entry: dalpha plus direct output gradients */
-static void entry_backward(const oprim *P, const ohit *H, const double *dcam, const double *opts,
-                           double dalpha, double w, const double gc[3], double gd, const double gn[3],
-                           ograd *G)
+/* Gaussian curvature of z = l1 x^2 + l2 y^2 at (x, y) (curvature equation,
+   Sec. 3.2.1 and its derivation in the supplement) */
+static double curvature_K(double l1, double l2, double x, double y)
 {
-    /* direct colour, depth and normal terms */
+    const double den = 1.0 + 4.0 * l1 * l1 * x * x + 4.0 * l2 * l2 * y * y;
+    return 4.0 * l1 * l2 / (den * den);
+}
+
+static void entry_backward(const oprim *P, const ohit *H, const double *dcam, const double *opts,
+                           double dalpha, double w, const double gc[3], double dt_direct, const double gn[3],
+                           double dK, ograd *G)
+{
+    /* direct colour, depth (and the depth terms of median and distortion),
+       normal and curvature terms */
     for (int c = 0; c < 3; ++c) G->drgb[c] += gc[c] * w;
-    double dt = gd * w;
+    double dt = dt_direct;
     double nl[3], flip, vlen;
     hit_normal(P, H, nl, &flip, &vlen);
     double dncam[3] = {gn[0] * w, gn[1] * w, gn[2] * w};
@@ -562,6 +575,17 @@ static void entry_backward(const oprim *P, const ohit *H, const double *dcam, co
     G->dl[1] += -2.0 * H->y * dv[1];
     dx += -2.0 * P->l1 * dv[0];
     dy += -2.0 * P->l2 * dv[1];
+    /* K = 4 l1 l2 / den^2, den = 1 + 4 l1^2 x^2 + 4 l2^2 y^2 */
+    if (dK != 0.0) {
+        const double l1 = P->l1, l2 = P->l2, x = H->x, y = H->y;
+        const double den = 1.0 + 4.0 * l1 * l1 * x * x + 4.0 * l2 * l2 * y * y;
+        const double K = 4.0 * l1 * l2 / (den * den);
+        const double dden = -2.0 * K / den * dK;  /* dK/dden = -2 K / den */
+        G->dl[0] += 4.0 * l2 / (den * den) * dK + 8.0 * l1 * x * x * dden;
+        G->dl[1] += 4.0 * l1 / (den * den) * dK + 8.0 * l2 * y * y * dden;
+        dx += 8.0 * l1 * l1 * x * dden;
+        dy += 8.0 * l2 * l2 * y * dden;
+    }
 
     /* opacity and density: alpha = min(alpha_max, op G), G = exp(-E/2) */
     const double Gv = exp(-0.5 * H->E);
@@ -633,17 +657,21 @@ static void entry_backward(const oprim *P, const ohit *H, const double *dcam, co
         }
 }
 
-/* the whole per-pixel sequence; with dL != NULL also its backward */
+/* the whole per-pixel sequence; with g != NULL also its backward */
 static void render_pixel(const obins *B, const double *cam, const double *opts, const double *delta,
-                         int px, int py, int cell, int32_t x0w, int32_t y0w,
-                         double out[7], double *T_out, int32_t *nb_out, double *margin_out, int64_t *evals,
-                         const double g7[7], ograd *grads, oentry **scratch, int *scratch_cap)
+                         int px, int py, int cell, double out[NCH], double *T_out, int32_t *nb_out,
+                         double *margin_out, int64_t *evals, const double g[NCH], ograd *grads, oentry **scratch,
+                         int *scratch_cap)
 {
     double dcam[3];
     pixel_ray(cam, px, py, dcam);
-    double T = 1.0, acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double T = 1.0, acc[NCH] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double margin = INFINITY;
-    int nb = 0;
+    int nb = 0, med_k = -1;
+    double med = 0.0, med2 = -INFINITY;
+    /* blended (w, t) for the depth distortion, kept for its plain double sum */
+    double *wt = NULL;
+    int wt_cap = 0;
     const int32_t s = B->cell_start[cell], e = B->cell_start[cell + 1];
     for (int32_t it = s; it < e; ++it) {
         const int32_t li = B->cell_items[it];
@@ -671,10 +699,30 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
         m = mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N);
         if (m < margin) margin = m;
         for (int c = 0; c < 3; ++c) acc[c] += w * P->rgb[c];
-        acc[3] += w * H.t;
+        acc[CH_DEPTH] += w * H.t;
         for (int i = 0; i < 3; ++i)
-            acc[4 + i] += w * flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
-        if (g7) {
+            acc[CH_N + i] += w * flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
+        acc[CH_K] += w * curvature_K(P->l1, P->l2, H.x, H.y);
+        /* median depth (mesh extraction, Sec. 4.1): the largest hit depth among
+           entries whose incoming transmittance exceeds 0.5 */
+        m = mscale(fabs(T - 0.5) / 0.5, delta, M_MED);
+        if (m < margin) margin = m;
+        if (T > 0.5) {
+            if (med_k < 0 || H.t > med) {
+                if (med_k >= 0) med2 = med;
+                med = H.t;
+                med_k = nb;
+            } else if (H.t > med2) {
+                med2 = H.t;
+            }
+        }
+        if (nb >= wt_cap) {
+            wt_cap = wt_cap ? 2 * wt_cap : 64;
+            wt = (double *)realloc(wt, sizeof(double) * 2 * (size_t)wt_cap);
+        }
+        wt[2 * nb] = w;
+        wt[2 * nb + 1] = H.t;
+        if (g) {
             if (nb >= *scratch_cap) {
                 *scratch_cap = *scratch_cap ? 2 * *scratch_cap : 256;
                 *scratch = (oentry *)realloc(*scratch, sizeof(oentry) * (size_t)*scratch_cap);
@@ -686,16 +734,42 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
         ++nb;
         T = Tn;
     }
+    /* depth distortion (Sec. 3.3): sum_i sum_{j<i} w_i w_j (t_i - t_j)^2 */
+    double dist = 0.0, W = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        W += wt[2 * i];
+        for (int j = 0; j < i; ++j) {
+            const double d = wt[2 * i + 1] - wt[2 * j + 1];
+            dist += wt[2 * i] * wt[2 * j] * d * d;
+        }
+    }
+    /* the median's choice between two close hit depths is a discrete decision */
+    if (med_k >= 0 && med2 > -INFINITY) {
+        const double m = mscale((med - med2) / fabs(med), delta, M_MED);
+        if (m < margin) margin = m;
+    }
+    acc[CH_MED] = med;
+    acc[CH_DIST] = dist;
     for (int c = 0; c < 3; ++c) acc[c] += T * opts[O_BG + c];
-    for (int c = 0; c < 7; ++c) out[c] = acc[c];
+    for (int c = 0; c < NCH; ++c) out[c] = acc[c];
     *T_out = T;
     *nb_out = nb;
     *margin_out = margin;
-    (void)x0w; (void)y0w;
 
-    if (!g7) return;
-    /* back to front: S = sum_{j>i} w_j X_j + T_final bg */
-    double S[7] = {T * opts[O_BG], T * opts[O_BG + 1], T * opts[O_BG + 2], 0, 0, 0, 0};
+    if (!g) {
+        free(wt);
+        return;
+    }
+    /* back to front: S_c = sum_{j>i} w_j X_j,c (+ T_final bg for colour).
+       Distortion: L = W B - A^2 over all blended entries (W = sum w, A = sum w t,
+       B = sum w t^2), so dL/dw_i = L/W + W (t_i - A/W)^2 and
+       dL/dt_i = 2 w_i W (t_i - A/W); the first is the distortion channel's X_i. */
+    const double A = acc[CH_DEPTH], mean = W > 0.0 ? A / W : 0.0;
+    enum { NX = 9 };  /* colour 3, depth, normal 3, curvature, distortion */
+    double S[NX] = {T * opts[O_BG], T * opts[O_BG + 1], T * opts[O_BG + 2], 0, 0, 0, 0, 0, 0};
+    double gx[NX];
+    for (int c = 0; c < 8; ++c) gx[c] = g[c];
+    gx[8] = g[CH_DIST];
     for (int k = nb - 1; k >= 0; --k) {
         const oentry *en = &(*scratch)[k];
         const oprim *P = &B->prims[en->list];
@@ -703,17 +777,22 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
         ray_hit(P, dcam, opts, delta, &H);
         double nl[3], flip, vlen;
         hit_normal(P, &H, nl, &flip, &vlen);
-        double X[7];
+        double X[NX];
         for (int c = 0; c < 3; ++c) X[c] = P->rgb[c];
         X[3] = H.t;
         for (int i = 0; i < 3; ++i)
             X[4 + i] = flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
+        X[7] = curvature_K(P->l1, P->l2, H.x, H.y);
+        X[8] = (W > 0.0 ? dist / W : 0.0) + W * (H.t - mean) * (H.t - mean);
         const double a = en->alpha, Ti = en->T, w = a * Ti;
         double dalpha = 0.0;
-        for (int c = 0; c < 7; ++c) dalpha += g7[c] * (Ti * X[c] - S[c] / (1.0 - a));
-        for (int c = 0; c < 7; ++c) S[c] += w * X[c];
-        entry_backward(P, &H, dcam, opts, dalpha, w, g7, g7[3], g7 + 4, &grads[en->list]);
+        for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] / (1.0 - a));
+        for (int c = 0; c < NX; ++c) S[c] += w * X[c];
+        double dt = g[CH_DEPTH] * w + g[CH_DIST] * 2.0 * w * W * (H.t - mean);
+        if (k == med_k) dt += g[CH_MED];
+        entry_backward(P, &H, dcam, opts, dalpha, w, g, dt, g + CH_N, g[CH_K] * w, &grads[en->list]);
     }
+    free(wt);
 }
 
 /* conservative pixel box of the ball |p - cc| <= r (oracle's own binning) */
@@ -765,8 +844,10 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
                       const double *opts, const double *delta,
                       int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
                       double *color, double *depth, double *normal, double *T_final,
-                      int32_t *n_blend, double *margin,
+                      int32_t *n_blend, double *margin, double *curvature, double *median_depth,
+                      double *distortion,
                       const double *dL_color, const double *dL_depth, const double *dL_normal,
+                      const double *dL_curv, const double *dL_median, const double *dL_dist,
                       double *g_center, double *g_quat, double *g_scale, double *g_curv,
                       double *g_opac, double *g_rgb)
 {
@@ -842,19 +923,25 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
             for (int i = 0; i < w; ++i) {
                 const size_t pix = (size_t)j * w + i;
                 const int cell = (j / OT) * cx_n + (i / OT);
-                double out[7], Tf, mg;
+                double out[NCH], Tf, mg;
                 int32_t nb;
-                double g7[7];
+                double gg[NCH] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
                 if (do_bwd) {
-                    for (int c = 0; c < 3; ++c) g7[c] = dL_color[c * npx + pix];
-                    g7[3] = dL_depth[pix];
-                    for (int c = 0; c < 3; ++c) g7[4 + c] = dL_normal[c * npx + pix];
+                    for (int c = 0; c < 3; ++c) gg[c] = dL_color[c * npx + pix];
+                    gg[CH_DEPTH] = dL_depth[pix];
+                    for (int c = 0; c < 3; ++c) gg[CH_N + c] = dL_normal[c * npx + pix];
+                    if (dL_curv) gg[CH_K] = dL_curv[pix];
+                    if (dL_median) gg[CH_MED] = dL_median[pix];
+                    if (dL_dist) gg[CH_DIST] = dL_dist[pix];
                 }
-                render_pixel(&Bn, cam, opts, delta, x0 + i, y0 + j, cell, x0, y0, out, &Tf, &nb, &mg, &ev,
-                             do_bwd ? g7 : NULL, mine, &scratch, &cap);
+                render_pixel(&Bn, cam, opts, delta, x0 + i, y0 + j, cell, out, &Tf, &nb, &mg, &ev,
+                             do_bwd ? gg : NULL, mine, &scratch, &cap);
                 for (int c = 0; c < 3; ++c) color[c * npx + pix] = out[c];
-                depth[pix] = out[3];
-                for (int c = 0; c < 3; ++c) normal[c * npx + pix] = out[4 + c];
+                depth[pix] = out[CH_DEPTH];
+                for (int c = 0; c < 3; ++c) normal[c * npx + pix] = out[CH_N + c];
+                if (curvature) curvature[pix] = out[CH_K];
+                if (median_depth) median_depth[pix] = out[CH_MED];
+                if (distortion) distortion[pix] = out[CH_DIST];
                 T_final[pix] = Tf;
                 n_blend[pix] = nb;
                 margin[pix] = mg;
@@ -930,17 +1017,17 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
 
 /*
  * Single ray against a single primitive (FP64), for pin tests.
- * out = {ok, linear, t, x, y, z_on_surface, E, G, A, B, C, n_cam[3] (flipped)}.
+ * out = {ok, linear, t, x, y, z_on_surface, E, G, A, B, C, n_cam[3] (flipped), K}.
  */
 void oracle_ray_hit(const double *c, const double *q, const double *s, const double *l,
                     const double *cam, const double *dcam, const double *opts, double *out)
 {
-    const double delta[M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1};
+    const double delta[M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
     oprim P;
     setup_prim(c, q, s, l, 1.0, (const double[3]){0, 0, 0}, cam, cam + 9, &P);
     ohit H;
     ray_hit(&P, dcam, opts, delta, &H);
-    for (int i = 0; i < 14; ++i) out[i] = 0.0;
+    for (int i = 0; i < 15; ++i) out[i] = 0.0;
     out[0] = H.ok;
     out[1] = H.linear;
     out[8] = H.A;
@@ -955,4 +1042,5 @@ void oracle_ray_hit(const double *c, const double *q, const double *s, const dou
     hit_normal(&P, &H, nl, &flip, &vlen);
     for (int i = 0; i < 3; ++i)
         out[11 + i] = flip * (P.Rc[3 * i] * nl[0] + P.Rc[3 * i + 1] * nl[1] + P.Rc[3 * i + 2] * nl[2]);
+    out[14] = curvature_K(P.l1, P.l2, H.x, H.y);
 }

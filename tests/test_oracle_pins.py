@@ -426,7 +426,7 @@ def _fd_scene(seed, n):
 
 @pytest.mark.parametrize("seed", [11, 12, 13, 14, 15])
 def test_backward_matches_finite_differences(seed):
-    strict = dict(A=1e-3, D=1e-4, near=1e-4, E=1e-4, alpha_min=1e-4, T=1e-4, normal=1e-4, clamp=1e-4)
+    strict = dict(A=1e-3, D=1e-4, near=1e-4, E=1e-4, alpha_min=1e-4, T=1e-4, normal=1e-4, clamp=1e-4, median=1e-4)
     cam = scenes.look_at((0.1, 0.05, -3.0), width=16, height=16, f=20)
     for attempt in range(20):
         s_ = seed + 1000 * attempt
@@ -435,7 +435,8 @@ def test_backward_matches_finite_differences(seed):
         if seed % 2 == 1:
             sc.curv[0] = 0.0   # one planar primitive: the small-|A| branch
         rng = np.random.default_rng(100 + s_)
-        dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)))
+        dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)),
+              rng.standard_normal((16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((16, 16)))
         ks = oracle.keys(sc, cam)
         base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2)
         if base["margin"].min() >= 1.0 and base["n_blend"].max() >= min(n, 2):
@@ -446,7 +447,9 @@ def test_backward_matches_finite_differences(seed):
 
     def loss(params):
         r = oracle.render(sc, cam, params64=params, key_stage=ks, nthreads=2)
-        return float(np.sum(dL[0] * r["color"]) + np.sum(dL[1] * r["depth"]) + np.sum(dL[2] * r["normal"]))
+        return float(np.sum(dL[0] * r["color"]) + np.sum(dL[1] * r["depth"]) + np.sum(dL[2] * r["normal"]) +
+                     np.sum(dL[3] * r["curvature"]) + np.sum(dL[4] * r["median_depth"]) +
+                     np.sum(dL[5] * r["distortion"]))
 
     worst = 0.0
     for ki, key in enumerate(FD_KEYS):
@@ -658,3 +661,155 @@ def test_equal_depth_ties_follow_primitive_index():
         s, e = ranges[t]
         if e - s == 2:
             assert list(prims[s:e]) == [0, 1]
+
+
+# --------------------------------------------------------------------------
+# curvature (Sec. 3.2.1 and the supplement's derivation), median depth and
+# depth distortion (Sec. 3.3; median depth as the output depth, Sec. 4.1)
+# --------------------------------------------------------------------------
+
+def _implicit_gaussian_curvature(lam, p):
+    """Gaussian curvature of the zero set of F = l1 x^2 + l2 y^2 - z at p, from
+    the bordered Hessian of F (a construction for implicit surfaces that does
+    not go through a parametrisation)."""
+    grad = np.array([2 * lam[0] * p[0], 2 * lam[1] * p[1], -1.0])
+    Hs = np.diag([2 * lam[0], 2 * lam[1], 0.0])
+    M = np.zeros((4, 4))
+    M[:3, :3] = Hs
+    M[:3, 3] = grad
+    M[3, :3] = grad
+    return -np.linalg.det(M) / np.dot(grad, grad) ** 2
+
+
+def test_curvature_matches_implicit_surface_formula():
+    rng = np.random.default_rng(21)
+    nh = 0
+    for _ in range(2000):
+        q = unit(rng.standard_normal(4))
+        c = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(1.0, 6.0)])
+        s = 10.0 ** rng.uniform(-2.0, -0.3, 2)
+        lam = rng.uniform(-5, 5, 2)
+        d = unit(c + rng.normal(0, 1, 3) * s.max())
+        h = oracle.ray_hit(c, q, s, lam, ID_CAM, d)
+        if not h["ok"]:
+            continue
+        nh += 1
+        K = _implicit_gaussian_curvature(lam, (h["x"], h["y"], h["z"]))
+        assert abs(h["K"] - K) <= 1e-9 * max(1.0, abs(K)), (h["K"], K)
+        # the principal curvatures at the vertex are 2 l1 and 2 l2, so |K| <= 4 |l1 l2|
+        assert abs(h["K"]) <= 4 * abs(lam[0] * lam[1]) * (1 + 1e-12)
+        assert np.sign(h["K"]) == np.sign(lam[0] * lam[1]) or h["K"] == 0.0
+    assert nh > 400
+    # a planar primitive has zero curvature everywhere
+    h = oracle.ray_hit([0.0, 0.0, 3.0], [1, 0, 0, 0], [0.3, 0.2], [0.0, 0.0], ID_CAM, unit([0.01, 0.02, 1.0]))
+    assert h["ok"] and h["K"] == 0.0
+
+
+def test_curvature_map_head_on_vertex():
+    # hit at the vertex: K = 4 l1 l2 (product of the principal curvatures 2 l1, 2 l2)
+    cam = scenes.look_at((0.0, 0.0, -3.0), width=16, height=16, f=16)
+    sc = Scene(center=np.array([[0.0, 0.0, 0.0]], np.float32), quat=np.array([[0, 1, 0, 0]], np.float32),
+               scale=np.array([[0.2, 0.1]], np.float32), curv=np.array([[1.5, -0.7]], np.float32),
+               opacity=np.array([0.7], np.float32), rgb=np.array([[0.3, 0.6, 0.9]], np.float32))
+    cam.cx, cam.cy = 8.5, 8.5
+    r = oracle.render(sc, cam, nthreads=1)
+    a = float(sc.opacity[0])
+    K0 = 4.0 * float(sc.curv[0, 0]) * float(sc.curv[0, 1])
+    assert abs(r["curvature"][8, 8] - a * K0) < 1e-12
+    # one layer: the median depth is its hit depth and there is no distortion
+    assert abs(r["median_depth"][8, 8] - 3.0) < 1e-12
+    assert r["distortion"][8, 8] == 0.0
+
+
+@pytest.mark.parametrize("opac,k_med", [(0.3, 1), (0.25, 2), (0.6, 0), (0.5, 0)])
+def test_median_depth_is_last_hit_before_half_transmittance(opac, k_med):
+    # T_i = (1 - o)^i; the median is the deepest hit whose incoming T exceeds 0.5
+    # (with o = 0.5, T_1 = 0.5 exactly, which is not above 0.5)
+    depths = np.array([1.0, 1.5, 2.0, 2.5, 3.0, 3.5], np.float32)
+    sc = _head_on_stack(depths, [opac] * 6, np.full((6, 3), 0.5))
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=16, height=16, f=16)
+    cam.cx, cam.cy = 8.5, 8.5
+    r = oracle.render(sc, cam, nthreads=1)
+    assert r["median_depth"][8, 8] == float(depths[k_med])
+
+
+def test_distortion_two_and_three_layers_closed_form():
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=16, height=16, f=16)
+    cam.cx, cam.cy = 8.5, 8.5
+    a0, a1 = float(np.float32(0.6)), float(np.float32(0.45))
+    sc = _head_on_stack([1.25, 2.0], [0.6, 0.45], [[1, 0, 0], [0, 1, 0]])
+    r = oracle.render(sc, cam, nthreads=1)
+    w0, w1 = a0, (1 - a0) * a1
+    assert abs(r["distortion"][8, 8] - w0 * w1 * 0.75 ** 2) < 1e-14
+    # three layers: w_i w_j (t_i - t_j)^2 over the three pairs
+    a2 = float(np.float32(0.3))
+    sc = _head_on_stack([1.25, 2.0, 2.5], [0.6, 0.45, 0.3], np.full((3, 3), 0.5))
+    r = oracle.render(sc, cam, nthreads=1)
+    w = [a0, (1 - a0) * a1, (1 - a0) * (1 - a1) * a2]
+    t = [1.25, 2.0, 2.5]
+    exp = w[1] * w[0] * 0.75 ** 2 + w[2] * w[0] * 1.25 ** 2 + w[2] * w[1] * 0.5 ** 2
+    assert abs(r["distortion"][8, 8] - exp) < 1e-14
+    # moving the camera back along the axis shifts every t by the same amount:
+    # distortion unchanged, depth grows by sum(w) * shift, median by the shift
+    cam2 = scenes.look_at((0.0, 0.0, -0.75), target=(0, 0, 1), width=16, height=16, f=16)
+    cam2.cx, cam2.cy = 8.5, 8.5
+    r2 = oracle.render(sc, cam2, nthreads=1)
+    assert abs(r2["distortion"][8, 8] - exp) < 1e-13
+    assert abs(r2["depth"][8, 8] - r["depth"][8, 8] - sum(w) * 0.75) < 1e-13
+    assert abs(r2["median_depth"][8, 8] - r["median_depth"][8, 8] - 0.75) < 1e-13
+    assert abs(sum(wi * ti for wi, ti in zip(w, t)) - r["depth"][8, 8]) < 1e-14
+
+
+def test_all_maps_match_brute_force_per_pixel():
+    """Every map of a tiny scene against a per-pixel loop written here: every
+    primitive in key order (depth key, then index) hit by its own ray, the
+    alpha rules, the stop rule, and each map by its definition."""
+    sc = _fd_scene(31, 7)
+    cam = scenes.look_at((0.1, 0.05, -3.0), width=16, height=16, f=20)
+    ks = oracle.keys(sc, cam)
+    r = oracle.render(sc, cam, key_stage=ks, nthreads=2)
+    o = oracle.opts_array()
+    near, amin, amax, teps = o[0], o[2], o[3], o[4]
+    camv = oracle.cam_array(cam, np.float64)
+    order = sorted([i for i in range(sc.n) if not ks["culled"][i]], key=lambda i: (int(ks["depth_bits"][i]), i))
+    assert len(order) >= 4
+    checked = 0
+    for py in range(cam.height):
+        for px in range(cam.width):
+            xn = ((px + 0.5) - camv[14]) / camv[12]
+            yn = ((py + 0.5) - camv[15]) / camv[13]
+            d = unit([xn, yn, 1.0])
+            T = 1.0
+            col = np.zeros(3); dep = 0.0; nrm = np.zeros(3); kk = 0.0
+            wt = []
+            med = None
+            for i in order:
+                h = oracle.ray_hit(sc.center[i], sc.quat[i], sc.scale[i], sc.curv[i], camv, d)
+                if not h["ok"]:
+                    continue
+                al = min(amax, float(sc.opacity[i]) * math.exp(-0.5 * h["E"]))
+                if al < amin:
+                    continue
+                if T * (1 - al) < teps:
+                    break
+                w = al * T
+                col += w * sc.rgb[i].astype(float)
+                dep += w * h["t"]
+                nrm += w * h["normal"]
+                kk += w * h["K"]
+                if T > 0.5 and (med is None or h["t"] > med):
+                    med = h["t"]
+                wt.append((w, h["t"]))
+                T *= 1 - al
+            dist = sum(wt[i][0] * wt[j][0] * (wt[i][1] - wt[j][1]) ** 2 for i in range(len(wt)) for j in range(i))
+            if r["margin"][py, px] < 1.0:
+                continue
+            checked += 1
+            assert np.allclose(r["color"][:, py, px], col, rtol=0, atol=1e-12)
+            assert abs(r["depth"][py, px] - dep) < 1e-12
+            assert np.allclose(r["normal"][:, py, px], nrm, rtol=0, atol=1e-12)
+            assert abs(r["curvature"][py, px] - kk) < 1e-10 * max(1.0, abs(kk))
+            assert abs(r["median_depth"][py, px] - (med if med is not None else 0.0)) < 1e-12
+            assert abs(r["distortion"][py, px] - dist) < 1e-12
+            assert abs(r["T_final"][py, px] - T) < 1e-14
+    assert checked > 200
