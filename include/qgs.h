@@ -154,20 +154,39 @@ typedef struct qgs_tile_lists {
     uint64_t capacity;
 } qgs_tile_lists;
 
-/* Forward outputs, planar, [c][height][width]. */
+/*
+ * Forward outputs, planar, [c][height][width].  w = alpha T is an entry's
+ * blending weight and t its hit depth along the unit ray.
+ * The four geometry maps are optional: either all four pointers are NULL (not
+ * computed, no cost) or all four are set.
+ */
 typedef struct qgs_images {
     float *color;    /* [3][H][W] sum w rgb + T_final bg */
-    float *depth;    /* [H][W] sum w t, t along the unit ray */
+    float *depth;    /* [H][W] sum w t */
     float *normal;   /* [3][H][W] sum w n, camera-space unit normals facing the camera */
     float *T_final;  /* [H][W] final transmittance */
     uint32_t *last;  /* [H][W] 1 + position in the tile list of the last blended entry (0: none) */
+    /* curvature map (normal and curvature render equation, Sec. 3.2.1): sum w K,
+       K = 4 l1 l2 / (1 + 4 l1^2 x^2 + 4 l2^2 y^2)^2 the Gaussian curvature at the hit */
+    float *curvature;       /* [H][W] */
+    /* median depth (output depth of the experiments, Sec. 4.1): the largest t
+       among blended entries whose incoming transmittance exceeds 0.5 (0: none) */
+    float *median_depth;    /* [H][W] */
+    /* depth distortion (Sec. 3.3): sum_i sum_{j<i} w_i w_j (t_i - t_j)^2,
+       accumulated in the running-mean form L += w (L/W + W (t - mean)^2) */
+    float *distortion;      /* [H][W] */
+    uint32_t *median_pos;   /* [H][W] 1 + tile-list position of the median entry (0: none) */
 } qgs_images;
 
-/* Upstream gradients, same layouts; a NULL plane means zero. */
+/* Upstream gradients, same layouts; a NULL plane means zero.  Any non-NULL
+   geometry plane needs the geometry maps of the matching forward. */
 typedef struct qgs_image_grads {
     const float *dcolor;
     const float *ddepth;
     const float *dnormal;
+    const float *dcurvature;
+    const float *dmedian_depth;
+    const float *ddistortion;
 } qgs_image_grads;
 
 /* Parameter gradients, same shapes as qgs_scene. */
@@ -235,7 +254,8 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
  * records staged in LDS in batches, per-pixel ray-paraboloid intersection with
  * near/far root selection and the k_sigma geodesic cut-off, geodesic Gaussian
  * density, front-to-back compositing with stop once T would fall below T_eps.
- * Writes all planes of `out`.  Errors: QGS_ERR_INVALID_ARG.
+ * Writes all planes of `out`; the geometry maps only if they are set (all four
+ * or none).  Errors: QGS_ERR_INVALID_ARG.
  */
 qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists, const qgs_camera *cam,
                           const qgs_render_opts *opts, qgs_images *out, qgs_stream_t stream);
@@ -248,7 +268,10 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
  * global atomic per field per (tile, primitive); QGS_DETERMINISTIC_BWD instead
  * stores one partial per pair and sums each primitive's partials in a fixed
  * order.  Then the chain rule to the scene parameters, one thread per
- * primitive.  `fwd` must hold T_final and last from the matching forward.
+ * primitive.  `fwd` must hold T_final and last from the matching forward, and
+ * with any geometry gradient also its depth, distortion and median_pos (the
+ * distortion adjoint needs the pixel's sum of weights, 1 - T_final, its mean
+ * depth and its distortion; the median's gradient goes to the median entry).
  * ws: at least bwd_ws_bytes from qgs_workspace_query.
  * Errors: QGS_ERR_INVALID_ARG, QGS_ERR_WORKSPACE.
  */

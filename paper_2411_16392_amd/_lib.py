@@ -57,11 +57,13 @@ class QgsTileLists(ctypes.Structure):
 
 class QgsImages(ctypes.Structure):
     _fields_ = [("color", c_void_p), ("depth", c_void_p), ("normal", c_void_p), ("T_final", c_void_p),
-                ("last", c_void_p)]
+                ("last", c_void_p), ("curvature", c_void_p), ("median_depth", c_void_p),
+                ("distortion", c_void_p), ("median_pos", c_void_p)]
 
 
 class QgsImageGrads(ctypes.Structure):
-    _fields_ = [("dcolor", c_void_p), ("ddepth", c_void_p), ("dnormal", c_void_p)]
+    _fields_ = [("dcolor", c_void_p), ("ddepth", c_void_p), ("dnormal", c_void_p), ("dcurvature", c_void_p),
+                ("dmedian_depth", c_void_p), ("ddistortion", c_void_p)]
 
 
 class QgsSceneGrads(ctypes.Structure):

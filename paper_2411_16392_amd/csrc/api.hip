@@ -233,6 +233,9 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     if (!prims || !prims_ok(prims, prims->n) || !lists_ok(lists) || !cam_ok(cam) || !opts_ok(opts) || !out)
         return QGS_ERR_INVALID_ARG;
     if (!out->color || !out->depth || !out->normal || !out->T_final || !out->last) return QGS_ERR_INVALID_ARG;
+    const int n_geo = (out->curvature != nullptr) + (out->median_depth != nullptr) + (out->distortion != nullptr) +
+                      (out->median_pos != nullptr);
+    if (n_geo != 0 && n_geo != 4) return QGS_ERR_INVALID_ARG;
     FwdOut o;
     o.color = out->color;
     o.depth = out->depth;
@@ -240,6 +243,10 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     o.T_final = out->T_final;
     o.last = out->last;
     o.counters = (opts->flags & QGS_COUNT_EVALS) ? lists->counters : nullptr;
+    o.curvature = out->curvature;
+    o.median_depth = out->median_depth;
+    o.distortion = out->distortion;
+    o.median_pos = out->median_pos;
     return hip_status(launch_render_fwd(raster_args(prims, lists, cam), raster_params(cam, opts), o,
                                         (hipStream_t)stream));
 }
@@ -254,6 +261,8 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
         return QGS_ERR_INVALID_ARG;
     if (scene->n > 0 && (!out->center || !out->quat || !out->scale || !out->curv || !out->opacity || !out->rgb))
         return QGS_ERR_INVALID_ARG;
+    const bool geo = dL->dcurvature || dL->dmedian_depth || dL->ddistortion;
+    if (geo && (!fwd->depth || !fwd->distortion || !fwd->median_pos)) return QGS_ERR_INVALID_ARG;
     const bool det = (opts->flags & QGS_DETERMINISTIC_BWD) != 0;
     if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags)) return QGS_ERR_WORKSPACE;
     float *grad_rec = reinterpret_cast<float *>(ws);
@@ -266,6 +275,12 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.dcolor = dL->dcolor;
     in.ddepth = dL->ddepth;
     in.dnormal = dL->dnormal;
+    in.dcurvature = dL->dcurvature;
+    in.dmedian = dL->dmedian_depth;
+    in.ddistortion = dL->ddistortion;
+    in.depth = fwd->depth;
+    in.distortion = fwd->distortion;
+    in.median_pos = fwd->median_pos;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
                                                  grad_rec, scratch, scene->n, lists->capacity, s));
     if (st != QGS_OK) return st;

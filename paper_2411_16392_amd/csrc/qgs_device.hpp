@@ -241,4 +241,13 @@ __device__ inline float hit_normal(const Prim &p, const Hit &H, float nl[3], flo
     return dot > 0.0f ? -1.0f : 1.0f;
 }
 
+// Gaussian curvature of the paraboloid at the hit (curvature equation,
+// Sec. 3.2.1): 4 l1 l2 / (1 + 4 l1^2 x^2 + 4 l2^2 y^2)^2, where inv_len from
+// hit_normal is 1 / sqrt of the bracket.
+__device__ inline float hit_curvature(const Prim &p, float inv_len)
+{
+    const float i2 = inv_len * inv_len;
+    return 4.0f * p.l1 * p.l2 * (i2 * i2);
+}
+
 }  // namespace qgs

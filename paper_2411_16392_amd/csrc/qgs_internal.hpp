@@ -87,12 +87,19 @@ struct FwdOut {
     float *color, *depth, *normal, *T_final;
     uint32_t *last;
     uint32_t *counters;  // counters[2..4] of the tile lists, or null
+    // geometry maps: all set or all null
+    float *curvature, *median_depth, *distortion;
+    uint32_t *median_pos;
 };
 
 struct BwdIn {
     const float *T_final;
     const uint32_t *last;
     const float *dcolor, *ddepth, *dnormal;
+    // geometry gradients (any may be null) and the forward maps they need
+    const float *dcurvature, *dmedian, *ddistortion;
+    const float *depth, *distortion;
+    const uint32_t *median_pos;
 };
 
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream);

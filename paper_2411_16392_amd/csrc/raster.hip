@@ -97,6 +97,8 @@ __device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int 
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+// GEO: also the curvature, median-depth and depth-distortion maps.
+template <bool GEO>
 #if QGS_FWD_MIN_WAVES > 0
 __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
 #else
@@ -117,6 +119,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
     uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
     bool done = !inside;
+    // geometry: curvature sum, median depth and its position, and the running
+    // sum of weights, mean depth and distortion
+    float kk = 0.0f, med = 0.0f, gW = 0.0f, gm = 0.0f, gL = 0.0f;
+    uint32_t med_pos = 0;
 
     for (uint32_t b0 = start; b0 < end; b0 += FWD_BATCH) {
         if (__syncthreads_count(!done) == 0) break;
@@ -152,15 +158,30 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                             c0 = __builtin_fmaf(w, cr.y, c0);
                             c1 = __builtin_fmaf(w, cr.z, c1);
                             c2 = __builtin_fmaf(w, cr.w, c2);
-                            dep = __builtin_fmaf(w, (p.Zc + H.s) * ray.enorm, dep);
+                            const float t = (p.Zc + H.s) * ray.enorm;
+                            dep = __builtin_fmaf(w, t, dep);
                             float nl[3], il;
                             const float f = hit_normal(p, H, nl, il);
                             const float wf = w * f;
                             n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
                             n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
                             n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
+                            const uint32_t pos1 = b0 - start + (uint32_t)j + 1u;
+                            if (GEO) {
+                                kk = __builtin_fmaf(w, hit_curvature(p, il), kk);
+                                if (T > 0.5f && (med_pos == 0u || t > med)) {
+                                    med = t;
+                                    med_pos = pos1;
+                                }
+                                // L += w (L / W + W (t - mean)^2); W += w; mean += w (t - mean) / W
+                                const float dtm = t - gm;
+                                const float Xd = gW > 0.0f ? __builtin_fmaf(gW * dtm, dtm, gL * __builtin_amdgcn_rcpf(gW)) : 0.0f;
+                                gL = __builtin_fmaf(w, Xd, gL);
+                                gW += w;
+                                gm = __builtin_fmaf(w * __builtin_amdgcn_rcpf(gW), dtm, gm);
+                            }
                             T = Tn;
-                            last = b0 - start + (uint32_t)j + 1u;
+                            last = pos1;
                             ++n_blend;
                         }
                     }
@@ -182,6 +203,12 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         o.normal[2 * hw + pix] = n2;
         o.T_final[pix] = T;
         o.last[pix] = last;
+        if (GEO) {
+            o.curvature[pix] = kk;
+            o.median_depth[pix] = med;
+            o.distortion[pix] = gL;
+            o.median_pos[pix] = med_pos;
+        }
     }
     if (o.counters) {
         // list entries processed per pixel (up to and including a stop),
@@ -204,16 +231,19 @@ struct PixGrad {
     float g[NGRAD];
 };
 
-// adjoint of one blended entry; adds into G (the primitive's record gradient)
+// adjoint of one blended entry; adds into gr (the primitive's record
+// gradient).  dt: gradient with respect to the hit depth t; dK (GEO): with
+// respect to the curvature value K at the hit.
+template <bool GEO>
 __device__ inline void entry_grad(const Prim &p, const float rgb[3], const PixelRay &ray, const RasterParams &P,
-                                  const Hit &H, float G, float dalpha, float w, const float gc[3], float gd,
-                                  const float gn[3], float *gr)
+                                  const Hit &H, float G, float dalpha, float w, const float gc[3], float dt,
+                                  const float gn[3], float dK, float *gr)
 {
     // colour and depth outputs
     gr[G_R] += gc[0] * w;
     gr[G_G] += gc[1] * w;
     gr[G_B] += gc[2] * w;
-    float dz = gd * w * ray.enorm;  // t = (Zc + s) |e|
+    float dz = dt * ray.enorm;  // t = (Zc + s) |e|
     float dx = 0.0f, dy = 0.0f;
     float dphi0 = 0.0f, dphi1 = 0.0f, dphi2 = 0.0f;
     // normal output: n_cam = f Rc nl, nl = v / |v|, v = (-2 l1 x, -2 l2 y, 1)
@@ -238,6 +268,16 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
         gr[G_L2] += -2.0f * H.y * dv1;
         dx += -2.0f * p.l1 * dv0;
         dy += -2.0f * p.l2 * dv1;
+        // curvature output: K = 4 l1 l2 / D^2, D = 1 + 4 l1^2 x^2 + 4 l2^2 y^2 = 1 / il^2
+        if (GEO) {
+            const float i2 = il * il, i4 = i2 * i2;
+            const float K = 4.0f * p.l1 * p.l2 * i4;
+            const float dD = -2.0f * K * i2 * dK;
+            gr[G_L1] += 4.0f * p.l2 * i4 * dK + 8.0f * p.l1 * H.x * H.x * dD;
+            gr[G_L2] += 4.0f * p.l1 * i4 * dK + 8.0f * p.l2 * H.y * H.y * dD;
+            dx += 8.0f * p.l1 * p.l1 * H.x * dD;
+            dy += 8.0f * p.l2 * p.l2 * H.y * dD;
+        }
     }
     // alpha = min(alpha_max, op G), G = exp(-E / 2), E = g(u)^2 Q
     float dG = 0.0f;
@@ -321,7 +361,7 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     gr[G_PHI2] += dphi2;
 }
 
-template <bool DET>
+template <bool DET, bool GEO>
 #if QGS_BWD_MIN_WAVES > 0
 __global__ __launch_bounds__(BLOCK, QGS_BWD_MIN_WAVES) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
                                                                          float *grad_rec, float *pair_scratch)
@@ -365,8 +405,29 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
             gn[2] = in.dnormal[2 * hw + pix];
         }
     }
-    // suffix sums S (colour starts with the background term)
-    float S[7] = {T * P.bg[0], T * P.bg[1], T * P.bg[2], 0.0f, 0.0f, 0.0f, 0.0f};
+    // geometry: upstream gradients and the pixel's final sum of weights W,
+    // mean depth and distortion L; the distortion adjoint is the linear one
+    // with X_i = dL/dw_i = L / W + W (t_i - mean)^2, plus dL/dt_i = 2 w_i W (t_i - mean)
+    float gK = 0.0f, gmed = 0.0f, gdist = 0.0f, gW = 0.0f, gm = 0.0f, gLW = 0.0f;
+    uint32_t med_pos = 0;
+    if (GEO && inside) {
+        if (in.dcurvature) gK = in.dcurvature[pix];
+        if (in.dmedian) gmed = in.dmedian[pix];
+        if (in.ddistortion) gdist = in.ddistortion[pix];
+        med_pos = in.median_pos[pix];
+        gW = 1.0f - T;
+        if (gW > 0.0f) {
+            const float iW = __builtin_amdgcn_rcpf(gW);
+            gm = in.depth[pix] * iW;
+            gLW = in.distortion[pix] * iW;
+        }
+    }
+    // suffix sums S (colour starts with the background term); GEO adds the
+    // curvature and distortion channels
+    constexpr int NX = GEO ? 9 : 7;
+    float S[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) S[c] = c < 3 ? T * P.bg[c] : 0.0f;
     const uint32_t wmax = wave_max_u32(last);
     if (tid == 0) s_maxlast = 0;
     __syncthreads();
@@ -422,24 +483,35 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                         const float iom = __builtin_amdgcn_rcpf(om);
                         const float Ti = T * iom;
                         const float w = alpha * Ti;
-                        float X[7];
+                        float X[NX];
                         X[0] = rgb[0];
                         X[1] = rgb[1];
                         X[2] = rgb[2];
-                        X[3] = (p.Zc + H.s) * ray.enorm;
+                        const float t = (p.Zc + H.s) * ray.enorm;
+                        X[3] = t;
                         float nl[3], il;
                         const float f = hit_normal(p, H, nl, il);
                         X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
                         X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
                         X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
-                        const float g7[7] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+                        float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+                        float dt = gd * w;
+                        if (GEO) {
+                            const float dtm = t - gm;
+                            X[7] = hit_curvature(p, il);
+                            X[8] = __builtin_fmaf(gW * dtm, dtm, gLW);
+                            gx[7] = gK;
+                            gx[8] = gdist;
+                            dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
+                            if (pos + 1u == med_pos) dt += gmed;
+                        }
                         float dalpha = 0.0f;
 #pragma unroll
-                        for (int c = 0; c < 7; ++c) dalpha += g7[c] * (Ti * X[c] - S[c] * iom);
+                        for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] * iom);
 #pragma unroll
-                        for (int c = 0; c < 7; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
+                        for (int c = 0; c < NX; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
                         T = Ti;
-                        entry_grad(p, rgb, ray, P, H, G, dalpha, w, gc, gd, gn, gr);
+                        entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
                     }
                 }
             }
@@ -510,7 +582,10 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
 {
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render_fwd, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+    if (o.curvature)
+        hipLaunchKernelGGL(k_render_fwd<true>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+    else
+        hipLaunchKernelGGL(k_render_fwd<false>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
     return hipGetLastError();
 }
 
@@ -521,16 +596,26 @@ hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const B
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grad_rec), 0u, (uint64_t)n_prims * 16, stream);
     if (e != hipSuccess) return e;
     if (ntiles == 0) return hipSuccess;
+    const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
     if (pair_scratch) {
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 16, stream);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_render_bwd<true>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
+        if (geo)
+            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
+                               pair_scratch);
+        else
+            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
+                               pair_scratch);
         if (n_prims > 0)
             hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
                                (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
                                grad_rec);
+    } else if (geo) {
+        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
+                           pair_scratch);
     } else {
-        hipLaunchKernelGGL(k_render_bwd<false>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec, pair_scratch);
+        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
+                           pair_scratch);
     }
     return hipGetLastError();
 }

@@ -91,6 +91,11 @@ class FrameState:
     normal: torch.Tensor
     T_final: torch.Tensor
     last: torch.Tensor
+    # geometry maps (None unless the renderer computes them)
+    curvature: torch.Tensor | None = None
+    median_depth: torch.Tensor | None = None
+    distortion: torch.Tensor | None = None
+    median_pos: torch.Tensor | None = None
 
     def prim_buf(self) -> L.QgsPrimBuf:
         p = L.QgsPrimBuf()
@@ -111,6 +116,9 @@ class FrameState:
         im = L.QgsImages()
         im.color, im.depth, im.normal = _ptr(self.color), _ptr(self.depth), _ptr(self.normal)
         im.T_final, im.last = _ptr(self.T_final), _ptr(self.last)
+        if self.curvature is not None:
+            im.curvature, im.median_depth = _ptr(self.curvature), _ptr(self.median_depth)
+            im.distortion, im.median_pos = _ptr(self.distortion), _ptr(self.median_pos)
         return im
 
 
@@ -119,12 +127,14 @@ class Renderer:
 
     capacity: pair-list capacity to start from; grown on demand (exact mode) or
     fixed (exact=False, no host synchronisation; overflow is then reported in
-    counters[1]).
+    counters[1]).  geometry: also render the curvature, median-depth and
+    depth-distortion maps.
     """
 
     def __init__(self, device="cuda", opts: L.QgsRenderOpts | None = None, capacity: int = 1 << 20,
-                 growth: float = 1.25):
+                 growth: float = 1.25, geometry: bool = False):
         self.device = torch.device(device)
+        self.geometry = bool(geometry)
         self.opts = opts if opts is not None else make_opts()
         self.capacity = int(capacity)
         self.growth = growth
@@ -169,6 +179,11 @@ class Renderer:
             T_final=torch.empty((H, W), dtype=torch.float32, device=dev),
             last=torch.empty((H, W), dtype=torch.int32, device=dev),
         )
+        if self.geometry:
+            st.curvature = torch.empty((H, W), dtype=torch.float32, device=dev)
+            st.median_depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+            st.distortion = torch.empty((H, W), dtype=torch.float32, device=dev)
+            st.median_pos = torch.empty((H, W), dtype=torch.int32, device=dev)
         L.qgs_preprocess(_scene_struct(scene_t), c, self.opts, st.prim_buf(), _stream())
         return st
 
@@ -196,7 +211,8 @@ class Renderer:
         return self.render_fwd(st)
 
     def backward(self, scene_t: dict, st: FrameState, dcolor=None, ddepth=None, dnormal=None,
-                 out: dict | None = None, accumulate: bool = False) -> dict:
+                 out: dict | None = None, accumulate: bool = False, dcurvature=None, dmedian_depth=None,
+                 ddistortion=None) -> dict:
         if out is None:
             out = {k: torch.empty_like(scene_t[k]) for k in SCENE_KEYS}
         g = L.QgsSceneGrads()
@@ -204,7 +220,10 @@ class Renderer:
             setattr(g, k, out[k].data_ptr())
         dl = L.QgsImageGrads()
         keep = []
-        for name, t in (("dcolor", dcolor), ("ddepth", ddepth), ("dnormal", dnormal)):
+        geo = (("dcurvature", dcurvature), ("dmedian_depth", dmedian_depth), ("ddistortion", ddistortion))
+        if st.curvature is None and any(t is not None for _, t in geo):
+            raise ValueError("geometry gradients need a forward rendered with geometry=True")
+        for name, t in (("dcolor", dcolor), ("ddepth", ddepth), ("dnormal", dnormal)) + geo:
             if t is not None:
                 t = t.contiguous().float()
                 keep.append(t)
@@ -221,7 +240,8 @@ class Renderer:
 
 class QGSRasterize(torch.autograd.Function):
     """colour, depth, normal = QGSRasterize.apply(center, quat, scale, curv,
-    opacity, rgb, renderer, camera)."""
+    opacity, rgb, renderer, camera); with a geometry renderer also curvature,
+    median depth and depth distortion."""
 
     @staticmethod
     def forward(ctx, center, quat, scale, curv, opacity, rgb, renderer: Renderer, cam):
@@ -231,18 +251,23 @@ class QGSRasterize(torch.autograd.Function):
         ctx.renderer = renderer
         ctx.state = st
         ctx.save_for_backward(*[scene_t[k] for k in SCENE_KEYS])
+        if renderer.geometry:
+            return st.color, st.depth, st.normal, st.curvature, st.median_depth, st.distortion
         return st.color, st.depth, st.normal
 
     @staticmethod
-    def backward(ctx, dcolor, ddepth, dnormal):
+    def backward(ctx, dcolor, ddepth, dnormal, *dgeo):
         scene_t = dict(zip(SCENE_KEYS, ctx.saved_tensors))
-        g = ctx.renderer.backward(scene_t, ctx.state, dcolor, ddepth, dnormal)
+        dk, dm, dd = (tuple(dgeo) + (None, None, None))[:3]
+        g = ctx.renderer.backward(scene_t, ctx.state, dcolor, ddepth, dnormal, dcurvature=dk, dmedian_depth=dm,
+                                  ddistortion=dd)
         return (g["center"], g["quat"], g["scale"], g["curv"], g["opacity"], g["rgb"], None, None)
 
 
-def render(scene_t: dict, cam, renderer: Renderer | None = None):
-    """Differentiable render of one view: (colour [3,H,W], depth [H,W], normal [3,H,W])."""
-    r = renderer if renderer is not None else Renderer(device=scene_t["center"].device)
+def render(scene_t: dict, cam, renderer: Renderer | None = None, geometry: bool = False):
+    """Differentiable render of one view: (colour [3,H,W], depth [H,W], normal [3,H,W]), and with
+    geometry=True also (curvature [H,W], median depth [H,W], depth distortion [H,W])."""
+    r = renderer if renderer is not None else Renderer(device=scene_t["center"].device, geometry=geometry)
     return QGSRasterize.apply(scene_t["center"], scene_t["quat"], scene_t["scale"], scene_t["curv"],
                               scene_t["opacity"], scene_t["rgb"], r, cam)
 

@@ -349,3 +349,16 @@ def upstream_grads(rng_seed: int, height: int, width: int, crop=None):
         m[y0:y0 + h, x0:x0 + w] = True
         g[:, ~m] = 0.0
     return g[0:3].copy(), g[3].copy(), g[4:7].copy()
+
+
+def upstream_geometry_grads(rng_seed: int, height: int, width: int, crop=None):
+    """dL/d(curvature[H,W], median depth[H,W], distortion[H,W]) drawn i.i.d.
+    N(0,1) from their own stream; zero outside `crop` as above."""
+    rng = np.random.Generator(np.random.PCG64([rng_seed, 3]))
+    g = rng.standard_normal((3, height, width)).astype(F32)
+    if crop is not None:
+        x0, y0, w, h = crop
+        m = np.zeros((height, width), bool)
+        m[y0:y0 + h, x0:x0 + w] = True
+        g[:, ~m] = 0.0
+    return g[0].copy(), g[1].copy(), g[2].copy()
