@@ -269,12 +269,15 @@ void scheduler(qgs_server *s)
             sl.phase = IDLE;
             s->in_flight--;
         }
-        // 2. admit waiting requests for rendering, oldest first
+        // 2. admit waiting requests for rendering in arrival order: only the
+        // oldest request not yet admitted may go, so a younger request whose
+        // count pass finished first waits behind an older one still counting
         for (;;) {
             Slot *oldest = nullptr;
             for (auto &sl : s->slots)
-                if (sl.phase == WAITING && (!oldest || sl.req->id < oldest->req->id)) oldest = &sl;
-            if (!oldest) break;
+                if ((sl.phase == WAITING || sl.phase == COUNTING) && (!oldest || sl.req->id < oldest->req->id))
+                    oldest = &sl;
+            if (!oldest || oldest->phase != WAITING) break;
             Req &r = *oldest->req;
             bool cancelled;
             {
