@@ -54,18 +54,41 @@ __device__ inline float dpp_f(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
 }
 
-// Sum over the wave with DPP: shifts within each 16-lane row, then the row
-// broadcasts 15 and 31; the total lands in lane 63.  Fixed order, so the result
-// is reproducible.
-__device__ inline float wave_sum_to_lane63(float v)
+// Reduce-scatter of 16 per-lane values over the wave: afterwards every lane l
+// holds the wave total of value (l >> 2).  Each step halves the values a lane
+// keeps: lanes whose step bit is 0 keep the first half and add the partner's
+// first half, the others the second half.  Steps 32 and 16 use the gfx950
+// row-swap instructions (v_permlane32_swap: upper half of the first operand
+// <-> lower half of the second; v_permlane16_swap: odd rows of the first <->
+// even rows of the second), so a swap plus one add merges a pair of values;
+// steps 8 and 4 exchange with the mirrored lane in the row / half-row (partners
+// differ exactly in that bit), and steps 2 and 1 are butterflies inside the
+// quad.  Fixed order, so the result is reproducible.
+__device__ inline float wave_reduce_scatter16(const float (&v)[16])
 {
-    v += dpp_f<0x111>(v);        // row_shr:1
-    v += dpp_f<0x112>(v);        // row_shr:2
-    v += dpp_f<0x114>(v);        // row_shr:4
-    v += dpp_f<0x118>(v);        // row_shr:8
-    v += dpp_f<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_f<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-    return v;
+    const int lane = threadIdx.x & 63;
+    float a[8], b[4], c[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+        a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // lanes 0-31: value i, 32-63: value i + 8
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[i]), __float_as_uint(a[i + 4]), false, false);
+        b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // even rows: a[i], odd rows: a[i + 4]
+    }
+    const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = hi8 ? b[i + 2] : b[i], send = hi8 ? b[i] : b[i + 2];
+        c[i] = keep + dpp_f<0x140>(send);  // row_mirror: lane 15 - l of the row
+    }
+    const float keep = hi4 ? c[1] : c[0], send = hi4 ? c[0] : c[1];
+    float d = keep + dpp_f<0x141>(send);  // row_half_mirror: lane 7 - l of the half-row
+    d += dpp_f<0x4E>(d);                  // quad_perm [2, 3, 0, 1]
+    d += dpp_f<0xB1>(d);                  // quad_perm [1, 0, 3, 2]
+    return d;
 }
 
 __device__ inline uint32_t wave_max_u32(uint32_t v)
@@ -516,17 +539,17 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                 }
             }
             if (__ballot(contrib) != 0ull) {
+                float g16[16];
 #pragma unroll
-                for (int f = 0; f < NGRAD; ++f) gr[f] = wave_sum_to_lane63(gr[f]);
-                if (lane == 63) {
-                    if (DET) {
-#pragma unroll
-                        for (int f = 0; f < NGRAD; ++f) s_acc[DET ? wave : 0][j][f] = gr[f];
-                    } else {
-#pragma unroll
-                        for (int f = 0; f < NGRAD; ++f)
-                            if (gr[f] != 0.0f) atomicAdd(&s_acc[0][j][f], gr[f]);
-                    }
+                for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD ? gr[f] : 0.0f;
+                // lane 4f (f < NGRAD) ends with the wave total of field f
+                const float tot = wave_reduce_scatter16(g16);
+                const int f = lane >> 2;
+                if ((lane & 3) == 0 && f < NGRAD) {
+                    if (DET)
+                        s_acc[DET ? wave : 0][j][f] = tot;
+                    else if (tot != 0.0f)
+                        atomicAdd(&s_acc[0][j][f], tot);
                 }
             }
         }
