@@ -302,26 +302,29 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
                                               const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
                                               uint32_t *emit_prim)
 {
+    __shared__ ConicLane s_cl[256];
+    if (counters[1]) return;  // overflow: the same for every thread
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n || counters[1]) return;
-    const uint64_t base = off[r], cnt = off[r + 1] - base;
-    if (cnt == 0) return;
-    const uint32_t p = order[r];
-    const int32_t *rc = rect + 4 * (size_t)p;
-    const double *C = conic + 8 * (size_t)p;
-    const bool cok = C[6] != 0.0;
-    uint64_t k = 0;
-    for (int ty = rc[1]; ty <= rc[3]; ++ty)
-        for (int tx = rc[0]; tx <= rc[2]; ++tx) {
-            if (cok && !conic_tile_hit(C, tx, ty, cam)) continue;
-            if (k < cnt) {
-                const uint64_t e = base + k;
-                out_tile[e] = (uint32_t)(ty * tiles_x + tx);
-                out_emit[e] = (uint32_t)e;
-                emit_prim[e] = p;
-            }
-            ++k;
+    ConicLane cl = {};
+    if (r < n) {
+        const uint64_t base = off[r], cnt = off[r + 1] - base;
+        if (cnt > 0) {
+            const uint32_t p = order[r];
+            const int32_t *rc = rect + 4 * (size_t)p;
+            const double *C = conic + 8 * (size_t)p;
+            for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
+            cl.cok = C[6] != 0.0 ? 1u : 0u;
+            if (cl.cok) conic_center(cl.C, cl.mx, cl.my);
+            cl.base = base;
+            cl.cnt = (uint32_t)cnt;
+            cl.prim = p;
+            cl.tx0 = rc[0];
+            cl.ty0 = rc[1];
+            cl.nx = rc[2] - rc[0] + 1;
+            cl.ny = rc[3] - rc[1] + 1;
         }
+    }
+    (void)wave_conic_tiles<true>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit, emit_prim);
 }
 
 // After the sort the values are emission indices: replace them by primitive

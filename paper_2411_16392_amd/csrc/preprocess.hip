@@ -20,11 +20,11 @@ namespace qgs {
 
 __device__ inline bool finite_f(float v) { return __builtin_isfinite(v); }
 
-__global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
+// Everything of one primitive except its tile count: the record, depth key,
+// rectangle and conic; `cl` receives the tile rectangle and conic for the
+// tile tests (nx = 0 when it covers no tile).
+__device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicLane &cl)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-
     float4 *rec = reinterpret_cast<float4 *>(reinterpret_cast<char *>(a.records) + p * 128);
     int32_t *rt = a.rect + 4 * p;
     const float4 empty_rect = make_float4(__int_as_float(0), __int_as_float(-1), __int_as_float(0), __int_as_float(-1));
@@ -59,7 +59,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
         rec[0] = empty_rect;
         a.depth_key[p] = 0u;
         rt[0] = 0; rt[1] = 0; rt[2] = -1; rt[3] = -1;
-        a.tiles[p] = 0u;
         return;
     }
 
@@ -138,7 +137,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
     if (empty) {
         rec[0] = empty_rect;
         rt[0] = 0; rt[1] = 0; rt[2] = -1; rt[3] = -1;
-        a.tiles[p] = 0u;
         return;
     }
     const int tx0 = px0 / TILE, tx1 = px1 / TILE, ty0 = py0 / TILE, ty1 = py1 / TILE;
@@ -175,10 +173,13 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
     }
     for (int i = 0; i < 6; ++i) cq[i] = C[i];
     cq[6] = cok ? 1.0 : 0.0;
-    uint32_t cnt = 0;
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) cnt += (!cok || conic_tile_hit(C, tx, ty, a.cam)) ? 1u : 0u;
-    a.tiles[p] = cnt;
+    for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
+    if (cok) conic_center(C, cl.mx, cl.my);
+    cl.cok = cok ? 1u : 0u;
+    cl.tx0 = tx0;
+    cl.ty0 = ty0;
+    cl.nx = tx1 - tx0 + 1;
+    cl.ny = ty1 - ty0 + 1;
 
     // projected centre split into integer + fraction, and the record
     const double uc = fma(fx, cc[0] / cc[2], cxp), vc = fma(fy, cc[1] / cc[2], cyp);
@@ -207,6 +208,17 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
     rec[5] = make_float4((float)Rc[4], (float)Rc[5], (float)Rc[6], (float)Rc[7]);
     rec[6] = make_float4((float)Rc[8], r0, r1, r2);
     rec[7] = make_float4(cC, cD, cE, 0.0f);
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
+{
+    __shared__ ConicLane s_cl[256];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    ConicLane cl = {};
+    if (p < a.n) preprocess_one(a, p, cl);
+    // every thread of the workgroup takes part in the tile tests
+    const uint32_t cnt = wave_conic_tiles<false>(s_cl + (threadIdx.x & ~63u), cl, a.cam, 0, nullptr, nullptr, nullptr);
+    if (p < a.n) a.tiles[p] = cnt;
 }
 
 // Chain rule from the record gradients (rotation as a right perturbation

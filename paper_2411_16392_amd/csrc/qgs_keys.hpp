@@ -24,7 +24,17 @@ __device__ inline double conic_eval(const double *C, double x, double y)
 
 __device__ inline double clamp_d(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ inline bool conic_tile_hit(const double *C, int tx, int ty, const qgs_camera &cam)
+// The conic's centre (minimiser of f), a per-primitive constant of the test.
+__device__ inline void conic_center(const double *C, double &mx, double &my)
+{
+#pragma clang fp contract(off)
+    const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
+    const double det = a * c - b * b;
+    mx = (b * e - c * d) / det;
+    my = (b * d - a * e) / det;
+}
+
+__device__ inline bool conic_tile_hit(const double *C, double mx, double my, int tx, int ty, const qgs_camera &cam)
 {
 #pragma clang fp contract(off)
     const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
@@ -34,8 +44,6 @@ __device__ inline bool conic_tile_hit(const double *C, int tx, int ty, const qgs
     const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) / fx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) / fx;
     const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) / fy, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) / fy;
     const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
-    const double det = a * c - b * b;
-    const double mx = (b * e - c * d) / det, my = (b * d - a * e) / det;
     if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
     const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
     for (int k = 0; k < 2; ++k) {
@@ -45,6 +53,104 @@ __device__ inline bool conic_tile_hit(const double *C, int tx, int ty, const qgs
         if (conic_eval(C, x, ys[k]) <= 0.0) return true;
     }
     return false;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-cooperative tile tests.  A primitive's candidate tiles are the tiles of
+// its rectangle, row-major.  Rather than one thread looping over its own
+// primitive's candidates (a wave then waits for its largest primitive), the
+// wave's candidates are numbered consecutively (an inclusive scan of the
+// per-lane counts) and processed 64 at a time, candidate c on lane c mod 64.
+// Each lane stages its primitive in LDS; a candidate finds its owner by binary
+// search over the scan.  The decisions are those of conic_tile_hit, so counts
+// and emitted tiles are the same as a per-primitive loop's.
+// ---------------------------------------------------------------------------
+struct ConicLane {
+    double C[6];
+    double mx, my;
+    uint64_t base;               // first emission index (emission only)
+    int32_t tx0, ty0, nx, ny;    // tile rectangle, nx * ny candidates (0: none)
+    uint32_t excl, cnt, prim, cok;
+};
+
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// number of lanes whose inclusive count is <= c (the owner of candidate c);
+// every lane of the wave must call it
+__device__ inline int wave_owner(uint32_t incl, uint32_t c)
+{
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(incl, o + step - 1, 64) <= c) o += step;
+    return o;
+}
+
+// bits [lo, hi) of a 64-bit lane mask, clamped to [0, 64)
+__device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
+{
+    lo = lo < 0 ? 0 : (lo > 64 ? 64 : lo);
+    hi = hi < 0 ? 0 : (hi > 64 ? 64 : hi);
+    if (hi <= lo) return 0ull;
+    const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    const uint64_t below_lo = (1ull << lo) - 1ull;
+    return below_hi & ~below_lo;
+}
+
+// Counts (and with EMIT writes) the tiles of each lane's rectangle that pass
+// the conic test (every tile when cok == 0).  s_wave: this wave's 64 LDS
+// entries.  Must be reached by every thread of the workgroup (one barrier).
+// EMIT: a hit of primitive `prim` with rank k among its hits goes to emission
+// index base + k (if k < cnt): out_tile = tile id, out_emit = the index,
+// emit_prim = prim.
+template <bool EMIT>
+__device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &me, const qgs_camera &cam,
+                                            int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t R = (me.nx > 0 && me.ny > 0) ? (uint32_t)me.nx * (uint32_t)me.ny : 0u;
+    const uint32_t incl = wave_incl_scan_u32(R), excl = incl - R;
+    const uint32_t total = __shfl(incl, 63, 64);
+    s_wave[lane] = me;
+    s_wave[lane].excl = excl;
+    __syncthreads();
+    uint32_t hits = 0;
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t c = base + (uint32_t)lane;
+        const int o = wave_owner(incl, c);
+        const uint32_t run_o = EMIT ? __shfl(hits, o & 63, 64) : 0u;
+        bool hit = false;
+        int tx = 0, ty = 0;
+        if (c < total) {
+            const ConicLane &q = s_wave[o];
+            const uint32_t loc = c - q.excl;
+            tx = q.tx0 + (int)(loc % (uint32_t)q.nx);
+            ty = q.ty0 + (int)(loc / (uint32_t)q.nx);
+            hit = q.cok == 0u || conic_tile_hit(q.C, q.mx, q.my, tx, ty, cam);
+        }
+        const uint64_t bal = __ballot(hit);
+        if (EMIT && hit) {
+            const ConicLane &q = s_wave[o];
+            const uint32_t k = run_o + (uint32_t)__popcll(bal & lane_range_mask((int64_t)q.excl - (int64_t)base, lane));
+            if (k < q.cnt) {
+                const uint64_t e = q.base + k;
+                out_tile[e] = (uint32_t)(ty * tiles_x + tx);
+                out_emit[e] = (uint32_t)e;
+                emit_prim[e] = q.prim;
+            }
+        }
+        hits += (uint32_t)__popcll(bal & lane_range_mask((int64_t)excl - (int64_t)base, (int64_t)incl - (int64_t)base));
+    }
+    return hits;
 }
 
 }  // namespace qgs
