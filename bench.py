@@ -185,15 +185,19 @@ def main():
 
     # roofline of the dominant kernel: algorithmic FP32 operations per launch
     # from the forward's pair counts, divided by the kernel's event time
-    evald, blended = [], []
+    evald, blended, wrect, weval = [], [], [], []
     for v in used[: min(8, len(used))]:
         st = cnt_r.forward(sc_t, cams[v], exact=False)
         torch.cuda.synchronize()
         c = st.counters.cpu().numpy().view(np.uint32)
         evald.append(int(c[3]))
         blended.append(int(c[4]))
+        wrect.append(int(c[5]))
+        weval.append(int(c[6]))
     ev = float(np.mean(evald))
     bl = float(np.mean(blended))
+    # forward lane use: intersections evaluated per (wave, entry) step that evaluated any
+    fwd_lane_use = ev / (64.0 * max(1.0, float(np.mean(weval))))
     kern = {"render_fwd": ev * FLOPS_EVAL + bl * FLOPS_BLEND_FWD,
             "render_bwd": bl * (FLOPS_EVAL + FLOPS_BLEND_BWD)}
     dominant = max(stage_ms, key=stage_ms.get)
@@ -202,7 +206,9 @@ def main():
         roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
                     "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
-                    "flops_per_launch": kern[dominant], "pairs_evaluated": ev, "pairs_blended": bl}
+                    "flops_per_launch": kern[dominant], "pairs_evaluated": ev, "pairs_blended": bl,
+                    "fwd_wave_steps_rect": float(np.mean(wrect)), "fwd_wave_steps_eval": float(np.mean(weval)),
+                    "fwd_lane_use": round(fwd_lane_use, 4)}
     else:
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": None, "traffic": None}

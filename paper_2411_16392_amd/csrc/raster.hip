@@ -121,6 +121,13 @@ __device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int 
 // forward
 // ---------------------------------------------------------------------------
 // GEO: also the curvature, median-depth and depth-distortion maps.
+//
+// Each wave walks its tile's list on its own, with no LDS and no barrier: the
+// list is read 64 entries at a time (lane i fetches entry b + i's primitive id
+// and pixel rectangle, one batch ahead), a ballot selects the entries whose
+// rectangle meets the wave's 8 x 8 block, and only those are visited.  A
+// visited entry's record is read with a wave-uniform address, so it is
+// fetched once for the wave (scalar loads) and sits in scalar registers.
 template <bool GEO>
 #if QGS_FWD_MIN_WAVES > 0
 __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
@@ -128,7 +135,6 @@ __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterA
 __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
 #endif
 {
-    __shared__ float4 s_rec[FWD_BATCH * 8];
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
@@ -136,32 +142,49 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t start = a.ranges[2 * tile], n = a.ranges[2 * tile + 1] - start;
     const PixelRay ray = make_ray(px, py, P);
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
-    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
+    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0, w_rect = 0, w_eval = 0;
     bool done = !inside;
     // geometry: curvature sum, median depth and its position, and the running
     // sum of weights, mean depth and distortion
     float kk = 0.0f, med = 0.0f, gW = 0.0f, gm = 0.0f, gL = 0.0f;
     uint32_t med_pos = 0;
 
-    for (uint32_t b0 = start; b0 < end; b0 += FWD_BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
-        const int nb = (int)min((uint32_t)FWD_BATCH, end - b0);
-        load_batch<FWD_BATCH>(a, b0, nb, s_rec, nullptr);
-        __syncthreads();
-        bool wave_alive = __ballot(!done) != 0ull;
-        for (int j = 0; j < nb && wave_alive; ++j) {
-            const float4 rr = s_rec[j * 8];
-            const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
-            const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
-            if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
-            const float *w = reinterpret_cast<const float *>(&s_rec[j * 8]);
+    // batch fetch: lane i holds entry b + i's primitive and rectangle
+    uint32_t nxt_pid = 0;
+    int4 nxt_rect = make_int4(0, -1, 0, -1);
+    if ((uint32_t)lane < n) {
+        nxt_pid = a.pair_prim[start + lane];
+        nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+    }
+    bool wave_alive = __ballot(!done) != 0ull;
+    for (uint32_t b = 0; b < n && wave_alive; b += 64) {
+        const uint32_t cur_pid = nxt_pid;
+        const int4 cur_rect = nxt_rect;
+        if (b + 64 + (uint32_t)lane < n) {
+            nxt_pid = a.pair_prim[start + b + 64 + lane];
+            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        }
+        const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                       cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        uint64_t m = __ballot(rel);
+        while (m != 0ull && wave_alive) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1ull;
+            ++w_rect;
+            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
+            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
             float dxp, dyp;
             const bool lane_on = !done && px >= x0 && px <= x1 && py >= y0 && py <= y1 && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
+            ++w_eval;
+            const uint32_t pos1 = b + (uint32_t)j + 1u;
             if (lane_on) {
                 Prim p;
                 load_prim(w, P, p);
@@ -174,24 +197,23 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                         const float Tn = T * (1.0f - alpha);
                         if (Tn < P.T_eps) {
                             done = true;
-                            stop_pos = b0 - start + (uint32_t)j + 1u;
+                            stop_pos = pos1;
                         } else {
-                            const float w = alpha * T;
-                            const float4 cr = s_rec[j * 8 + 6];
-                            c0 = __builtin_fmaf(w, cr.y, c0);
-                            c1 = __builtin_fmaf(w, cr.z, c1);
-                            c2 = __builtin_fmaf(w, cr.w, c2);
+                            const float wgt = alpha * T;
+                            const float4 cr = *reinterpret_cast<const float4 *>(w + 24);
+                            c0 = __builtin_fmaf(wgt, cr.y, c0);
+                            c1 = __builtin_fmaf(wgt, cr.z, c1);
+                            c2 = __builtin_fmaf(wgt, cr.w, c2);
                             const float t = (p.Zc + H.s) * ray.enorm;
-                            dep = __builtin_fmaf(w, t, dep);
+                            dep = __builtin_fmaf(wgt, t, dep);
                             float nl[3], il;
                             const float f = hit_normal(p, H, nl, il);
-                            const float wf = w * f;
+                            const float wf = wgt * f;
                             n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
                             n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
                             n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
-                            const uint32_t pos1 = b0 - start + (uint32_t)j + 1u;
                             if (GEO) {
-                                kk = __builtin_fmaf(w, hit_curvature(p, il), kk);
+                                kk = __builtin_fmaf(wgt, hit_curvature(p, il), kk);
                                 if (T > 0.5f && (med_pos == 0u || t > med)) {
                                     med = t;
                                     med_pos = pos1;
@@ -199,9 +221,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                                 // L += w (L / W + W (t - mean)^2); W += w; mean += w (t - mean) / W
                                 const float dtm = t - gm;
                                 const float Xd = gW > 0.0f ? __builtin_fmaf(gW * dtm, dtm, gL * __builtin_amdgcn_rcpf(gW)) : 0.0f;
-                                gL = __builtin_fmaf(w, Xd, gL);
-                                gW += w;
-                                gm = __builtin_fmaf(w * __builtin_amdgcn_rcpf(gW), dtm, gm);
+                                gL = __builtin_fmaf(wgt, Xd, gL);
+                                gW += wgt;
+                                gm = __builtin_fmaf(wgt * __builtin_amdgcn_rcpf(gW), dtm, gm);
                             }
                             T = Tn;
                             last = pos1;
@@ -212,7 +234,6 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             }
             wave_alive = __ballot(!done) != 0ull;
         }
-        __syncthreads();
     }
 
     if (inside) {
@@ -236,7 +257,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     if (o.counters) {
         // list entries processed per pixel (up to and including a stop),
         // intersections evaluated, pairs blended
-        uint32_t c[3] = {inside ? (stop_pos ? stop_pos : end - start) : 0u, n_eval, n_blend};
+        uint32_t c[3] = {inside ? (stop_pos ? stop_pos : n) : 0u, n_eval, n_blend};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             uint32_t v = c[k];
@@ -244,6 +265,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0 && v) atomicAdd(o.counters + 2 + k, v);
         }
+        // per-wave step counts (the same in every lane)
+        if (lane == 0 && w_rect) atomicAdd(o.counters + 5, w_rect);
+        if (lane == 0 && w_eval) atomicAdd(o.counters + 6, w_eval);
     }
 }
 
