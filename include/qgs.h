@@ -215,7 +215,7 @@ void qgs_default_opts(qgs_render_opts *opts);
  * Host-only size query.  For n primitives, a camera and a pair capacity:
  *  sort_ws_bytes  workspace of qgs_bin_sort
  *  bwd_ws_bytes   workspace of qgs_render_bwd for `flags` (QGS_DETERMINISTIC_BWD
- *                 adds capacity * 64 bytes)
+ *                 adds capacity * 256 bytes: one partial per pair and 8 x 8 block)
  * Any output pointer may be NULL.
  */
 qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t pair_capacity, uint32_t flags,

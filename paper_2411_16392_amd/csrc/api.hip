@@ -110,7 +110,8 @@ size_t bwd_bytes(int64_t n, uint64_t capacity, uint32_t flags)
 {
     size_t b = (size_t)(n > 0 ? n : 1) * 64;
     b = (b + 255) & ~(size_t)255;
-    if (flags & QGS_DETERMINISTIC_BWD) b += (size_t)(capacity > 0 ? capacity : 1) * 64;
+    // deterministic mode: one 16-float partial per (pair, wave of the tile)
+    if (flags & QGS_DETERMINISTIC_BWD) b += (size_t)(capacity > 0 ? capacity : 1) * 256;
     return b;
 }
 

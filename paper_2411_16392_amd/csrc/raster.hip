@@ -1,23 +1,24 @@
 // Tile rasterizer, forward and backward.
 //
 // One 256-thread workgroup (four wave64s) per 16 x 16 tile; wave w owns the
-// 8 x 8 quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) in it, so a
-// wave's pixels are a compact square and a primitive whose pixel rectangle
-// misses the square is skipped by the whole wave with one scalar test.  The
-// tile's list is walked in batches of records staged in LDS: 8 consecutive
-// threads copy one 128-byte record with 16-byte loads, so every global load
-// instruction moves whole, aligned 128-byte lines.
+// 8 x 8 block (w & 1, w >> 1) of the tile, lane l the pixel (l & 7, l >> 3) in
+// it.  The waves walk the tile's list independently, without LDS or barriers:
+// 64 entries at a time, lane i fetches entry b + i's primitive id and pixel
+// rectangle (one batch ahead), a ballot keeps the entries whose rectangle
+// meets the wave's block, and only those are visited.  A visited entry's
+// 128-byte record is read with a wave-uniform address, i.e. by scalar loads
+// into scalar registers, once per wave.  Each lane first applies the conic
+// pre-test; the intersection runs only if some lane passes it.
 //
-// Forward (Eq. 1, compositing front to back): a wave stops computing once
-// every lane is done (ballot), the workgroup once every wave is.
+// Forward (Eq. 1, compositing front to back): a wave stops once every lane is
+// done (ballot).
 // Backward (supplement, back-to-front adjoint): each pixel starts at its last
 // blended entry, recovers T_i = T_{i+1} / (1 - alpha_i), and keeps the suffix
 // sum S_i = sum_{j>i} w_j X_j + T_final bg, so dX/dalpha_i = T_i X_i - S_i /
-// (1 - alpha_i).  Per-primitive gradients are summed over the wave with a
-// butterfly, then over the four waves in LDS, then added to global memory with
-// one atomic per field per (tile, primitive); the deterministic variant keeps
-// per-wave partials, sums them in wave order and stores one partial per pair for
-// a fixed-order second pass.
+// (1 - alpha_i).  A visited entry's 14 per-primitive gradient fields are
+// reduce-scattered over the wave and added to global memory by 14 lanes with
+// one atomic instruction; the deterministic variant stores them into the
+// pair's slot for the wave and a second pass sums the slots in a fixed order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,14 +27,7 @@
 
 #pragma clang fp contract(off)
 
-// Records staged per LDS batch (forward, backward) and the minimum number of
-// waves per SIMD the compiler is asked to fit (0: no request).
-#ifndef QGS_FWD_BATCH
-#define QGS_FWD_BATCH 256
-#endif
-#ifndef QGS_BWD_BATCH
-#define QGS_BWD_BATCH 256
-#endif
+// Minimum number of waves per SIMD the compiler is asked to fit (0: no request).
 #ifndef QGS_FWD_MIN_WAVES
 #define QGS_FWD_MIN_WAVES 0
 #endif
@@ -42,10 +36,6 @@
 #endif
 
 namespace qgs {
-
-constexpr int FWD_BATCH = QGS_FWD_BATCH;
-constexpr int BWD_BATCH = QGS_BWD_BATCH;
-static_assert(FWD_BATCH % 32 == 0 && FWD_BATCH <= 256 && BWD_BATCH % 32 == 0 && BWD_BATCH <= 256, "batch size");
 
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ inline float dpp_f(float v)
@@ -99,22 +89,6 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
         v = w > v ? w : v;
     }
     return v;
-}
-
-template <int NBATCH>
-__device__ inline void load_batch(const RasterArgs &a, uint32_t list_begin, int nb, float4 *s_rec, uint32_t *s_pid)
-{
-    const int tid = threadIdx.x;
-    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
-#pragma unroll
-    for (int r = 0; r < NBATCH * 8 / BLOCK; ++r) {
-        const int slot = r * (BLOCK / 8) + (tid >> 3), k = tid & 7;
-        if (slot < nb) {
-            const uint32_t pid = a.pair_prim[list_begin + slot];
-            s_rec[slot * 8 + k] = recs[(size_t)pid * 8 + k];
-            if (s_pid && k == 0) s_pid[slot] = pid;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -408,22 +382,27 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     gr[G_PHI2] += dphi2;
 }
 
+// The backward walks each wave's entries from its pixels' largest `last` down
+// to the first, with the same per-wave list reading as the forward.  A
+// visited entry's per-lane gradients are reduce-scattered over the wave, and
+// the 14 field totals go to memory from 14 lanes in one instruction: atomic
+// adds into the primitive's record gradient, or (DET) a store into the pair's
+// slot for this wave, summed later in a fixed order.
 template <bool DET, bool GEO>
+// `recs` is a.records again, as a restrict argument: the records are never
+// written here, which lets the compiler read them with scalar loads although
+// the loop stores gradients.
 #if QGS_BWD_MIN_WAVES > 0
 __global__ __launch_bounds__(BLOCK, QGS_BWD_MIN_WAVES) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
-                                                                         float *grad_rec, float *pair_scratch)
+                                                                         const float4 *__restrict__ recs,
+                                                                         float *__restrict__ grad_rec,
+                                                                         float *__restrict__ pair_scratch)
 #else
-__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in, float *grad_rec,
-                                                      float *pair_scratch)
+__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
+                                                      const float4 *__restrict__ recs, float *__restrict__ grad_rec,
+                                                      float *__restrict__ pair_scratch)
 #endif
 {
-    constexpr int NB = DET ? 64 : BWD_BATCH;
-    constexpr int NACC = DET ? 4 : 1;
-    __shared__ float4 s_rec[NB * 8];
-    __shared__ uint32_t s_pid[NB];
-    __shared__ float s_acc[NACC][NB][NGRAD];
-    __shared__ uint32_t s_maxlast;
-
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
@@ -433,7 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     const bool inside = px < P.width && py < P.height;
     const uint32_t start = a.ranges[2 * tile], list_len = a.ranges[2 * tile + 1] - start;
     const PixelRay ray = make_ray(px, py, P);
-
+    
     const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
     float T = 1.0f, gc[3] = {0, 0, 0}, gd = 0.0f, gn[3] = {0, 0, 0};
     uint32_t last = 0;
@@ -475,38 +454,36 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     float S[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) S[c] = c < 3 ? T * P.bg[c] : 0.0f;
-    const uint32_t wmax = wave_max_u32(last);
-    if (tid == 0) s_maxlast = 0;
-    __syncthreads();
-    if (lane == 0) atomicMax(&s_maxlast, wmax);
-    __syncthreads();
     // never walk past the tile's list, whatever `last` holds
-    const uint32_t nmax = s_maxlast < list_len ? s_maxlast : list_len;
+    const uint32_t wmax = wave_max_u32(last);
+    const uint32_t nmax = wmax < list_len ? wmax : list_len;
 
-    for (int32_t hi = (int32_t)nmax; hi > 0; hi -= NB) {
-        const int32_t lo = hi - NB > 0 ? hi - NB : 0;
-        const int nb = hi - lo;
-        // stage records and clear accumulators
-#pragma unroll
-        for (int r = 0; r < (NB * 8 + BLOCK - 1) / BLOCK; ++r) {
-            const int slot = r * (BLOCK / 8) + (tid >> 3), k = tid & 7;
-            if (slot < nb) {
-                const uint32_t pid = a.pair_prim[start + lo + slot];
-                s_rec[slot * 8 + k] = reinterpret_cast<const float4 *>(a.records)[(size_t)pid * 8 + k];
-                if (k == 0) s_pid[slot] = pid;
-            }
+    // batch fetch, backwards: lane i holds entry lo + i of [lo, lo + 64)
+    uint32_t nxt_pid = 0;
+    int4 nxt_rect = make_int4(0, -1, 0, -1);
+    int32_t lo = ((int32_t)nmax - 1) & ~63;  // first batch: the one holding entry nmax - 1
+    if (nmax > 0 && (uint32_t)(lo + lane) < nmax) {
+        nxt_pid = a.pair_prim[start + lo + lane];
+        nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+    }
+    for (; nmax > 0 && lo >= 0; lo -= 64) {
+        const uint32_t cur_pid = nxt_pid;
+        const int4 cur_rect = nxt_rect;
+        if (lo >= 64) {
+            nxt_pid = a.pair_prim[start + lo - 64 + lane];
+            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
         }
-        for (int i = tid; i < NACC * NB * NGRAD; i += BLOCK) (&s_acc[0][0][0])[i] = 0.0f;
-        __syncthreads();
-
-        for (int j = nb - 1; j >= 0; --j) {
+        const bool rel = (uint32_t)(lo + lane) < nmax && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                         cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        uint64_t m = __ballot(rel);
+        while (m != 0ull) {
+            const int j = 63 - __builtin_clzll(m);
+            m &= ~(1ull << j);
             const uint32_t pos = (uint32_t)(lo + j);
-            if (pos >= wmax) continue;
-            const float4 rr = s_rec[j * 8];
-            const int x0 = __float_as_int(rr.x), x1 = __float_as_int(rr.y);
-            const int y0 = __float_as_int(rr.z), y1 = __float_as_int(rr.w);
-            if (x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7) continue;
-            const float *wr = reinterpret_cast<const float *>(&s_rec[j * 8]);
+            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+            const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
+            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
             float dxp, dyp;
             const bool lane_on = pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
                                  conic_offsets(wr, ray, dxp, dyp);
@@ -524,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
                         contrib = true;
-                        const float4 cr = s_rec[j * 8 + 6];
+                        const float4 cr = *reinterpret_cast<const float4 *>(wr + 24);
                         const float rgb[3] = {cr.y, cr.z, cr.w};
                         const float om = 1.0f - alpha;
                         const float iom = __builtin_amdgcn_rcpf(om);
@@ -571,39 +548,18 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                 const int f = lane >> 2;
                 if ((lane & 3) == 0 && f < NGRAD) {
                     if (DET)
-                        s_acc[DET ? wave : 0][j][f] = tot;
+                        pair_scratch[((size_t)start + pos) * 64 + wave * 16 + f] = tot;
                     else if (tot != 0.0f)
-                        atomicAdd(&s_acc[0][j][f], tot);
+                        unsafeAtomicAdd(grad_rec + (size_t)pj * 16 + f, tot);
                 }
             }
         }
-        __syncthreads();
-        // one global update per field per (tile, primitive)
-        for (int slot = tid; slot < nb; slot += BLOCK) {
-            const uint32_t pid = s_pid[slot];
-            if (DET) {
-                float *dst = pair_scratch + ((size_t)start + lo + slot) * 16;
-#pragma unroll
-                for (int f = 0; f < NGRAD; ++f) {
-                    float v = s_acc[0][slot][f];
-                    for (int w = 1; w < NACC; ++w) v += s_acc[w][slot][f];
-                    dst[f] = v;
-                }
-            } else {
-                float *dst = grad_rec + (size_t)pid * 16;
-#pragma unroll
-                for (int f = 0; f < NGRAD; ++f) {
-                    const float v = s_acc[0][slot][f];
-                    if (v != 0.0f) unsafeAtomicAdd(dst + f, v);
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 
 // deterministic second pass: sum each primitive's per-pair partials in
-// emission order (its pairs are pair_offset[p] ... + tiles[p] - 1 there)
+// emission order (its pairs are pair_offset[p] ... + tiles[p] - 1 there),
+// each pair's four per-wave slots in wave order
 __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, const uint32_t *pair_offset,
                                                     const uint32_t *tiles, const uint32_t *emit_to_sorted, int64_t n,
                                                     float *grad_rec)
@@ -615,9 +571,10 @@ __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, c
     for (int f = 0; f < NGRAD; ++f) acc[f] = 0.0f;
     const uint32_t cnt = tiles[p], e0 = pair_offset[p];
     for (uint32_t k = 0; k < cnt; ++k) {
-        const float *src = pair_scratch + (size_t)emit_to_sorted[e0 + k] * 16;
+        const float *src = pair_scratch + (size_t)emit_to_sorted[e0 + k] * 64;
+        for (int wv = 0; wv < 4; ++wv)
 #pragma unroll
-        for (int f = 0; f < NGRAD; ++f) acc[f] += src[f];
+            for (int f = 0; f < NGRAD; ++f) acc[f] += src[16 * wv + f];
     }
 #pragma unroll
     for (int f = 0; f < NGRAD; ++f) grad_rec[16 * p + f] = acc[f];
@@ -645,24 +602,24 @@ hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const B
     if (ntiles == 0) return hipSuccess;
     const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
     if (pair_scratch) {
-        e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 16, stream);
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
         if (e != hipSuccess) return e;
         if (geo)
-            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
-                               pair_scratch);
+            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                               reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
         else
-            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
-                               pair_scratch);
+            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                               reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
         if (n_prims > 0)
             hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
                                (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
                                grad_rec);
     } else if (geo) {
-        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
-                           pair_scratch);
+        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                           reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
     } else {
-        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, grad_rec,
-                           pair_scratch);
+        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                           reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
     }
     return hipGetLastError();
 }
