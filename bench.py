@@ -185,7 +185,7 @@ def main():
 
     # roofline of the dominant kernel: algorithmic FP32 operations per launch
     # from the forward's pair counts, divided by the kernel's event time
-    evald, blended, wrect, weval = [], [], [], []
+    evald, blended, wrect, weval, wblend = [], [], [], [], []
     for v in used[: min(8, len(used))]:
         st = cnt_r.forward(sc_t, cams[v], exact=False)
         torch.cuda.synchronize()
@@ -194,6 +194,7 @@ def main():
         blended.append(int(c[4]))
         wrect.append(int(c[5]))
         weval.append(int(c[6]))
+        wblend.append(int(c[7]))
     ev = float(np.mean(evald))
     bl = float(np.mean(blended))
     # forward lane use: intersections evaluated per (wave, entry) step that evaluated any
@@ -208,6 +209,7 @@ def main():
                     "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
                     "flops_per_launch": kern[dominant], "pairs_evaluated": ev, "pairs_blended": bl,
                     "fwd_wave_steps_rect": float(np.mean(wrect)), "fwd_wave_steps_eval": float(np.mean(weval)),
+                    "fwd_wave_steps_blend": float(np.mean(wblend)),
                     "fwd_lane_use": round(fwd_lane_use, 4)}
     else:
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",

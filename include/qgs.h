@@ -89,7 +89,7 @@ typedef struct qgs_render_opts {
 
 #define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */
 #define QGS_ACCUMULATE_GRADS  2u /* backward: add into qgs_scene_grads instead of overwriting */
-#define QGS_COUNT_EVALS       4u /* forward: work counters into counters[2..6] */
+#define QGS_COUNT_EVALS       4u /* forward: work counters into counters[2..7] */
 
 /*
  * Per-primitive preprocess output (device memory, caller-allocated, n entries).
@@ -144,7 +144,8 @@ typedef struct qgs_prim_buf {
  *                        intersection was evaluated, [4] pairs blended, [5]
  *                        (wave, entry) steps whose rectangle meets the wave's
  *                        8 x 8 pixel block, [6] steps in which at least one lane
- *                        evaluated an intersection; [7] reserved.
+ *                        evaluated an intersection, [7] steps in which at least
+ *                        one lane blended.
  *                        qgs_bin_sort resets [2..7] to zero.
  */
 typedef struct qgs_tile_lists {

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     const float4 *recs = reinterpret_cast<const float4 *>(a.records);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
-    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0, w_rect = 0, w_eval = 0;
+    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0, w_rect = 0, w_eval = 0, w_blend = 0;
     bool done = !inside;
     // geometry: curvature sum, median depth and its position, and the running
     // sum of weights, mean depth and distortion
@@ -206,6 +206,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                     }
                 }
             }
+            if (o.counters) w_blend += __ballot(last == pos1) != 0ull ? 1u : 0u;
             wave_alive = __ballot(!done) != 0ull;
         }
     }
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         // per-wave step counts (the same in every lane)
         if (lane == 0 && w_rect) atomicAdd(o.counters + 5, w_rect);
         if (lane == 0 && w_eval) atomicAdd(o.counters + 6, w_eval);
+        if (lane == 0 && w_blend) atomicAdd(o.counters + 7, w_blend);
     }
 }
 
