@@ -128,9 +128,13 @@ typedef struct qgs_prim_buf {
  * Sorted tile lists (device memory, caller-allocated).
  *  pair_tile, pair_prim  [capacity] tile id and primitive index of each pair,
  *                        sorted by (tile, depth key, primitive index)
- *  emit_to_sorted        [capacity] position in the sorted list of each pair,
- *                        indexed by emission order (primitive p's pairs are
- *                        pair_offset[p] ... pair_offset[p] + tiles[p] - 1)
+ *  emit_to_sorted        optional (NULL: not built): [capacity] position in
+ *                        the sorted list of each pair, indexed by emission
+ *                        order (primitive p's pairs are pair_offset[p] ...
+ *                        pair_offset[p] + tiles[p] - 1).  The deterministic
+ *                        backward needs it, and it must then have been set for
+ *                        the qgs_bin_sort that built the lists; building it
+ *                        costs a random gather and scatter over all pairs.
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
  *  tile_order            [tiles_x * tiles_y] tiles by decreasing list length
  *                        (log2 buckets): the order in which the rasterizer's

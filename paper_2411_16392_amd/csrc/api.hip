@@ -59,7 +59,7 @@ bool lists_ok(const qgs_tile_lists *l)
 {
     if (!l || !l->ranges || !l->counters) return false;
     if (l->capacity > 0xFFFFFFFFull) return false;
-    if (l->capacity > 0 && (!l->pair_tile || !l->pair_prim || !l->emit_to_sorted)) return false;
+    if (l->capacity > 0 && (!l->pair_tile || !l->pair_prim)) return false;
     return true;
 }
 
@@ -265,6 +265,7 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     const bool geo = dL->dcurvature || dL->dmedian_depth || dL->ddistortion;
     if (geo && (!fwd->depth || !fwd->distortion || !fwd->median_pos)) return QGS_ERR_INVALID_ARG;
     const bool det = (opts->flags & QGS_DETERMINISTIC_BWD) != 0;
+    if (det && lists->capacity > 0 && !lists->emit_to_sorted) return QGS_ERR_INVALID_ARG;
     if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags)) return QGS_ERR_WORKSPACE;
     float *grad_rec = reinterpret_cast<float *>(ws);
     size_t off = ((size_t)(scene->n > 0 ? scene->n : 1) * 64 + 255) & ~(size_t)255;

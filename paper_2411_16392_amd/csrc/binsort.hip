@@ -25,9 +25,16 @@
 namespace qgs {
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;  // elements per block
+// elements per thread of a radix block: small for the per-primitive depth
+// sort (more blocks for a small array), large for the per-pair tile sort
+constexpr int RS_ITEMS_DEPTH = (int)(DEPTH_SORT_CHUNK / RS_THREADS);
+constexpr int RS_ITEMS_TILE = (int)(TILE_SORT_CHUNK / RS_THREADS);
+static_assert(RS_ITEMS_DEPTH * RS_THREADS == (int)DEPTH_SORT_CHUNK && RS_ITEMS_TILE * RS_THREADS == (int)TILE_SORT_CHUNK,
+              "radix chunks");
 constexpr int SCAN_CHUNK = 4096;
+// arrays up to this size are scanned by a single workgroup (one kernel
+// instead of three; a workgroup's sequential chunks are slow for more)
+constexpr uint64_t SCAN_SINGLE_MAX = 8192;
 
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
@@ -130,11 +137,39 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_
     }
 }
 
+// exclusive scan of a small array by one 1024-thread workgroup: each thread
+// sums a contiguous chunk, the chunk sums are scanned, each chunk is rewritten
+// (in == out allowed)
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_single(const T *in, T *out, uint64_t n)
+{
+    __shared__ T s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t per = (n + 1023) / 1024;
+    const uint64_t b = (uint64_t)tid * per, e = b + per < n ? b + per : n;
+    T acc = 0;
+    for (uint64_t i = b; i < e; ++i) acc += in[i];
+    const T inc = wave_incl_scan(acc, lane);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    T run = inc - acc;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (uint64_t i = b; i < e; ++i) {
+        const T v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
 template <typename T>
 static hipError_t device_excl_scan(const T *in, T *out, uint64_t n, T *part, T *grand_total, hipStream_t stream)
 {
     const uint64_t nb = cdiv(n, SCAN_CHUNK);
     if (nb == 0) return hipSuccess;
+    if (n <= SCAN_SINGLE_MAX && !grand_total) {
+        hipLaunchKernelGGL(k_scan_single<T>, dim3(1), dim3(1024), 0, stream, in, out, n);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_partials<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, n, part);
     hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(256), 0, stream, part, nb, grand_total);
     hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, out, n, (const T *)part);
@@ -144,9 +179,11 @@ static hipError_t device_excl_scan(const T *in, T *out, uint64_t n, T *part, T *
 // ---------------------------------------------------------------------------
 // radix pass kernels (u32 keys, u32 values, 8-bit digit at `shift`)
 // ---------------------------------------------------------------------------
+template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t *keys, Count cnt, int shift, uint32_t *hist,
                                                            uint32_t nblocks)
 {
+    constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     __shared__ uint32_t h[4][256];
     for (int i = threadIdx.x; i < 1024; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
@@ -162,10 +199,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t *keys,
     hist[(uint64_t)d * nblocks + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
+template <int RS_ITEMS>
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
                                                               uint32_t *keys_out, uint32_t *vals_out, Count cnt,
                                                               int shift, const uint32_t *hist_scan, uint32_t nblocks)
 {
+    constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
     __shared__ uint32_t s_keys[RS_CHUNK];
     __shared__ uint32_t s_vals[RS_CHUNK];
     __shared__ uint32_t wcnt[4][256];
@@ -237,18 +276,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *ke
 }
 
 // one stable 8-bit pass; grid sized for `bound` elements
+template <int RS_ITEMS>
 static hipError_t radix_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, Count cnt,
                              uint64_t bound, int shift, const SortWorkspace &ws, hipStream_t stream)
 {
-    const uint64_t nb = cdiv(bound, RS_CHUNK);
+    const uint64_t nb = cdiv(bound, (uint64_t)RS_THREADS * RS_ITEMS);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, cnt, shift, ws.hist,
-                       (uint32_t)nb);
+    hipLaunchKernelGGL(k_radix_hist<RS_ITEMS>, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, cnt, shift,
+                       ws.hist, (uint32_t)nb);
     hipError_t e = device_excl_scan<uint32_t>(ws.hist, ws.hist, 256 * nb, reinterpret_cast<uint32_t *>(ws.part),
                                               (uint32_t *)nullptr, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, vi, ko, vo, cnt, shift,
-                       (const uint32_t *)ws.hist, (uint32_t)nb);
+    hipLaunchKernelGGL(k_radix_scatter<RS_ITEMS>, dim3((unsigned)nb), dim3(RS_THREADS), 0, stream, ki, vi, ko, vo,
+                       cnt, shift, (const uint32_t *)ws.hist, (uint32_t)nb);
     return hipGetLastError();
 }
 
@@ -293,10 +333,13 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t *order, con
     pair_offset[order[r]] = o > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)o;
 }
 
-// One thread per primitive, in depth order: emits the (tile, emission index)
-// pairs of the tiles of its rectangle that pass the conic test, row-major,
-// at its offset, and records each pair's primitive.  The decisions are those
-// the preprocess counted with the same test.
+// Primitives in depth order (one per thread, the tests spread over the wave):
+// emits the pairs of the tiles of each rectangle that pass the conic test,
+// row-major, at the primitive's offset.  The value of a pair is its emission
+// index (EMIT_INDEX, with emit_prim[e] = its primitive, for the emission map)
+// or directly its primitive.  The decisions are those the preprocess counted
+// with the same test.
+template <bool EMIT_INDEX>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
                                               const double *conic, int64_t n, qgs_camera cam, int32_t tiles_x,
                                               const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
@@ -324,7 +367,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
             cl.ny = rc[3] - rc[1] + 1;
         }
     }
-    (void)wave_conic_tiles<true>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit, emit_prim);
+    (void)wave_conic_tiles<true, EMIT_INDEX>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit,
+                                             emit_prim);
 }
 
 // After the sort the values are emission indices: replace them by primitive
@@ -399,7 +443,9 @@ SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
 {
     SortWorkspace w{};
     const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
-    const uint64_t nbmax = cdiv(nn > capacity ? nn : capacity, RS_CHUNK) + 1;
+    const uint64_t nb_depth = cdiv(nn, (uint64_t)RS_THREADS * RS_ITEMS_DEPTH);
+    const uint64_t nb_tile = cdiv(capacity > 0 ? capacity : 1, (uint64_t)RS_THREADS * RS_ITEMS_TILE);
+    const uint64_t nbmax = (nb_depth > nb_tile ? nb_depth : nb_tile) + 1;
     const uint64_t nparts = cdiv(nn + 1, SCAN_CHUNK) + cdiv(256 * nbmax, SCAN_CHUNK) + 64;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -430,13 +476,13 @@ hipError_t bin_sort_phase1(const BinSortArgs &a, const SortWorkspace &ws, hipStr
         // 4 stable passes over the 32-bit depth keys: A -> B -> A -> B -> A
         Count c{nullptr, (uint64_t)n};
         hipError_t e;
-        e = radix_pass(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 0, ws, stream);
+        e = radix_pass<RS_ITEMS_DEPTH>(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 0, ws, stream);
         if (e != hipSuccess) return e;
-        e = radix_pass(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 8, ws, stream);
+        e = radix_pass<RS_ITEMS_DEPTH>(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 8, ws, stream);
         if (e != hipSuccess) return e;
-        e = radix_pass(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 16, ws, stream);
+        e = radix_pass<RS_ITEMS_DEPTH>(ws.dkA, ws.dvA, ws.dkB, ws.dvB, c, n, 16, ws, stream);
         if (e != hipSuccess) return e;
-        e = radix_pass(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 24, ws, stream);
+        e = radix_pass<RS_ITEMS_DEPTH>(ws.dkB, ws.dvB, ws.dkA, ws.dvA, c, n, 24, ws, stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_gather_tiles, dim3(pb), dim3(256), 0, stream, ws.dvA, a.tiles, n, ws.off);
         e = device_excl_scan<uint64_t>(ws.off, ws.off, (uint64_t)n, ws.part, ws.off + n, stream);
@@ -482,20 +528,26 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
     // emit into the buffer that makes the final pass land in the caller's lists
     uint32_t *et = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
     uint32_t *ep = (passes % 2 == 0) ? a.pair_prim : ws.primT;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA, ws.off, a.rect,
-                       a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
+    const bool emit_map = a.emit_to_sorted != nullptr;
+    if (emit_map)
+        hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA, ws.off,
+                           a.rect, a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
+    else
+        hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA,
+                           ws.off, a.rect, a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
     Count c{a.counters, bound};
     uint32_t *ki = et, *vi = ep;
     for (int pass = 0; pass < passes; ++pass) {
         uint32_t *ko = (ki == a.pair_tile) ? ws.tileT : a.pair_tile;
         uint32_t *vo = (vi == a.pair_prim) ? ws.primT : a.pair_prim;
-        e = radix_pass(ki, vi, ko, vo, c, bound, 8 * pass, ws, stream);
+        e = radix_pass<RS_ITEMS_TILE>(ki, vi, ko, vo, c, bound, 8 * pass, ws, stream);
         if (e != hipSuccess) return e;
         ki = ko;
         vi = vo;
     }
-    hipLaunchKernelGGL(k_gather_prims, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream,
-                       (const uint32_t *)ws.emit_prim, c, a.pair_prim, a.emit_to_sorted);
+    if (emit_map)
+        hipLaunchKernelGGL(k_gather_prims, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream,
+                           (const uint32_t *)ws.emit_prim, c, a.pair_prim, a.emit_to_sorted);
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream, (const uint32_t *)a.pair_tile,
                        c, a.ranges, (uint32_t)ntiles);
     return hipGetLastError();

@@ -43,6 +43,12 @@ hipError_t launch_preprocess_bwd(const PreprocessBwdArgs &a, hipStream_t stream)
 
 // ---- bin / sort --------------------------------------------------------------
 
+// Elements per block of the radix passes: the per-primitive depth sort and
+// the per-pair tile sort.  A pass over m elements uses a count table of
+// 256 * ceil(m / chunk) entries (SortWorkspace::hist).
+constexpr uint64_t DEPTH_SORT_CHUNK = 1024;
+constexpr uint64_t TILE_SORT_CHUNK = 4096;
+
 struct SortWorkspace {
     uint32_t *dkA, *dvA, *dkB, *dvB;  // depth keys / primitive ids, ping-pong [n]
     uint64_t *off;                    // [n + 1] pair offsets in depth order

@@ -110,9 +110,9 @@ __device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
 // the conic test (every tile when cok == 0).  s_wave: this wave's 64 LDS
 // entries.  Must be reached by every thread of the workgroup (one barrier).
 // EMIT: a hit of primitive `prim` with rank k among its hits goes to emission
-// index base + k (if k < cnt): out_tile = tile id, out_emit = the index,
-// emit_prim = prim.
-template <bool EMIT>
+// index base + k (if k < cnt): out_tile = tile id, and out_emit = the index
+// with emit_prim = prim (EMIT_INDEX), or out_emit = prim.
+template <bool EMIT, bool EMIT_INDEX = true>
 __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &me, const qgs_camera &cam,
                                             int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim)
 {
@@ -144,8 +144,12 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
             if (k < q.cnt) {
                 const uint64_t e = q.base + k;
                 out_tile[e] = (uint32_t)(ty * tiles_x + tx);
-                out_emit[e] = (uint32_t)e;
-                emit_prim[e] = q.prim;
+                if (EMIT_INDEX) {
+                    out_emit[e] = (uint32_t)e;
+                    emit_prim[e] = q.prim;
+                } else {
+                    out_emit[e] = q.prim;
+                }
             }
         }
         hits += (uint32_t)__popcll(bal & lane_range_mask((int64_t)excl - (int64_t)base, (int64_t)incl - (int64_t)base));

@@ -564,7 +564,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
 // each pair's four per-wave slots in wave order
 __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, const uint32_t *pair_offset,
                                                     const uint32_t *tiles, const uint32_t *emit_to_sorted, int64_t n,
-                                                    float *grad_rec)
+                                                    uint64_t capacity, float *grad_rec)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -573,7 +573,10 @@ __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, c
     for (int f = 0; f < NGRAD; ++f) acc[f] = 0.0f;
     const uint32_t cnt = tiles[p], e0 = pair_offset[p];
     for (uint32_t k = 0; k < cnt; ++k) {
-        const float *src = pair_scratch + (size_t)emit_to_sorted[e0 + k] * 64;
+        if ((uint64_t)e0 + k >= capacity) break;  // cannot happen for lists built here
+        const uint32_t i = emit_to_sorted[e0 + k];
+        if (i >= capacity) continue;  // cannot happen for lists built with the map
+        const float *src = pair_scratch + (size_t)i * 64;
         for (int wv = 0; wv < 4; ++wv)
 #pragma unroll
             for (int f = 0; f < NGRAD; ++f) acc[f] += src[16 * wv + f];
@@ -615,7 +618,7 @@ hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const B
         if (n_prims > 0)
             hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
                                (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
-                               grad_rec);
+                               capacity, grad_rec);
     } else if (geo) {
         hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
                            reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);

@@ -38,8 +38,10 @@ uint64_t cdiv64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 size_t list_bytes(uint64_t pairs)
 {
     const uint64_t c = pairs > 0 ? pairs : 1;
-    const uint64_t nb = cdiv64(c, 4096) + 1;
-    return 6 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, 4096) + 64));
+    const uint64_t nb = cdiv64(c, TILE_SORT_CHUNK) + 1;
+    // pair_tile, pair_prim and their two sort buffers (no emission map: the
+    // server runs no deterministic backward)
+    return 4 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, 4096) + 64));
 }
 
 enum Phase { IDLE = 0, COUNTING = 1, WAITING = 2, RENDERING = 3 };
@@ -177,7 +179,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
 {
     Req &r = *sl.req;
     const uint64_t c = r.pairs > 0 ? r.pairs : 1;
-    const uint64_t nb = cdiv64(c, 4096) + 1;
+    const uint64_t nb = cdiv64(c, TILE_SORT_CHUNK) + 1;
     char *base = (char *)s->pool_base + r.mem_off;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -187,17 +189,16 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     };
     uint32_t *pair_tile = (uint32_t *)take(4 * c);
     uint32_t *pair_prim = (uint32_t *)take(4 * c);
-    uint32_t *emit_to_sorted = (uint32_t *)take(4 * c);
     SortWorkspace w = fixed_ws(sl);
     w.tileT = (uint32_t *)take(4 * c);
     w.primT = (uint32_t *)take(4 * c);
-    w.emit_prim = (uint32_t *)take(4 * c);
+    w.emit_prim = nullptr;
     w.hist = (uint32_t *)take(4 * 256 * nb);
     w.part = (uint64_t *)take(8 * (cdiv64(256 * nb, 4096) + 64));
     BinSortArgs a = sort_args(s, sl, r.cam);
     a.pair_tile = pair_tile;
     a.pair_prim = pair_prim;
-    a.emit_to_sorted = emit_to_sorted;
+    a.emit_to_sorted = nullptr;
     a.capacity = c;
     hipError_t e = bin_sort_phase2(a, w, r.pairs, sl.stream);
     if (e != hipSuccess) return e;
@@ -205,7 +206,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     ra.records = (const float *)sl.records;
     ra.pair_prim = pair_prim; ra.pair_tile = pair_tile;
     ra.ranges = sl.ranges; ra.tile_order = sl.tile_order; ra.counters = sl.counters;
-    ra.pair_offset = sl.pair_offset; ra.tiles = sl.tiles; ra.emit_to_sorted = emit_to_sorted;
+    ra.pair_offset = sl.pair_offset; ra.tiles = sl.tiles; ra.emit_to_sorted = nullptr;
     ra.tiles_x = a.tiles_x; ra.tiles_y = a.tiles_y;
     FwdOut fo{};
     fo.color = r.out; fo.depth = sl.depth; fo.normal = sl.normal; fo.T_final = sl.T; fo.last = sl.last;
@@ -374,7 +375,8 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
     const uint64_t n = (uint64_t)(scene->n > 0 ? scene->n : 1);
     const uint64_t px = (uint64_t)cfg->max_width * cfg->max_height;
     const uint64_t ntiles = (uint64_t)((cfg->max_width + 15) / 16) * ((cfg->max_height + 15) / 16);
-    const uint64_t nb_n = cdiv64(n, 4096) + 1;
+    // count table of the per-slot depth sort
+    const uint64_t nb_n = cdiv64(n, DEPTH_SORT_CHUNK) + 1;
     for (int i = 0; i < cfg->n_streams && e == hipSuccess; ++i) {
         hipStream_t st;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);

@@ -107,7 +107,7 @@ class FrameState:
     def lists(self) -> L.QgsTileLists:
         l = L.QgsTileLists()
         l.pair_tile, l.pair_prim = _ptr(self.pair_tile), _ptr(self.pair_prim)
-        l.emit_to_sorted = _ptr(self.emit_to_sorted)
+        l.emit_to_sorted = _ptr(self.emit_to_sorted) if self.emit_to_sorted is not None else None
         l.ranges, l.counters, l.capacity = _ptr(self.ranges), _ptr(self.counters), self.capacity
         l.tile_order = _ptr(self.tile_order)
         return l
@@ -152,7 +152,9 @@ class Renderer:
         st.capacity = int(cap)
         st.pair_tile = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
         st.pair_prim = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
-        st.emit_to_sorted = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        # the emission map is built only for the deterministic backward
+        st.emit_to_sorted = (torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+                             if self.opts.flags & L.QGS_DETERMINISTIC_BWD else None)
 
     def preprocess(self, scene_t: dict, cam) -> FrameState:
         n = int(scene_t["center"].shape[0])
@@ -229,6 +231,8 @@ class Renderer:
                 keep.append(t)
                 setattr(dl, name, t.data_ptr())
         opts = L.QgsRenderOpts.from_buffer_copy(self.opts)
+        if (opts.flags & L.QGS_DETERMINISTIC_BWD) and st.emit_to_sorted is None:
+            raise ValueError("the deterministic backward needs lists binned with the deterministic flag")
         if accumulate:
             opts.flags |= L.QGS_ACCUMULATE_GRADS
         _, bwd_bytes = L.qgs_workspace_query(st.n, st.cam, st.capacity, opts.flags)

@@ -61,17 +61,18 @@ def check_keys(scene, cam, st):
 def check_lists(ks, cam, st):
     keys_, prims, ranges = oracle.bin_sort(ks, cam)
     npairs = len(prims)
-    # emit_to_sorted: primitive p's pairs (row-major tiles) start at
-    # pair_offset[p] in emission order and land at its sorted positions
-    e2s = to_np(st.emit_to_sorted).view(np.uint32)[:npairs]
-    off = to_np(st.pair_offset).view(np.uint32)[:len(ks["tiles"])]
-    tile = (keys_ >> np.uint64(32)).astype(np.int64)
-    order = np.lexsort((tile, prims.astype(np.int64)))   # by primitive, then tile
-    want = np.empty(npairs, np.uint32)
-    first = np.searchsorted(prims[order], prims[order], side="left")
-    k = np.arange(npairs) - first
-    want[(off[prims[order]].astype(np.int64) + k)] = order.astype(np.uint32)
-    assert np.array_equal(e2s, want), "emission -> sorted positions"
+    if st.emit_to_sorted is not None:
+        # emit_to_sorted: primitive p's pairs (row-major tiles) start at
+        # pair_offset[p] in emission order and land at its sorted positions
+        e2s = to_np(st.emit_to_sorted).view(np.uint32)[:npairs]
+        off = to_np(st.pair_offset).view(np.uint32)[:len(ks["tiles"])]
+        tile = (keys_ >> np.uint64(32)).astype(np.int64)
+        order = np.lexsort((tile, prims.astype(np.int64)))   # by primitive, then tile
+        want = np.empty(npairs, np.uint32)
+        first = np.searchsorted(prims[order], prims[order], side="left")
+        k = np.arange(npairs) - first
+        want[(off[prims[order]].astype(np.int64) + k)] = order.astype(np.uint32)
+        assert np.array_equal(e2s, want), "emission -> sorted positions"
     assert st.num_pairs is None or st.num_pairs == npairs
     cnt = to_np(st.counters).view(np.uint32)
     assert cnt[0] == npairs and cnt[1] == 0
@@ -90,21 +91,24 @@ def check_lists(ks, cam, st):
 # key stage: bit-exact
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ci", [0, 1])
-def test_keys_and_lists_bitexact_small(ci):
+@pytest.mark.parametrize("ci,det", [(0, False), (1, False), (0, True), (1, True)])
+def test_keys_and_lists_bitexact_small(ci, det):
+    # det: lists binned with the deterministic flag also carry the emission map
     c = cfg(ci)
     cam = c.cameras[0]
-    r, st = gpu_forward(c.scene, cam)
+    r, st = gpu_forward(c.scene, cam, opts=dict(flags=L.QGS_DETERMINISTIC_BWD) if det else None)
+    assert (st.emit_to_sorted is not None) == det
     ks = check_keys(c.scene, cam, st)
     check_lists(ks, cam, st)
 
 
 def test_keys_and_lists_bitexact_headline_size():
-    # 500K quadrics, 1600 x 1200 (the timed configuration), two ring views
+    # 500K quadrics, 1600 x 1200 (the timed configuration), two ring views, the
+    # second binned with the emission map
     c = cfg(2, n_views=64)
-    for v in (0, 21):
+    for v, det in ((0, False), (21, True)):
         cam = c.cameras[v]
-        r, st = gpu_forward(c.scene, cam)
+        r, st = gpu_forward(c.scene, cam, opts=dict(flags=L.QGS_DETERMINISTIC_BWD) if det else None)
         ks = check_keys(c.scene, cam, st)
         n = check_lists(ks, cam, st)
         assert n > 1_000_000
