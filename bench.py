@@ -46,6 +46,29 @@ FLOPS_BLEND_FWD = 38
 FLOPS_BLEND_BWD = 230
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_render_500k_1600x1200.md")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when the rasterizer sources changed since the counters
+    were taken."""
+    import hashlib
+    try:
+        line = next(l for l in open(TRAFFIC_SUMMARY) if l.strip().startswith("traffic "))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.strip()[len("traffic "):])
+    h = hashlib.sha256()
+    for f in ("raster.hip", "qgs_device.hpp", "qgs_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2411_16392_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec.get("source"):
+        return None
+    return rec.get("bytes") if kernel == "render_bwd" else rec.get("fwd_bytes")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +229,7 @@ def main():
         achieved = kern[dominant] / (stage_ms[dominant] * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
                     "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": measured_traffic(dominant),
                     "flops_per_launch": kern[dominant], "pairs_evaluated": ev, "pairs_blended": bl,
                     "fwd_wave_steps_rect": float(np.mean(wrect)), "fwd_wave_steps_eval": float(np.mean(weval)),
                     "fwd_wave_steps_blend": float(np.mean(wblend)),

@@ -165,8 +165,11 @@ typedef struct qgs_tile_lists {
 /*
  * Forward outputs, planar, [c][height][width].  w = alpha T is an entry's
  * blending weight and t its hit depth along the unit ray.
- * The four geometry maps are optional: either all four pointers are NULL (not
- * computed, no cost) or all four are set.
+ * color is required.  depth and normal are optional together (both NULL:
+ * colour-only rendering, which skips the normal computation); T_final and
+ * last may be NULL (not written), but the backward needs both.  The four
+ * geometry maps are optional: either all four pointers are NULL (not computed,
+ * no cost) or all four are set, and then depth and normal must be set too.
  */
 typedef struct qgs_images {
     float *color;    /* [3][H][W] sum w rgb + T_final bg */

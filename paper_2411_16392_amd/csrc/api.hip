@@ -233,10 +233,12 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
 {
     if (!prims || !prims_ok(prims, prims->n) || !lists_ok(lists) || !cam_ok(cam) || !opts_ok(opts) || !out)
         return QGS_ERR_INVALID_ARG;
-    if (!out->color || !out->depth || !out->normal || !out->T_final || !out->last) return QGS_ERR_INVALID_ARG;
+    // depth and normal: both or neither (colour-only rendering)
+    if (!out->color || (out->depth == nullptr) != (out->normal == nullptr)) return QGS_ERR_INVALID_ARG;
     const int n_geo = (out->curvature != nullptr) + (out->median_depth != nullptr) + (out->distortion != nullptr) +
                       (out->median_pos != nullptr);
     if (n_geo != 0 && n_geo != 4) return QGS_ERR_INVALID_ARG;
+    if (n_geo == 4 && !out->depth) return QGS_ERR_INVALID_ARG;
     FwdOut o;
     o.color = out->color;
     o.depth = out->depth;

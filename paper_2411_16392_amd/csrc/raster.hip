@@ -94,7 +94,8 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
-// GEO: also the curvature, median-depth and depth-distortion maps.
+// GEO: also the curvature, median-depth and depth-distortion maps.  NRM:
+// accumulate depth and normal (off for colour-only rendering).
 //
 // Each wave walks its tile's list on its own, with no LDS and no barrier: the
 // list is read 64 entries at a time (lane i fetches entry b + i's primitive id
@@ -102,7 +103,7 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
 // rectangle meets the wave's 8 x 8 block, and only those are visited.  A
 // visited entry's record is read with a wave-uniform address, so it is
 // fetched once for the wave (scalar loads) and sits in scalar registers.
-template <bool GEO>
+template <bool GEO, bool NRM>
 #if QGS_FWD_MIN_WAVES > 0
 __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
 #else
@@ -179,13 +180,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                             c1 = __builtin_fmaf(wgt, cr.z, c1);
                             c2 = __builtin_fmaf(wgt, cr.w, c2);
                             const float t = (p.Zc + H.s) * ray.enorm;
-                            dep = __builtin_fmaf(wgt, t, dep);
-                            float nl[3], il;
-                            const float f = hit_normal(p, H, nl, il);
-                            const float wf = wgt * f;
-                            n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
-                            n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
-                            n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
+                            float nl[3], il = 0.0f;
+                            if (NRM || GEO) {
+                                dep = __builtin_fmaf(wgt, t, dep);
+                                const float f = hit_normal(p, H, nl, il);
+                                const float wf = wgt * f;
+                                n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
+                                n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
+                                n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
+                            }
                             if (GEO) {
                                 kk = __builtin_fmaf(wgt, hit_curvature(p, il), kk);
                                 if (T > 0.5f && (med_pos == 0u || t > med)) {
@@ -216,12 +219,14 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         o.color[pix] = c0 + T * P.bg[0];
         o.color[hw + pix] = c1 + T * P.bg[1];
         o.color[2 * hw + pix] = c2 + T * P.bg[2];
-        o.depth[pix] = dep;
-        o.normal[pix] = n0;
-        o.normal[hw + pix] = n1;
-        o.normal[2 * hw + pix] = n2;
-        o.T_final[pix] = T;
-        o.last[pix] = last;
+        if (NRM || GEO) {
+            o.depth[pix] = dep;
+            o.normal[pix] = n0;
+            o.normal[hw + pix] = n1;
+            o.normal[2 * hw + pix] = n2;
+        }
+        if (o.T_final) o.T_final[pix] = T;
+        if (o.last) o.last[pix] = last;
         if (GEO) {
             o.curvature[pix] = kk;
             o.median_depth[pix] = med;
@@ -592,9 +597,11 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
     if (ntiles == 0) return hipSuccess;
     if (o.curvature)
-        hipLaunchKernelGGL(k_render_fwd<true>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+    else if (o.depth)
+        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
     else
-        hipLaunchKernelGGL(k_render_fwd<false>, dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
     return hipGetLastError();
 }
 

@@ -66,8 +66,6 @@ struct Slot {
     uint32_t *dkA = nullptr, *dvA = nullptr, *dkB = nullptr, *dvB = nullptr, *hist = nullptr;
     uint64_t *off = nullptr, *part = nullptr;
     uint32_t *ranges = nullptr, *tile_order = nullptr, *counters = nullptr, *counters_host = nullptr;
-    float *depth = nullptr, *normal = nullptr, *T = nullptr;
-    uint32_t *last = nullptr;
     std::shared_ptr<Req> req;
     Phase phase = IDLE;
 };
@@ -209,7 +207,8 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     ra.pair_offset = sl.pair_offset; ra.tiles = sl.tiles; ra.emit_to_sorted = nullptr;
     ra.tiles_x = a.tiles_x; ra.tiles_y = a.tiles_y;
     FwdOut fo{};
-    fo.color = r.out; fo.depth = sl.depth; fo.normal = sl.normal; fo.T_final = sl.T; fo.last = sl.last;
+    // colour only: no depth, normal, transmittance or last-entry planes
+    fo.color = r.out; fo.depth = nullptr; fo.normal = nullptr; fo.T_final = nullptr; fo.last = nullptr;
     fo.counters = nullptr;
     e = launch_render_fwd(ra, params_for(r.cam, s->cfg.opts), fo, sl.stream);
     if (e != hipSuccess) return e;
@@ -373,7 +372,6 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
     s->t0 = std::chrono::steady_clock::now();
     hipError_t e = hipSetDevice(cfg->device);
     const uint64_t n = (uint64_t)(scene->n > 0 ? scene->n : 1);
-    const uint64_t px = (uint64_t)cfg->max_width * cfg->max_height;
     const uint64_t ntiles = (uint64_t)((cfg->max_width + 15) / 16) * ((cfg->max_height + 15) / 16);
     // count table of the per-slot depth sort
     const uint64_t nb_n = cdiv64(n, DEPTH_SORT_CHUNK) + 1;
@@ -418,11 +416,7 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
         sl.tile_order = (uint32_t *)p;
         if ((e = dev_alloc(s, &p, 32)) != hipSuccess) break;
         sl.counters = (uint32_t *)p;
-        if ((e = dev_alloc(s, &p, 4 * 6 * px)) != hipSuccess) break;
-        sl.depth = (float *)p;
-        sl.normal = sl.depth + px;
-        sl.T = sl.depth + 4 * px;
-        sl.last = (uint32_t *)(sl.depth + 5 * px);
+
         if ((e = hipHostMalloc((void **)&sl.counters_host, 32, hipHostMallocDefault)) != hipSuccess) break;
     }
     if (e == hipSuccess) e = dev_alloc(s, &s->pool_base, (size_t)cfg->budget_bytes);

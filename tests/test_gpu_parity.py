@@ -170,6 +170,50 @@ def test_invalid_arguments_are_rejected():
     assert e.value.status == L.QGS_ERR_WORKSPACE
 
 
+def test_colour_only_forward_and_optional_planes():
+    # depth and normal both NULL: colour-only rendering, bit-identical colour;
+    # T_final / last may be NULL; half a pair or a geometry map without depth is
+    # rejected; the deterministic backward needs lists binned with the map
+    c = cfg(1)
+    cam = c.cameras[0]
+    sc = R.scene_to_device(c.scene)
+    r = R.Renderer()
+    st = r.forward(sc, cam)
+    col = torch.full_like(st.color, -1.0)
+    im = L.QgsImages()
+    im.color = col.data_ptr()
+    L.qgs_render_fwd(st.prim_buf(), st.lists(), st.cam, r.opts, im)
+    torch.cuda.synchronize()
+    assert torch.equal(col, st.color)
+    bad = L.QgsImages()
+    bad.color, bad.depth = col.data_ptr(), st.depth.data_ptr()
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_render_fwd(st.prim_buf(), st.lists(), st.cam, r.opts, bad)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    geo = L.QgsImages()
+    geo.color = col.data_ptr()
+    geo.curvature = geo.median_depth = geo.distortion = geo.median_pos = st.T_final.data_ptr()
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_render_fwd(st.prim_buf(), st.lists(), st.cam, r.opts, geo)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    det = R.make_opts(flags=L.QGS_DETERMINISTIC_BWD)
+    with pytest.raises(ValueError):
+        R.Renderer(opts=det).backward(sc, st, dcolor=torch.ones_like(st.color))
+    out = {k: torch.empty_like(v) for k, v in sc.items()}
+    g = L.QgsSceneGrads()
+    for k in R.SCENE_KEYS:
+        setattr(g, k, out[k].data_ptr())
+    dl = L.QgsImageGrads()
+    dc = torch.ones_like(st.color)
+    dl.dcolor = dc.data_ptr()
+    _, nbytes = L.qgs_workspace_query(st.n, st.cam, st.capacity, det.flags)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_render_bwd(R._scene_struct(sc), st.prim_buf(), st.lists(), st.cam, det, st.images(), dl, g,
+                         ws.data_ptr(), ws.numel())
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+
+
 # ---------------------------------------------------------------------------
 # forward parity
 # ---------------------------------------------------------------------------
