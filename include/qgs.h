@@ -316,7 +316,13 @@ typedef struct qgs_serve_config {
     int32_t n_streams;               /* HIP streams used by the scheduler (default priority) */
     int32_t device;                  /* HIP device ordinal */
     qgs_render_opts opts;
+    uint32_t flags;                  /* QGS_SERVE_* below */
+    uint32_t pad;
 } qgs_serve_config;
+
+/* Launch each request's work directly instead of through the slot's
+   persistent graphs (for comparison). */
+#define QGS_SERVE_NO_GRAPHS 1u
 
 #define QGS_REQ_DONE      0
 #define QGS_REQ_CANCELLED 1
@@ -337,6 +343,8 @@ typedef struct qgs_serve_stats {
     uint64_t peak_pool_bytes;   /* high-water mark of reserved list memory */
     int32_t peak_in_flight;     /* most requests on the device at once */
     int32_t pad;
+    uint64_t graph_launches;    /* count and render passes launched as graphs */
+    uint64_t graph_builds;      /* graphs instantiated (the rest were updated in place) */
 } qgs_serve_stats;
 
 /* scene: device arrays that must outlive the server.  Errors:

@@ -73,7 +73,8 @@ class QgsSceneGrads(ctypes.Structure):
 
 class QgsServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", c_int64), ("max_slots", c_int32), ("max_width", c_int32), ("max_height", c_int32),
-                ("n_streams", c_int32), ("device", c_int32), ("opts", QgsRenderOpts)]
+                ("n_streams", c_int32), ("device", c_int32), ("opts", QgsRenderOpts), ("flags", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class QgsCompletion(ctypes.Structure):
@@ -83,9 +84,11 @@ class QgsCompletion(ctypes.Structure):
 
 class QgsServeStats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("cancelled", c_uint64), ("failed", c_uint64),
-                ("peak_pool_bytes", c_uint64), ("peak_in_flight", c_int32), ("pad", c_int32)]
+                ("peak_pool_bytes", c_uint64), ("peak_in_flight", c_int32), ("pad", c_int32),
+                ("graph_launches", c_uint64), ("graph_builds", c_uint64)]
 
 
+QGS_SERVE_NO_GRAPHS = 1
 QGS_REQ_DONE = 0
 QGS_REQ_CANCELLED = 1
 QGS_REQ_FAILED = 2

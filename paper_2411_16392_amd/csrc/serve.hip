@@ -68,6 +68,8 @@ struct Slot {
     uint32_t *ranges = nullptr, *tile_order = nullptr, *counters = nullptr, *counters_host = nullptr;
     std::shared_ptr<Req> req;
     Phase phase = IDLE;
+    // persistent graphs of the count pass and of the render pass
+    hipGraphExec_t count_exec = nullptr, render_exec = nullptr;
 };
 
 }  // namespace
@@ -150,7 +152,65 @@ SortWorkspace fixed_ws(Slot &sl)
     return w;
 }
 
+// Runs issue(stream) on the slot's stream, normally through a graph: the
+// launches are captured, the slot's executable graph for this pass is updated
+// in place with the new arguments (same topology: same kernels and grids
+// shape, different camera, sizes and pool addresses) or instantiated when the
+// topology differs, and launched as one unit.  Every fill in these passes is
+// a kernel, so the graphs hold no memset nodes.
+hipError_t enqueue_count(qgs_server *s, Slot &sl, hipStream_t stream);
+
+template <class F>
+hipError_t run_pass(qgs_server *s, Slot &sl, hipGraphExec_t &exec, F &&issue)
+{
+    if (s->cfg.flags & QGS_SERVE_NO_GRAPHS) return issue(sl.stream);
+    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ei = issue(sl.stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(sl.stream, &g);
+    if (ei != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return ei != hipSuccess ? ei : e;
+    }
+    bool updated = false;
+    if (exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        }
+    }
+    if (!updated) {
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            exec = nullptr;
+            (void)hipGraphDestroy(g);
+            return e;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.graph_builds++;
+    }
+    (void)hipGraphDestroy(g);
+    e = hipGraphLaunch(exec, sl.stream);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.graph_launches++;
+    }
+    return e;
+}
+
 hipError_t issue_count(qgs_server *s, Slot &sl)
+{
+    hipError_t e = run_pass(s, sl, sl.count_exec, [&](hipStream_t st) { return enqueue_count(s, sl, st); });
+    if (e != hipSuccess) return e;
+    return hipEventRecord(sl.ev, sl.stream);
+}
+
+hipError_t enqueue_count(qgs_server *s, Slot &sl, hipStream_t stream)
 {
     const Req &r = *sl.req;
     PreprocessArgs pa{};
@@ -162,18 +222,25 @@ hipError_t issue_count(qgs_server *s, Slot &sl)
     pa.k_sigma = s->cfg.opts.k_sigma;
     pa.records = sl.records; pa.depth_key = sl.depth_key; pa.rect = sl.rect; pa.tiles = sl.tiles;
     pa.conic = sl.conic;
-    hipError_t e = launch_preprocess(pa, sl.stream);
+    hipError_t e = launch_preprocess(pa, stream);
     if (e != hipSuccess) return e;
     BinSortArgs a = sort_args(s, sl, r.cam);
     a.capacity = 0xFFFFFFFFull;  // the count pass never overflows
-    e = bin_sort_phase1(a, fixed_ws(sl), sl.stream);
+    e = bin_sort_phase1(a, fixed_ws(sl), stream);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(sl.counters_host, sl.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, sl.stream);
+    return hipMemcpyAsync(sl.counters_host, sl.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+}
+
+hipError_t enqueue_render(qgs_server *s, Slot &sl, hipStream_t stream);
+
+hipError_t issue_render(qgs_server *s, Slot &sl)
+{
+    hipError_t e = run_pass(s, sl, sl.render_exec, [&](hipStream_t st) { return enqueue_render(s, sl, st); });
     if (e != hipSuccess) return e;
     return hipEventRecord(sl.ev, sl.stream);
 }
 
-hipError_t issue_render(qgs_server *s, Slot &sl)
+hipError_t enqueue_render(qgs_server *s, Slot &sl, hipStream_t stream)
 {
     Req &r = *sl.req;
     const uint64_t c = r.pairs > 0 ? r.pairs : 1;
@@ -198,7 +265,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     a.pair_prim = pair_prim;
     a.emit_to_sorted = nullptr;
     a.capacity = c;
-    hipError_t e = bin_sort_phase2(a, w, r.pairs, sl.stream);
+    hipError_t e = bin_sort_phase2(a, w, r.pairs, stream);
     if (e != hipSuccess) return e;
     RasterArgs ra{};
     ra.records = (const float *)sl.records;
@@ -210,9 +277,7 @@ hipError_t issue_render(qgs_server *s, Slot &sl)
     // colour only: no depth, normal, transmittance or last-entry planes
     fo.color = r.out; fo.depth = nullptr; fo.normal = nullptr; fo.T_final = nullptr; fo.last = nullptr;
     fo.counters = nullptr;
-    e = launch_render_fwd(ra, params_for(r.cam, s->cfg.opts), fo, sl.stream);
-    if (e != hipSuccess) return e;
-    return hipEventRecord(sl.ev, sl.stream);
+    return launch_render_fwd(ra, params_for(r.cam, s->cfg.opts), fo, stream);
 }
 
 void complete(qgs_server *s, const Req &r, int32_t state, int32_t status)
@@ -522,6 +587,8 @@ qgs_status qgs_serve_destroy(qgs_server *s)
     for (auto &st : s->streams) (void)hipStreamSynchronize(st);
     for (auto &sl : s->slots) {
         if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.count_exec) (void)hipGraphExecDestroy(sl.count_exec);
+        if (sl.render_exec) (void)hipGraphExecDestroy(sl.render_exec);
         if (sl.counters_host) (void)hipHostFree(sl.counters_host);
     }
     for (void *p : s->allocations) (void)hipFree(p);

@@ -19,7 +19,7 @@ from . import render as R
 
 class Server:
     def __init__(self, scene_t: dict, budget_bytes: int = 8 << 30, max_slots: int = 8, max_size=(1920, 1080),
-                 n_streams: int = 4, opts: L.QgsRenderOpts | None = None, device: int = 0):
+                 n_streams: int = 4, opts: L.QgsRenderOpts | None = None, device: int = 0, graphs: bool = True):
         self.scene_t = scene_t  # keeps the resident arrays alive
         cfg = L.QgsServeConfig()
         cfg.budget_bytes = int(budget_bytes)
@@ -28,6 +28,7 @@ class Server:
         cfg.n_streams = int(n_streams)
         cfg.device = int(device)
         cfg.opts = opts if opts is not None else R.make_opts()
+        cfg.flags = 0 if graphs else L.QGS_SERVE_NO_GRAPHS
         self.handle = L.qgs_serve_create(R._scene_struct(scene_t), cfg)
 
     def submit(self, cam, out: torch.Tensor) -> int:

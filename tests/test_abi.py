@@ -71,3 +71,35 @@ def test_invalid_arguments_rejected_before_launch():
     pb.n = 0
     with pytest.raises(L.QgsError):
         L.qgs_preprocess(sc, cam, o, pb)
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the header's structs, as compiled by the
+    C compiler, against the ctypes mirrors of the binding."""
+    import ctypes
+    import subprocess
+    structs = {"qgs_scene": L.QgsScene, "qgs_camera": L.QgsCamera, "qgs_render_opts": L.QgsRenderOpts,
+               "qgs_prim_buf": L.QgsPrimBuf, "qgs_tile_lists": L.QgsTileLists, "qgs_images": L.QgsImages,
+               "qgs_image_grads": L.QgsImageGrads, "qgs_scene_grads": L.QgsSceneGrads,
+               "qgs_serve_config": L.QgsServeConfig, "qgs_completion": L.QgsCompletion,
+               "qgs_serve_stats": L.QgsServeStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qgs.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -61,6 +61,29 @@ def test_each_result_alone_equals_in_the_mix(scene_t):
         assert err <= 1e-6, (rid, err)
 
 
+def test_graph_launches_match_direct_launches(scene_t):
+    # the slots' persistent graphs (updated in place per request) against
+    # plain stream launches: bit-identical images, and every pass went
+    # through a graph
+    cams = _views(16, 21)
+    res = {}
+    for graphs in (True, False):
+        outs = [torch.full((3, c.height, c.width), -1.0, device="cuda") for c in cams]
+        with serve.Server(scene_t, budget_bytes=2 << 30, max_slots=4, n_streams=2, graphs=graphs) as srv:
+            ids = [srv.submit(c, o) for c, o in zip(cams, outs)]
+            got = _drain(srv, len(ids))
+            st = srv.stats()
+        assert all(got[i][0] == L.QGS_REQ_DONE for i in ids)
+        if graphs:
+            assert st.graph_launches == 2 * len(cams)
+            assert 1 <= st.graph_builds <= st.graph_launches
+        else:
+            assert st.graph_launches == 0
+        res[graphs] = outs
+    for a, b in zip(res[True], res[False]):
+        assert torch.equal(a, b)
+
+
 def test_admission_waits_for_list_memory(scene_t):
     cams = _views(12, 12)
     # the budget fits about one large request's lists at a time
