@@ -23,13 +23,13 @@ _SO = os.path.join(_HERE, "liboracle.so")
 # Readings of the unstated constants (the renderer inherits them from the 3DGS
 # framework the paper builds on); every one is an input.
 DEFAULT_OPTS = dict(near=0.2, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99,
-                    T_eps=1e-4, A_eps=1e-6, bg=(0.0, 0.0, 0.0))
+                    T_eps=1e-4, A_eps=1e-6, bg=(0.0, 0.0, 0.0), resort=0, tile_depth=False)
 
 # Margin scales for the discrete decisions: a pixel whose relative distance to a
 # decision boundary is below its scale is reported with margin < 1.
 DEFAULT_DELTA = dict(A=1e-3, D=1e-6, near=1e-5, E=1e-5, alpha_min=1e-4, T=1e-4,
-                     normal=1e-4, clamp=1e-4, median=1e-5)
-_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median"]
+                     normal=1e-4, clamp=1e-4, median=1e-5, sort=1e-5)
+_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median", "sort"]
 
 
 def build() -> str:
@@ -50,11 +50,13 @@ def _lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
-        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P]
+        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P, P]
         L.oracle_keys.restype = None
-        L.oracle_bin_sort.argtypes = [i64, P, P, P, P, P, P, i32, i32, i32, i32, i64, P, P, P, P]
+        L.oracle_bin_sort.argtypes = [i64, P, P, P, P, P, P, i32, i32, i32, i32, i64, P, P, P, P, P, f32]
         L.oracle_bin_sort.restype = i64
-        L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
+        L.oracle_tile_depth_bits.argtypes = [P, i32, i32, P, i32, i32, f64]
+        L.oracle_tile_depth_bits.restype = ctypes.c_uint32
+        L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                     i32, i32, i32, i32, i32,
                                     P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.oracle_render.restype = i64
@@ -92,7 +94,8 @@ def opts_array(opts=None):
     if opts:
         o.update(opts)
     # thresholds are FP32 values on the GPU; the oracle uses the same values
-    vals = [o["near"], o["k_sigma"], o["alpha_min"], o["alpha_max"], o["T_eps"], o["A_eps"], *o["bg"]]
+    vals = [o["near"], o["k_sigma"], o["alpha_min"], o["alpha_max"], o["T_eps"], o["A_eps"], *o["bg"],
+            float(o["resort"])]
     return np.asarray(vals, np.float32).astype(np.float64)
 
 
@@ -126,17 +129,26 @@ def keys(scene, cam, opts=None):
     tiles = np.zeros(n, np.uint32)
     conic = np.zeros((n, 6), np.float64)
     conic_ok = np.zeros(n, np.uint8)
+    frame = np.zeros((n, 16), np.float64)
     arrs = [_f32(a) for a in scene.arrays()]
     camv = cam_array(cam)
     _lib().oracle_keys(n, *[_ptr(a) for a in arrs], _ptr(camv), cam.width, cam.height,
                        ctypes.c_float(o[0]), ctypes.c_float(o[1]),
                        _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles),
-                       _ptr(conic), _ptr(conic_ok))
+                       _ptr(conic), _ptr(conic_ok), _ptr(frame))
     return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles,
-                conic=conic, conic_ok=conic_ok, cam=camv, width=cam.width, height=cam.height)
+                conic=conic, conic_ok=conic_ok, frame=frame, cam=camv, width=cam.width, height=cam.height,
+                near=float(o[0]))
 
 
-def bin_sort(k, cam, with_seq=False):
+def tile_depth_bits(k, p, tx, ty):
+    """Per-tile sort depth key of primitive p for tile (tx, ty) (key-stage spec)."""
+    return int(_lib().oracle_tile_depth_bits(_ptr(np.ascontiguousarray(k["frame"][p])), int(tx), int(ty),
+                                             _ptr(_f64(k["cam"].astype(np.float64))), k["width"], k["height"],
+                                             float(k["near"])))
+
+
+def bin_sort(k, cam, with_seq=False, tile_depth=False):
     """Sorted tile|depth key list and per-tile ranges from the key stage
     (with_seq: also the emission index of every sorted pair)."""
     n = k["culled"].shape[0]
@@ -145,11 +157,13 @@ def bin_sort(k, cam, with_seq=False):
     L = _lib()
     args = (_ptr(k["culled"]), _ptr(k["depth_bits"]), _ptr(k["rect_tile"]), _ptr(k["conic"]), _ptr(k["conic_ok"]),
             _ptr(k["cam"]), k["width"], k["height"], tx, ty)
-    total = L.oracle_bin_sort(n, *args, 0, None, None, None, _ptr(ranges))
+    fr = _ptr(k["frame"]) if tile_depth else None
+    total = L.oracle_bin_sort(n, *args, 0, None, None, None, _ptr(ranges), fr, ctypes.c_float(k["near"]))
     keys_out = np.zeros(max(total, 1), np.uint64)
     prims = np.zeros(max(total, 1), np.uint32)
     seq = np.zeros(max(total, 1), np.uint32)
-    total2 = L.oracle_bin_sort(n, *args, total, _ptr(keys_out), _ptr(prims), _ptr(seq), _ptr(ranges))
+    total2 = L.oracle_bin_sort(n, *args, total, _ptr(keys_out), _ptr(prims), _ptr(seq), _ptr(ranges), fr,
+                               ctypes.c_float(k["near"]))
     assert total2 == total
     if with_seq:
         return keys_out[:total], prims[:total], ranges, seq[:total]
@@ -196,7 +210,12 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
                      curv=np.zeros((n, 2)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
         gp = ([_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(m) if m is not None else None for m in extra] +
               [_ptr(grads[k]) for k in ("center", "quat", "scale", "curv", "opacity", "rgb")])
+    o_d = dict(DEFAULT_OPTS)
+    o_d.update(opts or {})
+    keycam = _f64(key_stage["cam"].astype(np.float64))
+    fr = _ptr(key_stage["frame"]) if o_d["tile_depth"] else None
     ev = _lib().oracle_render(n, *[_ptr(a) for a in arrs], _ptr(key_stage["culled"]), _ptr(key_stage["depth_bits"]),
+                              fr, _ptr(keycam),
                               _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv),
                               x0, y0, w, h, int(nthreads),
                               _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin),

@@ -124,7 +124,7 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
                  const float *curv, const float *opac, const float *rgb,
                  const float *cam, int32_t width, int32_t height, float near_f, float k_sigma,
                  uint8_t *culled, uint32_t *depth_bits, int32_t *rect_px, int32_t *rect_tile,
-                 uint32_t *tiles, double *conic, uint8_t *conic_ok)
+                 uint32_t *tiles, double *conic, uint8_t *conic_ok, double *frame)
 {
     double W[9], T[3];
     for (int i = 0; i < 9; ++i) W[i] = cam[i];
@@ -143,6 +143,7 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
         culled[p] = 1;
         conic_ok[p] = 0;
         for (int i = 0; i < 6; ++i) conic[6 * p + i] = 0.0;
+        if (frame) for (int i = 0; i < 16; ++i) frame[16 * p + i] = 0.0;
 
         const float *cf = center + 3 * p, *qf = quat + 4 * p, *sf = scale + 2 * p, *lf = curv + 2 * p;
         if (!finite_f(cf, 3) || !finite_f(qf, 4) || !finite_f(sf, 2) || !finite_f(lf, 2) ||
@@ -223,6 +224,16 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
         }
         culled[p] = 0;
         memcpy(&depth_bits[p], &zf, 4);
+        if (frame) {
+            /* camera frame of the primitive for the per-tile sort depth */
+            double *F = frame + 16 * p;
+            for (int i = 0; i < 3; ++i) F[i] = cc[i];
+            for (int i = 0; i < 9; ++i) F[3 + i] = Rc[i];
+            F[12] = fma(fx, cc[0] / cc[2], cx);
+            F[13] = fma(fy, cc[1] / cc[2], cy);
+            F[14] = l1;
+            F[15] = l2;
+        }
         if (px0 > px1 || py0 > py1) continue;
         rp[0] = px0; rp[1] = py0; rp[2] = px1; rp[3] = py1;
         rt[0] = px0 / OT; rt[1] = py0 / OT; rt[2] = px1 / OT; rt[3] = py1 / OT;
@@ -265,8 +276,68 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
     }
 }
 
+/*
+ * Per-tile sort depth (supplement, per-tile sorting): for tile (tx, ty), the
+ * camera depth at which the ray through the tile's pixel nearest the
+ * projected vertex meets the paraboloid.  The pixel is the one containing the
+ * projected vertex, clamped to the tile.  The ray d = (x_n, y_n, 1) makes the
+ * ray parameter the camera depth; in the local frame p = o + s e with
+ * o = -Rc^T c_cam and e = Rc^T d, and A s^2 + B s + C = 0 as for shading.  The
+ * depth is the smallest root beyond the near plane (the small-|A| root -C/B
+ * when |A| <= 1e-12 |e|^2), or the centre depth if there is none.  F is the
+ * frame written by oracle_keys: c_cam[3], Rc[9], projected vertex (u, v),
+ * lambda1, lambda2.  FP64, no contraction, the operation order as written.
+ */
+static uint32_t tile_depth_bits(const double *F, int tx, int ty, const double *cam, int width, int height,
+                                double near_d)
+{
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const int ux0 = tx * OT, ux1 = tx * OT + OT - 1 < width - 1 ? tx * OT + OT - 1 : width - 1;
+    const int vy0 = ty * OT, vy1 = ty * OT + OT - 1 < height - 1 ? ty * OT + OT - 1 : height - 1;
+    const double fu = floor(F[12]), fv = floor(F[13]);
+    const int px = fu < (double)ux0 ? ux0 : (fu > (double)ux1 ? ux1 : (int)fu);
+    const int py = fv < (double)vy0 ? vy0 : (fv > (double)vy1 ? vy1 : (int)fv);
+    const double dx = (((double)px + 0.5) - cx) / fx, dy = (((double)py + 0.5) - cy) / fy;
+    double o[3], e[3];
+    for (int k = 0; k < 3; ++k) {
+        o[k] = -((F[3 + k] * F[0] + F[6 + k] * F[1]) + F[9 + k] * F[2]);
+        e[k] = (F[3 + k] * dx + F[6 + k] * dy) + F[9 + k];
+    }
+    const double l1 = F[14], l2 = F[15];
+    const double A = (l1 * e[0]) * e[0] + (l2 * e[1]) * e[1];
+    const double B = 2.0 * ((l1 * o[0]) * e[0] + (l2 * o[1]) * e[1]) - e[2];
+    const double C = ((l1 * o[0]) * o[0] + (l2 * o[1]) * o[1]) - o[2];
+    double r[2];
+    int nr = 0;
+    if (fabs(A) <= 1e-12 * ((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])) {
+        if (B != 0.0) r[nr++] = -C / B;
+    } else {
+        const double D = B * B - 4.0 * (A * C);
+        if (D >= 0.0) {
+            const double sq = sqrt(D);
+            const double q = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            if (q != 0.0) {
+                r[nr++] = q / A;
+                r[nr++] = C / q;
+            }
+        }
+    }
+    double z = F[2];
+    int found = 0;
+    for (int i = 0; i < nr; ++i)
+        if (r[i] > near_d && (!found || r[i] < z)) {
+            z = r[i];
+            found = 1;
+        }
+    const float zf = (float)z;
+    uint32_t bits;
+    memcpy(&bits, &zf, 4);
+    return bits;
+}
+
 typedef struct {
-    uint64_t key; /* tile << 32 | depth bits */
+    uint64_t key; /* tile << 32 | depth bits (centre depth, or the per-tile depth) */
+    uint64_t tie; /* centre depth bits << 32 | primitive: the emission order of equal keys */
     uint64_t seq; /* emission index: primitive-major, tiles row-major in its rect */
     uint32_t prim;
 } opair;
@@ -275,22 +346,27 @@ static int cmp_pair(const void *a, const void *b)
 {
     const opair *x = (const opair *)a, *y = (const opair *)b;
     if (x->key != y->key) return x->key < y->key ? -1 : 1;
-    if (x->seq != y->seq) return x->seq < y->seq ? -1 : 1;
+    if (x->tie != y->tie) return x->tie < y->tie ? -1 : 1;
     return 0;
 }
 
 /*
  * Emits one (key, primitive) pair per tile of every rectangle that passes the
  * conic test, in primitive order and row-major within a rectangle, and sorts
- * by key with ties kept in emission order.  Returns the pair count; writes
- * outputs only if it fits cap.  ranges[2t], ranges[2t+1] = [start, end) of
- * tile t in the sorted list; out_seq = emission index of each sorted pair.
+ * by key; equal keys are ordered by (centre depth key, primitive index).  The
+ * key's depth is the primitive's centre depth, or with frame != NULL the
+ * per-tile depth of tile_depth_bits.  Returns the pair count; writes outputs
+ * only if it fits cap.  ranges[2t], ranges[2t+1] = [start, end) of tile t in
+ * the sorted list; out_seq = emission index of each sorted pair.
  */
 int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_bits,
                         const int32_t *rect_tile, const double *conic, const uint8_t *conic_ok,
                         const float *cam, int32_t width, int32_t height, int32_t tiles_x, int32_t tiles_y,
-                        int64_t cap, uint64_t *out_keys, uint32_t *out_prim, uint32_t *out_seq, uint32_t *ranges)
+                        int64_t cap, uint64_t *out_keys, uint32_t *out_prim, uint32_t *out_seq, uint32_t *ranges,
+                        const double *frame, float near_f)
 {
+    double camd[16];
+    for (int i = 0; i < 16; ++i) camd[i] = cam[i];
     int64_t total = 0;
     for (int64_t p = 0; p < n; ++p) {
         const int32_t *r = rect_tile + 4 * p;
@@ -308,7 +384,10 @@ int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_
         for (int ty = r[1]; ty <= r[3]; ++ty)
             for (int tx = r[0]; tx <= r[2]; ++tx) {
                 if (conic_ok[p] && !oracle_tile_hit(conic + 6 * p, tx, ty, cam, width, height)) continue;
-                pairs[k].key = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | depth_bits[p];
+                const uint32_t db = frame ? tile_depth_bits(frame + 16 * p, tx, ty, camd, width, height, near_f)
+                                          : depth_bits[p];
+                pairs[k].key = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | db;
+                pairs[k].tie = ((uint64_t)depth_bits[p] << 32) | (uint64_t)p;
                 pairs[k].seq = (uint64_t)k;
                 pairs[k].prim = (uint32_t)p;
                 ++k;
@@ -329,6 +408,12 @@ int64_t oracle_bin_sort(int64_t n, const uint8_t *culled, const uint32_t *depth_
     return total;
 }
 
+uint32_t oracle_tile_depth_bits(const double *F, int32_t tx, int32_t ty, const double *cam, int32_t width,
+                                int32_t height, double near_d)
+{
+    return tile_depth_bits(F, tx, ty, cam, width, height, near_d);
+}
+
 double oracle_gfun(double u);
 
 /* ======================================================================== */
@@ -336,10 +421,10 @@ double oracle_gfun(double u);
 /* ======================================================================== */
 
 /* options: near, k_sigma, alpha_min, alpha_max, T_eps, A_eps, bg[3] */
-enum { O_NEAR = 0, O_K, O_AMIN, O_AMAX, O_TEPS, O_AEPS, O_BG };
+enum { O_NEAR = 0, O_K, O_AMIN, O_AMAX, O_TEPS, O_AEPS, O_BG, O_RESORT = O_BG + 3, O_NOPTS };
 /* margin scales: |A| vs A_eps, D vs 0, near test, E vs k^2, alpha_min, T_eps,
    normal facing, alpha clamp */
-enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_MED, M_COUNT };
+enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_MED, M_SORT, M_COUNT };
 
 /* per-pixel channels: colour[3], depth, normal[3], curvature, median depth,
    depth distortion */
@@ -530,7 +615,35 @@ typedef struct {
     const int64_t *ids;     /* compact index -> original primitive index */
     int32_t *cell_start, *cell_items; /* CSR over cells of OT x OT pixels */
     int32_t cells_x, cells_y;
+    /* per-tile order (frame != NULL): key-stage frames, centre depth keys and
+       the key-stage camera */
+    const double *frame;
+    const uint32_t *dbits;
+    const double *keycam;
+    int32_t width, height;
+    double near_key;
 } obins;
+
+/* an accepted hit waiting in the per-pixel resort buffer */
+typedef struct {
+    int32_t list;
+    int32_t seq;  /* arrival order, for equal depths */
+    double alpha;
+    ohit H;
+} opending;
+
+typedef struct {
+    uint64_t key, tie;
+    int32_t item;
+} ocand;
+
+static int cmp_cand(const void *a, const void *b)
+{
+    const ocand *x = (const ocand *)a, *y = (const ocand *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->tie != y->tie) return x->tie < y->tie ? -1 : 1;
+    return 0;
+}
 
 static void pixel_ray(const double *cam, int px, int py, double d[3])
 {
@@ -673,67 +786,123 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
     double *wt = NULL;
     int wt_cap = 0;
     const int32_t s = B->cell_start[cell], e = B->cell_start[cell + 1];
-    for (int32_t it = s; it < e; ++it) {
-        const int32_t li = B->cell_items[it];
-        const oprim *P = &B->prims[li];
-        ohit H;
-        ++*evals;
-        ray_hit(P, dcam, opts, delta, &H);
-        if (H.margin < margin) margin = H.margin;
-        if (!H.ok) continue;
-        const double Gv = exp(-0.5 * H.E);
-        const double aa = P->op * Gv;
-        double m = mscale(fabs(aa - opts[O_AMAX]) / opts[O_AMAX], delta, M_CLAMP);
-        if (m < margin) margin = m;
-        const double alpha = aa < opts[O_AMAX] ? aa : opts[O_AMAX];
-        m = mscale(fabs(alpha - opts[O_AMIN]) / opts[O_AMIN], delta, M_AMIN);
-        if (m < margin) margin = m;
-        if (alpha < opts[O_AMIN]) continue;
-        const double Tn = T * (1.0 - alpha);
-        m = mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T);
-        if (m < margin) margin = m;
-        if (Tn < opts[O_TEPS]) break;
-        const double w = alpha * T;
-        double nl[3], flip, vlen;
-        hit_normal(P, &H, nl, &flip, &vlen);
-        m = mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N);
-        if (m < margin) margin = m;
-        for (int c = 0; c < 3; ++c) acc[c] += w * P->rgb[c];
-        acc[CH_DEPTH] += w * H.t;
-        for (int i = 0; i < 3; ++i)
-            acc[CH_N + i] += w * flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
-        acc[CH_K] += w * curvature_K(P->l1, P->l2, H.x, H.y);
-        /* median depth (mesh extraction, Sec. 4.1): the largest hit depth among
-           entries whose incoming transmittance exceeds 0.5 */
-        m = mscale(fabs(T - 0.5) / 0.5, delta, M_MED);
-        if (m < margin) margin = m;
-        if (T > 0.5) {
-            if (med_k < 0 || H.t > med) {
-                if (med_k >= 0) med2 = med;
-                med = H.t;
-                med_k = nb;
-            } else if (H.t > med2) {
-                med2 = H.t;
-            }
+    /* candidate order: the global (centre depth, index) order of the cell, or
+       the order of the pixel's tile list by per-tile depth */
+    ocand *order = NULL;
+    if (B->frame && e > s) {
+        order = (ocand *)malloc(sizeof(ocand) * (size_t)(e - s));
+        for (int32_t it = s; it < e; ++it) {
+            const int32_t li = B->cell_items[it];
+            const int64_t p = B->ids[li];
+            order[it - s].key = tile_depth_bits(B->frame + 16 * p, px / OT, py / OT, B->keycam, B->width, B->height,
+                                                B->near_key);
+            order[it - s].tie = ((uint64_t)B->dbits[p] << 32) | (uint64_t)p;
+            order[it - s].item = li;
         }
-        if (nb >= wt_cap) {
-            wt_cap = wt_cap ? 2 * wt_cap : 64;
-            wt = (double *)realloc(wt, sizeof(double) * 2 * (size_t)wt_cap);
-        }
-        wt[2 * nb] = w;
-        wt[2 * nb + 1] = H.t;
-        if (g) {
-            if (nb >= *scratch_cap) {
-                *scratch_cap = *scratch_cap ? 2 * *scratch_cap : 256;
-                *scratch = (oentry *)realloc(*scratch, sizeof(oentry) * (size_t)*scratch_cap);
-            }
-            (*scratch)[nb].list = li;
-            (*scratch)[nb].alpha = alpha;
-            (*scratch)[nb].T = T;
-        }
-        ++nb;
-        T = Tn;
+        qsort(order, (size_t)(e - s), sizeof(ocand), cmp_cand);
     }
+    /* per-pixel resort (supplement, per-pixel resorting): accepted hits wait in
+       a buffer of K entries; whenever it is full the nearest (smallest t, the
+       earliest arrival among equal t) is blended, and at the end of the list
+       the rest in the same way.  K <= 1 blends in list order. */
+    const int K = opts[O_RESORT] > 1.0 ? (int)opts[O_RESORT] : 1;
+    opending *buf = (opending *)malloc(sizeof(opending) * (size_t)K);
+    int nbuf = 0, nseq = 0, stopped = 0;
+    for (int32_t it = s; it <= e && !stopped; ++it) {
+        if (it < e) {
+            const int32_t li = order ? order[it - s].item : B->cell_items[it];
+            const oprim *P = &B->prims[li];
+            ohit H;
+            ++*evals;
+            ray_hit(P, dcam, opts, delta, &H);
+            if (H.margin < margin) margin = H.margin;
+            if (!H.ok) continue;
+            const double Gv = exp(-0.5 * H.E);
+            const double aa = P->op * Gv;
+            double m = mscale(fabs(aa - opts[O_AMAX]) / opts[O_AMAX], delta, M_CLAMP);
+            if (m < margin) margin = m;
+            const double alpha = aa < opts[O_AMAX] ? aa : opts[O_AMAX];
+            m = mscale(fabs(alpha - opts[O_AMIN]) / opts[O_AMIN], delta, M_AMIN);
+            if (m < margin) margin = m;
+            if (alpha < opts[O_AMIN]) continue;
+            buf[nbuf].list = li;
+            buf[nbuf].seq = nseq++;
+            buf[nbuf].alpha = alpha;
+            buf[nbuf].H = H;
+            ++nbuf;
+            if (nbuf < K) continue;
+        }
+        /* blend: one entry when the buffer is full, all of them at the end */
+        while (nbuf > 0 && !stopped) {
+            int best = 0;
+            for (int b = 1; b < nbuf; ++b)
+                if (buf[b].H.t < buf[best].H.t || (buf[b].H.t == buf[best].H.t && buf[b].seq < buf[best].seq))
+                    best = b;
+            if (nbuf > 1) {
+                /* choosing the nearest of two close depths is a discrete decision */
+                double gap = INFINITY;
+                for (int b = 0; b < nbuf; ++b)
+                    if (b != best && buf[b].H.t - buf[best].H.t < gap) gap = buf[b].H.t - buf[best].H.t;
+                const double m = mscale(gap / fabs(buf[best].H.t), delta, M_SORT);
+                if (m < margin) margin = m;
+            }
+            const opending en = buf[best];
+            buf[best] = buf[--nbuf];
+            const oprim *P = &B->prims[en.list];
+            const ohit H = en.H;
+            const double alpha = en.alpha;
+            const double Tn = T * (1.0 - alpha);
+            double m = mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T);
+            if (m < margin) margin = m;
+            if (Tn < opts[O_TEPS]) {
+                stopped = 1;
+                break;
+            }
+            const double w = alpha * T;
+            double nl[3], flip, vlen;
+            hit_normal(P, &H, nl, &flip, &vlen);
+            m = mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N);
+            if (m < margin) margin = m;
+            for (int c = 0; c < 3; ++c) acc[c] += w * P->rgb[c];
+            acc[CH_DEPTH] += w * H.t;
+            for (int i = 0; i < 3; ++i)
+                acc[CH_N + i] += w * flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
+            acc[CH_K] += w * curvature_K(P->l1, P->l2, H.x, H.y);
+            /* median depth (mesh extraction, Sec. 4.1): the largest hit depth among
+               entries whose incoming transmittance exceeds 0.5 */
+            m = mscale(fabs(T - 0.5) / 0.5, delta, M_MED);
+            if (m < margin) margin = m;
+            if (T > 0.5) {
+                if (med_k < 0 || H.t > med) {
+                    if (med_k >= 0) med2 = med;
+                    med = H.t;
+                    med_k = nb;
+                } else if (H.t > med2) {
+                    med2 = H.t;
+                }
+            }
+            if (nb >= wt_cap) {
+                wt_cap = wt_cap ? 2 * wt_cap : 64;
+                wt = (double *)realloc(wt, sizeof(double) * 2 * (size_t)wt_cap);
+            }
+            wt[2 * nb] = w;
+            wt[2 * nb + 1] = H.t;
+            if (g) {
+                if (nb >= *scratch_cap) {
+                    *scratch_cap = *scratch_cap ? 2 * *scratch_cap : 256;
+                    *scratch = (oentry *)realloc(*scratch, sizeof(oentry) * (size_t)*scratch_cap);
+                }
+                (*scratch)[nb].list = en.list;
+                (*scratch)[nb].alpha = alpha;
+                (*scratch)[nb].T = T;
+            }
+            ++nb;
+            T = Tn;
+            if (it < e) break; /* one blend per arrival while the list lasts */
+        }
+    }
+    free(buf);
+    free(order);
     /* depth distortion (Sec. 3.3): sum_i sum_{j<i} w_i w_j (t_i - t_j)^2 */
     double dist = 0.0, W = 0.0;
     for (int i = 0; i < nb; ++i) {
@@ -829,7 +998,10 @@ static int cmp_order(const void *a, const void *b)
  * Render the pixel window [x0, x0+w) x [y0, y0+h) of a width x height view.
  * Parameters are FP64 (exact copies of FP32 inputs, or perturbed for finite
  * differences).  culled/depth_bits come from oracle_keys and fix the active set
- * and the order.  cam = {R[9], t[3], fx, fy, cx, cy}.
+ * and the order; with frame != NULL (oracle_keys' frames, and keycam the
+ * key-stage camera) each pixel takes its tile's per-tile-depth order instead.
+ * opts[O_RESORT] > 1 enables the per-pixel resort buffer of that size.
+ * cam = {R[9], t[3], fx, fy, cx, cy}.
  * Outputs (window-sized, planar): color[3][h][w], depth, normal[3][h][w],
  * T_final, n_blend (entries blended), margin (min over decisions of the
  * relative distance to the boundary divided by its scale in delta).
@@ -839,8 +1011,8 @@ static int cmp_order(const void *a, const void *b)
  */
 int64_t oracle_render(int64_t n, const double *center, const double *quat, const double *scale,
                       const double *curv, const double *opac, const double *rgb,
-                      const uint8_t *culled, const uint32_t *depth_bits,
-                      const double *cam, int32_t width, int32_t height,
+                      const uint8_t *culled, const uint32_t *depth_bits, const double *frame,
+                      const double *keycam, const double *cam, int32_t width, int32_t height,
                       const double *opts, const double *delta,
                       int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
                       double *color, double *depth, double *normal, double *T_final,
@@ -894,7 +1066,7 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
     for (int64_t i = 0; i < nw; ++i)
         for (int cy = box[4 * i + 1]; cy <= box[4 * i + 3]; ++cy)
             for (int cx = box[4 * i]; cx <= box[4 * i + 2]; ++cx) items[fill[cy * cx_n + cx]++] = (int32_t)i;
-    obins Bn = {tmp, ids, cnt, items, cx_n, cy_n};
+    obins Bn = {tmp, ids, cnt, items, cx_n, cy_n, frame, depth_bits, keycam, width, height, opts[O_NEAR]};
 
     int nthr = nthreads > 0 ? nthreads : 1;
 #ifdef _OPENMP

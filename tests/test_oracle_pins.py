@@ -813,3 +813,245 @@ def test_all_maps_match_brute_force_per_pixel():
             assert abs(r["distortion"][py, px] - dist) < 1e-12
             assert abs(r["T_final"][py, px] - T) < 1e-14
     assert checked > 200
+
+
+# --------------------------------------------------------------------------
+# full-model ordering (supplement, per-tile sorting and per-pixel resorting)
+# --------------------------------------------------------------------------
+
+def _hits_along(sc, cam, px, py, order):
+    """Accepted hits (t, alpha, item) of pixel (px, py) for primitives in `order`."""
+    o = oracle.opts_array()
+    camv = oracle.cam_array(cam, np.float64)
+    xn = ((px + 0.5) - camv[14]) / camv[12]
+    yn = ((py + 0.5) - camv[15]) / camv[13]
+    d = unit([xn, yn, 1.0])
+    out = []
+    for i in order:
+        h = oracle.ray_hit(sc.center[i], sc.quat[i], sc.scale[i], sc.curv[i], camv, d)
+        if not h["ok"]:
+            continue
+        al = min(o[3], float(sc.opacity[i]) * math.exp(-0.5 * h["E"]))
+        if al < o[2]:
+            continue
+        out.append((h["t"], al, i, h))
+    return out
+
+
+def _composite(seq, sc):
+    o = oracle.opts_array()
+    T, col, dep = 1.0, np.zeros(3), 0.0
+    for t, al, i, h in seq:
+        if T * (1 - al) < o[4]:
+            break
+        w = al * T
+        col += w * sc.rgb[i].astype(float)
+        dep += w * t
+        T *= 1 - al
+    return col, dep, T
+
+
+def _buffered(hits, K):
+    """The resort buffer written from its description: keep up to K pending
+    hits; when the buffer is full, blend the nearest (earliest on ties); at
+    the end blend the rest nearest first."""
+    pend, outq = [], []
+    for k, hit in enumerate(hits):
+        pend.append((hit[0], k, hit))
+        if len(pend) == K:
+            j = min(range(len(pend)), key=lambda a: (pend[a][0], pend[a][1]))
+            outq.append(pend.pop(j)[2])
+    outq += [p[2] for p in sorted(pend, key=lambda p: (p[0], p[1]))]
+    return outq
+
+
+def _stack_scene(seed, n=9):
+    # tilted, curved primitives around the optical axis at overlapping depths
+    rng = np.random.default_rng(seed)
+    c = np.stack([rng.uniform(-0.25, 0.25, n), rng.uniform(-0.25, 0.25, n), rng.uniform(-0.15, 0.15, n)], 1)
+    q = np.stack([unit(v) for v in rng.standard_normal((n, 4))])
+    s = rng.uniform(0.3, 0.6, (n, 2))
+    l = rng.uniform(-2.0, 2.0, (n, 2))
+    o = rng.uniform(0.2, 0.7, n)
+    rgb = rng.uniform(0, 1, (n, 3))
+    return Scene(*(np.asarray(a, np.float32) for a in (c, q, s, l, o, rgb)))
+
+
+@pytest.mark.parametrize("K", [1, 3, 8, 64])
+def test_resort_buffer_matches_its_description(K):
+    sc = _stack_scene(41)
+    cam = scenes.look_at((0.05, 0.02, -3.0), width=32, height=32, f=40)
+    ks = oracle.keys(sc, cam)
+    r = oracle.render(sc, cam, opts=dict(resort=K), key_stage=ks, nthreads=2)
+    order = sorted([i for i in range(sc.n) if not ks["culled"][i]], key=lambda i: (int(ks["depth_bits"][i]), i))
+    checked = reordered = 0
+    for py in range(0, 32, 3):
+        for px in range(0, 32, 3):
+            if r["margin"][py, px] < 1.0:
+                continue
+            hits = _hits_along(sc, cam, px, py, order)
+            seq = _buffered(hits, K)
+            col, dep, T = _composite(seq, sc)
+            assert np.allclose(r["color"][:, py, px], col, rtol=0, atol=1e-12)
+            assert abs(r["depth"][py, px] - dep) < 1e-12
+            assert abs(r["T_final"][py, px] - T) < 1e-14
+            checked += 1
+            reordered += [h[2] for h in seq] != [h[2] for h in hits]
+    assert checked > 60
+    if K > 1:
+        assert reordered > 5   # the buffer does change the blend order here
+    # a buffer longer than every list is a full per-pixel sort by hit depth
+    if K == 64:
+        for py in range(0, 32, 5):
+            for px in range(0, 32, 5):
+                if r["margin"][py, px] < 1.0:
+                    continue
+                hits = sorted(_hits_along(sc, cam, px, py, order), key=lambda h: h[0])
+                col, _, _ = _composite(hits, sc)
+                assert np.allclose(r["color"][:, py, px], col, rtol=0, atol=1e-12)
+
+
+def test_resort_of_one_is_the_plain_order():
+    sc = _stack_scene(42)
+    cam = scenes.look_at((0.05, 0.02, -3.0), width=32, height=32, f=40)
+    ks = oracle.keys(sc, cam)
+    a = oracle.render(sc, cam, key_stage=ks, nthreads=2)
+    b = oracle.render(sc, cam, opts=dict(resort=1), key_stage=ks, nthreads=2)
+    for k in ("color", "depth", "normal", "T_final"):
+        assert np.array_equal(a[k], b[k])
+
+
+def _numpy_tile_depth(sc, cam, p, tx, ty, near=0.2):
+    """Per-tile sort depth from its description, with numpy's polynomial roots:
+    the ray through the tile pixel containing the projected vertex (clamped to
+    the tile) against the paraboloid, nearest root beyond the near plane."""
+    camv = oracle.cam_array(cam, np.float64)
+    W = camv[:9].reshape(3, 3); t = camv[9:12]
+    c = W @ sc.center[p].astype(float) + t
+    R = W @ rot(sc.quat[p].astype(float))
+    u = camv[12] * c[0] / c[2] + camv[14]
+    v = camv[13] * c[1] / c[2] + camv[15]
+    px = int(np.clip(np.floor(u), tx * 16, min(tx * 16 + 15, cam.width - 1)))
+    py = int(np.clip(np.floor(v), ty * 16, min(ty * 16 + 15, cam.height - 1)))
+    d = np.array([(px + 0.5 - camv[14]) / camv[12], (py + 0.5 - camv[15]) / camv[13], 1.0])
+    o_ = -R.T @ c; e = R.T @ d
+    l1, l2 = float(sc.curv[p, 0]), float(sc.curv[p, 1])
+    A = l1 * e[0] ** 2 + l2 * e[1] ** 2
+    B = 2 * (l1 * o_[0] * e[0] + l2 * o_[1] * e[1]) - e[2]
+    C = l1 * o_[0] ** 2 + l2 * o_[1] ** 2 - o_[2]
+    roots = np.roots([A, B, C]) if abs(A) > 1e-12 * (e @ e) else np.array([-C / B])
+    roots = [r.real for r in np.atleast_1d(roots) if abs(r.imag) < 1e-12 and r.real > near]
+    return np.float32(min(roots)) if roots else np.float32(c[2])
+
+
+def test_tile_depth_matches_numpy_roots_and_closed_forms():
+    rng = np.random.default_rng(43)
+    n = 40
+    sc = scenes.scene_uniform_cube(n, 43, scale_range=(0.05, 0.4), curv_lim=3.0)
+    cam = scenes.look_at((0.3, -0.2, -3.0), width=96, height=80, f=90)
+    ks = oracle.keys(sc, cam)
+    checked = 0
+    for p in range(n):
+        if ks["culled"][p]:
+            continue
+        r = ks["rect_tile"][p]
+        for ty in range(max(r[1], 0), r[3] + 1):
+            for tx in range(max(r[0], 0), r[2] + 1):
+                got = np.uint32(oracle.tile_depth_bits(ks, p, tx, ty)).view(np.float32)
+                want = _numpy_tile_depth(sc, cam, p, tx, ty)
+                assert abs(float(got) - float(want)) <= 2 * np.spacing(np.float32(want)), (p, tx, ty, got, want)
+                checked += 1
+    assert checked > 100
+    # a fronto-parallel plane at depth 2.5 is met at depth 2.5 by every ray
+    pl = Scene(center=np.array([[0.1, -0.05, 0.0]], np.float32), quat=np.array([[0, 1, 0, 0]], np.float32),
+               scale=np.array([[0.5, 0.5]], np.float32), curv=np.zeros((1, 2), np.float32),
+               opacity=np.array([0.5], np.float32), rgb=np.ones((1, 3), np.float32))
+    cam2 = scenes.look_at((0.0, 0.0, -2.5), target=(0, 0, 0), width=64, height=64, f=64)
+    k2 = oracle.keys(pl, cam2)
+    for ty in range(4):
+        for tx in range(4):
+            got = np.uint32(oracle.tile_depth_bits(k2, 0, tx, ty)).view(np.float32)
+            assert abs(float(got) - 2.5) <= 2 * np.spacing(np.float32(2.5))
+
+
+def test_tile_depth_sort_orders_each_tile_by_its_own_depth():
+    sc = scenes.scene_uniform_cube(60, 44, scale_range=(0.05, 0.3), curv_lim=3.0)
+    cam = scenes.look_at((0.2, 0.1, -3.0), width=64, height=64, f=70)
+    ks = oracle.keys(sc, cam)
+    keys_, prims, ranges = oracle.bin_sort(ks, cam, tile_depth=True)
+    keys0, prims0, ranges0 = oracle.bin_sort(ks, cam)
+    assert np.array_equal(ranges, ranges0)   # same tile sets, other order inside
+    moved = 0
+    for t in range(len(ranges)):
+        s, e = ranges[t]
+        tx, ty = t % cam.tiles_x, t // cam.tiles_x
+        want = sorted(prims0[s:e], key=lambda p: (_numpy_tile_depth(sc, cam, p, tx, ty).view(np.uint32),
+                                                   int(ks["depth_bits"][p]), int(p)))
+        assert list(prims[s:e]) == [int(p) for p in want], t
+        moved += list(prims[s:e]) != list(prims0[s:e])
+    assert moved > 0
+
+
+def test_tile_depth_render_follows_the_tile_order():
+    sc = _stack_scene(45, 12)
+    cam = scenes.look_at((0.05, 0.02, -3.0), width=32, height=32, f=40)
+    ks = oracle.keys(sc, cam)
+    r = oracle.render(sc, cam, opts=dict(tile_depth=True), key_stage=ks, nthreads=2)
+    differs = 0
+    base = oracle.render(sc, cam, key_stage=ks, nthreads=2)
+    for py in range(0, 32, 3):
+        for px in range(0, 32, 3):
+            if r["margin"][py, px] < 1.0:
+                continue
+            tx, ty = px // 16, py // 16
+            order = sorted([i for i in range(sc.n) if not ks["culled"][i]],
+                           key=lambda i: (oracle.tile_depth_bits(ks, i, tx, ty), int(ks["depth_bits"][i]), i))
+            col, dep, T = _composite(_hits_along(sc, cam, px, py, order), sc)
+            assert np.allclose(r["color"][:, py, px], col, rtol=0, atol=1e-12)
+            differs += not np.allclose(base["color"][:, py, px], col, atol=1e-9)
+    assert differs > 0
+
+
+@pytest.mark.parametrize("seed", [51, 52, 53])
+def test_full_model_backward_matches_finite_differences(seed):
+    strict = dict(A=1e-3, D=1e-4, near=1e-4, E=1e-4, alpha_min=1e-4, T=1e-4, normal=1e-4, clamp=1e-4, median=1e-4,
+                  sort=1e-4)
+    opts = dict(resort=4, tile_depth=True)
+    cam = scenes.look_at((0.1, 0.05, -3.0), width=16, height=16, f=20)
+    for attempt in range(30):
+        s_ = seed + 1000 * attempt
+        n = 4 + seed % 4
+        sc = _fd_scene(s_, n)
+        rng = np.random.default_rng(100 + s_)
+        dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)),
+              rng.standard_normal((16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((16, 16)))
+        ks = oracle.keys(sc, cam)
+        base = oracle.render(sc, cam, opts=opts, dL=dL, key_stage=ks, delta=strict, nthreads=2)
+        if base["margin"].min() >= 1.0 and base["n_blend"].max() >= 3:
+            break
+    else:
+        pytest.fail("no base point away from decision boundaries")
+    p64 = [a.astype(np.float64) for a in sc.arrays()]
+
+    def loss(params):
+        r = oracle.render(sc, cam, opts=opts, params64=params, key_stage=ks, nthreads=2)
+        return float(np.sum(dL[0] * r["color"]) + np.sum(dL[1] * r["depth"]) + np.sum(dL[2] * r["normal"]) +
+                     np.sum(dL[3] * r["curvature"]) + np.sum(dL[4] * r["median_depth"]) +
+                     np.sum(dL[5] * r["distortion"]))
+
+    for ki, key in enumerate(FD_KEYS):
+        an = base["grads"][key]
+        fd = np.zeros_like(an)
+        flat = p64[ki].reshape(n, -1)
+        for p in range(n):
+            for j in range(flat.shape[1]):
+                hstep = 1e-6 * max(1.0, abs(flat[p, j]))
+                plus = [a.copy() for a in p64]
+                minus = [a.copy() for a in p64]
+                plus[ki].reshape(n, -1)[p, j] += hstep
+                minus[ki].reshape(n, -1)[p, j] -= hstep
+                fd.reshape(n, -1)[p, j] = (loss(plus) - loss(minus)) / (2 * hstep)
+        scale = np.abs(fd).max() + 1e-12
+        err = np.abs(an.reshape(fd.shape) - fd)
+        tol = 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9
+        assert np.all(err <= tol), (key, an, fd)
