@@ -90,6 +90,16 @@ typedef struct qgs_render_opts {
 #define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */
 #define QGS_ACCUMULATE_GRADS  2u /* backward: add into qgs_scene_grads instead of overwriting */
 #define QGS_COUNT_EVALS       4u /* forward: work counters into counters[2..7] */
+/* The paper's full-model ordering (supplement, per-tile sorting and per-pixel
+   resorting), both optional:
+   QGS_TILE_DEPTH  qgs_bin_sort keys each (tile, primitive) pair by the depth at
+                   which the ray through the tile's pixel nearest the projected
+                   vertex meets the paraboloid (needs prims->frame).
+   QGS_RESORT      the rasterizers pass accepted hits through a per-pixel buffer
+                   of 8 and blend the nearest whenever it is full; the backward
+                   then walks the lists front to back. */
+#define QGS_TILE_DEPTH        8u
+#define QGS_RESORT            16u
 
 /*
  * Per-primitive preprocess output (device memory, caller-allocated, n entries).
@@ -122,6 +132,10 @@ typedef struct qgs_prim_buf {
     uint32_t *pair_offset;
     double *conic;
     int64_t n;
+    /* optional (NULL: not written): [n][16] FP64 camera frame for the per-tile
+       sort depth: c_cam[3], camera-from-local rotation [9] row-major, projected
+       vertex u, v, lambda_1, lambda_2 */
+    double *frame;
 } qgs_prim_buf;
 
 /*

@@ -28,6 +28,8 @@ QGS_RECORD_BYTES = 128
 QGS_DETERMINISTIC_BWD = 1
 QGS_ACCUMULATE_GRADS = 2
 QGS_COUNT_EVALS = 4
+QGS_TILE_DEPTH = 8
+QGS_RESORT = 16
 
 
 class QgsScene(ctypes.Structure):
@@ -47,7 +49,7 @@ class QgsRenderOpts(ctypes.Structure):
 
 class QgsPrimBuf(ctypes.Structure):
     _fields_ = [("records", c_void_p), ("depth_key", c_void_p), ("rect", c_void_p), ("tiles", c_void_p),
-                ("pair_offset", c_void_p), ("conic", c_void_p), ("n", c_int64)]
+                ("pair_offset", c_void_p), ("conic", c_void_p), ("n", c_int64), ("frame", c_void_p)]
 
 
 class QgsTileLists(ctypes.Structure):

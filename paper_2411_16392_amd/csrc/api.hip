@@ -179,6 +179,7 @@ qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const q
     a.rect = out->rect;
     a.tiles = out->tiles;
     a.conic = out->conic;
+    a.frame = out->frame;
     return hip_status(launch_preprocess(a, (hipStream_t)stream));
 }
 
@@ -208,6 +209,9 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
     a.tile_order = lists->tile_order;
     a.counters = lists->counters;
     a.capacity = lists->capacity;
+    a.frame = (opts->flags & QGS_TILE_DEPTH) ? prims->frame : nullptr;
+    a.near_plane = opts->near_plane;
+    if ((opts->flags & QGS_TILE_DEPTH) && !prims->frame) return QGS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     qgs_status st = hip_status(bin_sort_phase1(a, w, s));
     if (st != QGS_OK) return st;

@@ -343,7 +343,8 @@ template <bool EMIT_INDEX>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
                                               const double *conic, int64_t n, qgs_camera cam, int32_t tiles_x,
                                               const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
-                                              uint32_t *emit_prim)
+                                              uint32_t *emit_prim, const double *frame, uint32_t *out_dkey,
+                                              float near_plane)
 {
     __shared__ ConicLane s_cl[256];
     if (counters[1]) return;  // overflow: the same for every thread
@@ -368,7 +369,21 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
         }
     }
     (void)wave_conic_tiles<true, EMIT_INDEX>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit,
-                                             emit_prim);
+                                             emit_prim, frame, out_dkey, (double)near_plane);
+}
+
+// tile-depth lists: after the depth passes the values are emission indices;
+// fetch each pair's tile as the key of the tile passes
+__global__ __launch_bounds__(256) void k_gather_tile_keys(const uint32_t *tile_by_emit, const uint32_t *vals, Count cnt,
+                                                          uint32_t *keys_out, uint32_t *vals_out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = cnt.get();
+    if (i >= n) return;
+    const uint32_t e = vals[i];
+    if (e >= n) return;  // cannot happen for lists built here
+    keys_out[i] = tile_by_emit[e];
+    vals_out[i] = e;
 }
 
 // After the sort the values are emission indices: replace them by primitive
@@ -382,7 +397,7 @@ __global__ __launch_bounds__(256) void k_gather_prims(const uint32_t *emit_prim,
     const uint32_t e = pair_prim[i];
     if (e >= n) return;  // cannot happen for lists built here
     pair_prim[i] = emit_prim[e];
-    emit_to_sorted[e] = (uint32_t)i;
+    if (emit_to_sorted) emit_to_sorted[e] = (uint32_t)i;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
@@ -463,6 +478,7 @@ SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
     w.tileT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.primT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.emit_prim = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
+    w.dkeyT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.bytes = o;
     return w;
 }
@@ -525,31 +541,59 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
 {
     const int64_t n = a.n;
     hipError_t e = hipSuccess;
-    // emit into the buffer that makes the final pass land in the caller's lists
-    uint32_t *et = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
-    uint32_t *ep = (passes % 2 == 0) ? a.pair_prim : ws.primT;
     const bool emit_map = a.emit_to_sorted != nullptr;
-    if (emit_map)
-        hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA, ws.off,
-                           a.rect, a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
-    else
-        hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)cdiv((uint64_t)n, 256)), dim3(256), 0, stream, ws.dvA,
-                           ws.off, a.rect, a.conic, n, a.cam, a.tiles_x, a.counters, et, ep, ws.emit_prim);
     Count c{a.counters, bound};
-    uint32_t *ki = et, *vi = ep;
+    const unsigned eb = (unsigned)cdiv((uint64_t)n, 256), gb = (unsigned)cdiv(bound, 256);
+    uint32_t *ki, *vi;
+    bool values_are_emission = emit_map;
+    if (a.frame) {
+        // per-tile depth keys: emission writes (tile, depth key, emission
+        // index, primitive) by emission index; four stable passes over the
+        // depth key, then the tile passes on the gathered tiles (ties keep the
+        // emission order: centre depth, then primitive)
+        hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n, a.cam,
+                           a.tiles_x, a.counters, ws.tileT, ws.primT, ws.emit_prim, a.frame, ws.dkeyT,
+                           a.near_plane);
+        uint32_t *dk = ws.dkeyT, *dv = ws.primT, *ak = a.pair_tile, *av = a.pair_prim;
+        for (int pass = 0; pass < 4; ++pass) {
+            e = radix_pass<RS_ITEMS_TILE>(dk, dv, ak, av, c, bound, 8 * pass, ws, stream);
+            if (e != hipSuccess) return e;
+            uint32_t *tk = dk, *tv = dv;
+            dk = ak; dv = av; ak = tk; av = tv;
+        }
+        // (dk, dv) = (ws.dkeyT, ws.primT): sorted by depth key, values are
+        // emission indices; start the tile passes where they end in the lists
+        ki = (passes % 2 == 0) ? a.pair_tile : ws.dkeyT;
+        vi = (passes % 2 == 0) ? a.pair_prim : ws.primT;
+        hipLaunchKernelGGL(k_gather_tile_keys, dim3(gb), dim3(256), 0, stream, (const uint32_t *)ws.tileT,
+                           (const uint32_t *)ws.primT, c, ki, vi);
+        values_are_emission = true;
+    } else {
+        // emit into the buffers that make the final pass land in the caller's lists
+        ki = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
+        vi = (passes % 2 == 0) ? a.pair_prim : ws.primT;
+        if (emit_map)
+            hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
+                               a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
+                               (uint32_t *)nullptr, 0.0f);
+        else
+            hipLaunchKernelGGL(k_emit<false>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
+                               a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
+                               (uint32_t *)nullptr, 0.0f);
+    }
     for (int pass = 0; pass < passes; ++pass) {
-        uint32_t *ko = (ki == a.pair_tile) ? ws.tileT : a.pair_tile;
+        uint32_t *ko = (ki == a.pair_tile) ? (a.frame ? ws.dkeyT : ws.tileT) : a.pair_tile;
         uint32_t *vo = (vi == a.pair_prim) ? ws.primT : a.pair_prim;
         e = radix_pass<RS_ITEMS_TILE>(ki, vi, ko, vo, c, bound, 8 * pass, ws, stream);
         if (e != hipSuccess) return e;
         ki = ko;
         vi = vo;
     }
-    if (emit_map)
-        hipLaunchKernelGGL(k_gather_prims, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream,
-                           (const uint32_t *)ws.emit_prim, c, a.pair_prim, a.emit_to_sorted);
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(bound, 256)), dim3(256), 0, stream, (const uint32_t *)a.pair_tile,
-                       c, a.ranges, (uint32_t)ntiles);
+    if (values_are_emission)
+        hipLaunchKernelGGL(k_gather_prims, dim3(gb), dim3(256), 0, stream, (const uint32_t *)ws.emit_prim, c,
+                           a.pair_prim, a.emit_to_sorted);
+    hipLaunchKernelGGL(k_ranges, dim3(gb), dim3(256), 0, stream, (const uint32_t *)a.pair_tile, c, a.ranges,
+                       (uint32_t)ntiles);
     return hipGetLastError();
 }
 

@@ -141,6 +141,16 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     }
     const int tx0 = px0 / TILE, tx1 = px1 / TILE, ty0 = py0 / TILE, ty1 = py1 / TILE;
     rt[0] = tx0; rt[1] = ty0; rt[2] = tx1; rt[3] = ty1;
+    if (a.frame) {
+        // camera frame for the per-tile sort depth (projected vertex as for the record)
+        double *F = a.frame + 16 * p;
+        for (int i = 0; i < 3; ++i) F[i] = cc[i];
+        for (int i = 0; i < 9; ++i) F[3 + i] = Rc[i];
+        F[12] = fma(fx, cc[0] / cc[2], cxp);
+        F[13] = fma(fy, cc[1] / cc[2], cyp);
+        F[14] = l1;
+        F[15] = l2;
+    }
 
     // Ellipsoid enclosing the box's elliptic cylinder {x^2/hx^2 + y^2/hy^2 <= 1,
     // z in [zlo, zhi]}: squared semi-axes hx^2/(1-t), hy^2/(1-t), hz^2/t about

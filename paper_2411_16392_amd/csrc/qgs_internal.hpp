@@ -26,6 +26,7 @@ struct PreprocessArgs {
     int32_t *rect;
     uint32_t *tiles;
     double *conic;
+    double *frame;  // optional
 };
 
 struct PreprocessBwdArgs {
@@ -56,6 +57,7 @@ struct SortWorkspace {
     uint32_t *hist;                   // [256][nblocks]
     uint32_t *tileT, *primT;          // pair ping-pong [capacity]
     uint32_t *emit_prim;              // primitive of each emitted pair [capacity]
+    uint32_t *dkeyT;                  // per-tile depth key of each emitted pair [capacity]
     size_t bytes;
 };
 
@@ -72,6 +74,8 @@ struct BinSortArgs {
     int32_t tiles_x, tiles_y;
     uint32_t *pair_tile, *pair_prim, *emit_to_sorted, *ranges, *tile_order, *counters;
     uint64_t capacity;
+    const double *frame;  // non-null: key pairs by the per-tile depth
+    float near_plane;
 };
 
 // Phase 1: depth sort, offsets, counters.  Phase 2: emission, tile sort, ranges

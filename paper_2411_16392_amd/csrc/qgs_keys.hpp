@@ -55,6 +55,61 @@ __device__ inline bool conic_tile_hit(const double *C, double mx, double my, int
     return false;
 }
 
+// Per-tile sort depth (supplement, per-tile sorting): the camera depth at which
+// the ray through tile (tx, ty)'s pixel nearest the projected vertex meets the
+// paraboloid; the smallest root beyond the near plane, or the centre depth if
+// there is none.  F: the primitive's frame (c_cam, Rc, projected vertex,
+// lambda_1, lambda_2).  FP64, fixed operation order, no contraction; returns
+// the bits of the depth rounded to FP32.
+__device__ inline uint32_t tile_depth_bits(const double *F, int tx, int ty, const qgs_camera &cam, double near_d)
+{
+#pragma clang fp contract(off)
+    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+    const int ux0 = tx * 16, ux1 = (tx * 16 + 15) < cam.width - 1 ? tx * 16 + 15 : cam.width - 1;
+    const int vy0 = ty * 16, vy1 = (ty * 16 + 15) < cam.height - 1 ? ty * 16 + 15 : cam.height - 1;
+    const double fu = floor(F[12]), fv = floor(F[13]);
+    const int px = fu < (double)ux0 ? ux0 : (fu > (double)ux1 ? ux1 : (int)fu);
+    const int py = fv < (double)vy0 ? vy0 : (fv > (double)vy1 ? vy1 : (int)fv);
+    const double dx = (((double)px + 0.5) - cx) / fx, dy = (((double)py + 0.5) - cy) / fy;
+    double o[3], e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[k] = -((F[3 + k] * F[0] + F[6 + k] * F[1]) + F[9 + k] * F[2]);
+        e[k] = (F[3 + k] * dx + F[6 + k] * dy) + F[9 + k];
+    }
+    const double l1 = F[14], l2 = F[15];
+    const double A = (l1 * e[0]) * e[0] + (l2 * e[1]) * e[1];
+    const double B = 2.0 * ((l1 * o[0]) * e[0] + (l2 * o[1]) * e[1]) - e[2];
+    const double C = ((l1 * o[0]) * o[0] + (l2 * o[1]) * o[1]) - o[2];
+    double r0 = 0.0, r1 = 0.0;
+    int nr = 0;
+    if (fabs(A) <= 1e-12 * ((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])) {
+        if (B != 0.0) {
+            r0 = -C / B;
+            nr = 1;
+        }
+    } else {
+        const double D = B * B - 4.0 * (A * C);
+        if (D >= 0.0) {
+            const double sq = sqrt(D);
+            const double q = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            if (q != 0.0) {
+                r0 = q / A;
+                r1 = C / q;
+                nr = 2;
+            }
+        }
+    }
+    double z = F[2];
+    bool found = false;
+    if (nr >= 1 && r0 > near_d) {
+        z = r0;
+        found = true;
+    }
+    if (nr >= 2 && r1 > near_d && (!found || r1 < z)) z = r1;
+    return __float_as_uint((float)z);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-cooperative tile tests.  A primitive's candidate tiles are the tiles of
 // its rectangle, row-major.  Rather than one thread looping over its own
@@ -114,7 +169,9 @@ __device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
 // with emit_prim = prim (EMIT_INDEX), or out_emit = prim.
 template <bool EMIT, bool EMIT_INDEX = true>
 __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &me, const qgs_camera &cam,
-                                            int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim)
+                                            int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim,
+                                            const double *frame = nullptr, uint32_t *out_dkey = nullptr,
+                                            double near_d = 0.0)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t R = (me.nx > 0 && me.ny > 0) ? (uint32_t)me.nx * (uint32_t)me.ny : 0u;
@@ -144,6 +201,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
             if (k < q.cnt) {
                 const uint64_t e = q.base + k;
                 out_tile[e] = (uint32_t)(ty * tiles_x + tx);
+                if (out_dkey) out_dkey[e] = tile_depth_bits(frame + 16 * (size_t)q.prim, tx, ty, cam, near_d);
                 if (EMIT_INDEX) {
                     out_emit[e] = (uint32_t)e;
                     emit_prim[e] = q.prim;

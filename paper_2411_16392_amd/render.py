@@ -96,12 +96,14 @@ class FrameState:
     median_depth: torch.Tensor | None = None
     distortion: torch.Tensor | None = None
     median_pos: torch.Tensor | None = None
+    frame: torch.Tensor | None = None  # per-primitive frames for the per-tile sort depth
 
     def prim_buf(self) -> L.QgsPrimBuf:
         p = L.QgsPrimBuf()
         p.records, p.depth_key, p.rect = _ptr(self.records), _ptr(self.depth_key), _ptr(self.rect)
         p.tiles, p.pair_offset, p.n = _ptr(self.tiles), _ptr(self.pair_offset), self.n
         p.conic = _ptr(self.conic)
+        p.frame = _ptr(self.frame) if self.frame is not None else None
         return p
 
     def lists(self) -> L.QgsTileLists:
@@ -181,6 +183,8 @@ class Renderer:
             T_final=torch.empty((H, W), dtype=torch.float32, device=dev),
             last=torch.empty((H, W), dtype=torch.int32, device=dev),
         )
+        if self.opts.flags & L.QGS_TILE_DEPTH:
+            st.frame = torch.empty(max(n, 1) * 16, dtype=torch.float64, device=dev)
         if self.geometry:
             st.curvature = torch.empty((H, W), dtype=torch.float32, device=dev)
             st.median_depth = torch.empty((H, W), dtype=torch.float32, device=dev)

@@ -58,8 +58,8 @@ def check_keys(scene, cam, st):
     return ks
 
 
-def check_lists(ks, cam, st):
-    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+def check_lists(ks, cam, st, tile_depth=False):
+    keys_, prims, ranges = oracle.bin_sort(ks, cam, tile_depth=tile_depth)
     npairs = len(prims)
     if st.emit_to_sorted is not None:
         # emit_to_sorted: primitive p's pairs (row-major tiles) start at
@@ -112,6 +112,30 @@ def test_keys_and_lists_bitexact_headline_size():
         ks = check_keys(c.scene, cam, st)
         n = check_lists(ks, cam, st)
         assert n > 1_000_000
+
+
+@pytest.mark.parametrize("ci,det", [(0, False), (1, True)])
+def test_keys_and_lists_bitexact_tile_depth(ci, det):
+    # per-tile sort depth: every (tile, primitive) pair keyed by the depth of
+    # the ray through the tile's pixel nearest the projected vertex
+    c = cfg(ci)
+    cam = c.cameras[0]
+    flags = L.QGS_TILE_DEPTH | (L.QGS_DETERMINISTIC_BWD if det else 0)
+    r, st = gpu_forward(c.scene, cam, opts=dict(flags=flags))
+    ks = check_keys(c.scene, cam, st)
+    fr = to_np(st.frame).reshape(-1, 16)
+    live = ks["tiles"] > 0
+    assert np.array_equal(fr[live].view(np.uint64), ks["frame"][live].view(np.uint64)), "frames"
+    check_lists(ks, cam, st, tile_depth=True)
+
+
+def test_keys_and_lists_bitexact_tile_depth_headline():
+    c = cfg(2, n_views=64)
+    cam = c.cameras[9]
+    r, st = gpu_forward(c.scene, cam, opts=dict(flags=L.QGS_TILE_DEPTH))
+    ks = check_keys(c.scene, cam, st)
+    n = check_lists(ks, cam, st, tile_depth=True)
+    assert n > 1_000_000
 
 
 def test_keys_and_lists_bitexact_unbounded():
