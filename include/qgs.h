@@ -280,7 +280,9 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
  * near/far root selection and the k_sigma geodesic cut-off, geodesic Gaussian
  * density, front-to-back compositing with stop once T would fall below T_eps.
  * Writes all planes of `out`; the geometry maps only if they are set (all four
- * or none).  Errors: QGS_ERR_INVALID_ARG.
+ * or none).  With QGS_RESORT, accepted hits pass through the per-pixel buffer
+ * (depth and normal planes required) and `last` is 1 + the list position of
+ * the last hit the pixel took in.  Errors: QGS_ERR_INVALID_ARG.
  */
 qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists, const qgs_camera *cam,
                           const qgs_render_opts *opts, qgs_images *out, qgs_stream_t stream);
@@ -293,7 +295,11 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
  * global atomic per field per (tile, primitive); QGS_DETERMINISTIC_BWD instead
  * stores one partial per pair and sums each primitive's partials in a fixed
  * order.  Then the chain rule to the scene parameters, one thread per
- * primitive.  `fwd` must hold T_final and last from the matching forward, and
+ * primitive.  With QGS_RESORT the lists are walked front to back instead,
+ * replaying each pixel's resort buffer up to its `last` (supplement,
+ * front-to-back form of the adjoint), and `fwd` must also hold the forward's
+ * colour, depth and normal (and curvature with geometry gradients).
+ * `fwd` must hold T_final and last from the matching forward, and
  * with any geometry gradient also its depth, distortion and median_pos (the
  * distortion adjoint needs the pixel's sum of weights, 1 - T_final, its mean
  * depth and its distortion; the median's gradient goes to the median entry).

@@ -28,7 +28,7 @@ DEFAULT_OPTS = dict(near=0.2, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99
 # Margin scales for the discrete decisions: a pixel whose relative distance to a
 # decision boundary is below its scale is reported with margin < 1.
 DEFAULT_DELTA = dict(A=1e-3, D=1e-6, near=1e-5, E=1e-5, alpha_min=1e-4, T=1e-4,
-                     normal=1e-4, clamp=1e-4, median=1e-5, sort=1e-5)
+                     normal=1e-4, clamp=1e-4, median=1e-5, sort=3e-6)
 _DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median", "sort"]
 
 

@@ -243,7 +243,9 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
                       (out->median_pos != nullptr);
     if (n_geo != 0 && n_geo != 4) return QGS_ERR_INVALID_ARG;
     if (n_geo == 4 && !out->depth) return QGS_ERR_INVALID_ARG;
+    if ((opts->flags & QGS_RESORT) && !out->depth) return QGS_ERR_INVALID_ARG;
     FwdOut o;
+    o.flags = opts->flags;
     o.color = out->color;
     o.depth = out->depth;
     o.normal = out->normal;
@@ -272,6 +274,9 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     if (geo && (!fwd->depth || !fwd->distortion || !fwd->median_pos)) return QGS_ERR_INVALID_ARG;
     const bool det = (opts->flags & QGS_DETERMINISTIC_BWD) != 0;
     if (det && lists->capacity > 0 && !lists->emit_to_sorted) return QGS_ERR_INVALID_ARG;
+    // the front-to-back adjoint of the resort mode needs every composited output
+    if ((opts->flags & QGS_RESORT) && (!fwd->color || !fwd->depth || !fwd->normal)) return QGS_ERR_INVALID_ARG;
+    if ((opts->flags & QGS_RESORT) && geo && !fwd->curvature) return QGS_ERR_INVALID_ARG;
     if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags)) return QGS_ERR_WORKSPACE;
     float *grad_rec = reinterpret_cast<float *>(ws);
     size_t off = ((size_t)(scene->n > 0 ? scene->n : 1) * 64 + 255) & ~(size_t)255;
@@ -289,6 +294,10 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.depth = fwd->depth;
     in.distortion = fwd->distortion;
     in.median_pos = fwd->median_pos;
+    in.color = fwd->color;
+    in.normal = fwd->normal;
+    in.curvature = fwd->curvature;
+    in.flags = opts->flags;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
                                                  grad_rec, scratch, scene->n, lists->capacity, s));
     if (st != QGS_OK) return st;

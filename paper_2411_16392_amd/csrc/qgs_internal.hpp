@@ -96,6 +96,7 @@ struct RasterArgs {
 struct FwdOut {
     float *color, *depth, *normal, *T_final;
     uint32_t *last;
+    uint32_t flags;      // QGS_RESORT selects the resort kernels
     uint32_t *counters;  // counters[2..4] of the tile lists, or null
     // geometry maps: all set or all null
     float *curvature, *median_depth, *distortion;
@@ -110,6 +111,10 @@ struct BwdIn {
     const float *dcurvature, *dmedian, *ddistortion;
     const float *depth, *distortion;
     const uint32_t *median_pos;
+    // the forward's colour, normal and curvature (the front-to-back adjoint of
+    // the resort mode needs every composited output)
+    const float *color, *normal, *curvature;
+    uint32_t flags;
 };
 
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream);

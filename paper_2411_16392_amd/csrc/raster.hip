@@ -592,10 +592,469 @@ __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, c
     grad_rec[16 * p + 15] = 0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// resort mode (supplement, per-pixel resorting)
+// ---------------------------------------------------------------------------
+// Each lane keeps its accepted hits in a buffer of RS_K entries; when the
+// buffer is full the nearest (smallest t, the earliest list position among
+// equal t) is blended, and at the end of the list the rest in the same way.
+// The buffer lives in registers: fixed-size arrays indexed only by unrolled
+// loops.
+constexpr int RS_K = 8;
+
+template <typename T, int N>
+__device__ inline T pick(const T (&v)[N], int k)
+{
+    T r = v[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+        if (i == k) r = v[i];
+    return r;
+}
+
+template <typename T, int N>
+__device__ inline void put(T (&v)[N], int k, T x)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i == k) v[i] = x;
+}
+
+// index of the nearest of the first cnt entries
+__device__ inline int nearest(const float (&t)[RS_K], const uint32_t (&pos)[RS_K], int cnt)
+{
+    int best = 0;
+    float bt = t[0];
+    uint32_t bp = pos[0];
+#pragma unroll
+    for (int i = 1; i < RS_K; ++i)
+        if (i < cnt && (t[i] < bt || (t[i] == bt && pos[i] < bp))) {
+            best = i;
+            bt = t[i];
+            bp = pos[i];
+        }
+    return best;
+}
+
+// local ray direction e = Rc^T (xn, yn, 1), as in ray_hit
+__device__ inline void local_dir(const Prim &p, const PixelRay &r, float &e0, float &e1, float &e2)
+{
+    e0 = __builtin_fmaf(p.R[0], r.xn, __builtin_fmaf(p.R[3], r.yn, p.R[6]));
+    e1 = __builtin_fmaf(p.R[1], r.xn, __builtin_fmaf(p.R[4], r.yn, p.R[7]));
+    e2 = __builtin_fmaf(p.R[2], r.xn, __builtin_fmaf(p.R[5], r.yn, p.R[8]));
+}
+
+template <bool GEO>
+__global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterParams P, FwdOut o)
+{
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
+    const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < P.width && py < P.height;
+    const uint32_t start = a.ranges[2 * tile], n = a.ranges[2 * tile + 1] - start;
+    const PixelRay ray = make_ray(px, py, P);
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
+    uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
+    bool done = !inside;
+    float kk = 0.0f, med = 0.0f, gW = 0.0f, gm = 0.0f, gL = 0.0f;
+    uint32_t med_pos = 0;
+    float bt[RS_K], ba[RS_K], bx[RS_K], by[RS_K];
+    uint32_t bpid[RS_K], bpos[RS_K];
+    int cnt = 0;
+
+    // blend the nearest pending hit (per lane)
+    auto pop_blend = [&]() {
+        const int k = nearest(bt, bpos, cnt);
+        const float t = pick(bt, k), alpha = pick(ba, k), x = pick(bx, k), y = pick(by, k);
+        const uint32_t pid = pick(bpid, k), pos1 = pick(bpos, k);
+        --cnt;
+        put(bt, k, pick(bt, cnt));
+        put(ba, k, pick(ba, cnt));
+        put(bx, k, pick(bx, cnt));
+        put(by, k, pick(by, cnt));
+        put(bpid, k, pick(bpid, cnt));
+        put(bpos, k, pick(bpos, cnt));
+        const float Tn = T * (1.0f - alpha);
+        if (Tn < P.T_eps) {
+            done = true;
+            stop_pos = last;
+            return;
+        }
+        const float wgt = alpha * T;
+        const float *w = reinterpret_cast<const float *>(recs + (size_t)pid * 8);
+        Prim p;
+        load_prim(w, P, p);
+        Hit H;
+        H.x = x;
+        H.y = y;
+        local_dir(p, ray, H.e0, H.e1, H.e2);
+        c0 = __builtin_fmaf(wgt, w[25], c0);
+        c1 = __builtin_fmaf(wgt, w[26], c1);
+        c2 = __builtin_fmaf(wgt, w[27], c2);
+        dep = __builtin_fmaf(wgt, t, dep);
+        float nl[3], il;
+        const float f = hit_normal(p, H, nl, il);
+        const float wf = wgt * f;
+        n0 = __builtin_fmaf(wf, __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2])), n0);
+        n1 = __builtin_fmaf(wf, __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2])), n1);
+        n2 = __builtin_fmaf(wf, __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2])), n2);
+        if (GEO) {
+            kk = __builtin_fmaf(wgt, hit_curvature(p, il), kk);
+            if (T > 0.5f && (med_pos == 0u || t > med)) {
+                med = t;
+                med_pos = pos1;
+            }
+            const float dtm = t - gm;
+            const float Xd = gW > 0.0f ? __builtin_fmaf(gW * dtm, dtm, gL * __builtin_amdgcn_rcpf(gW)) : 0.0f;
+            gL = __builtin_fmaf(wgt, Xd, gL);
+            gW += wgt;
+            gm = __builtin_fmaf(wgt * __builtin_amdgcn_rcpf(gW), dtm, gm);
+        }
+        T = Tn;
+        ++n_blend;
+    };
+
+    uint32_t nxt_pid = 0;
+    int4 nxt_rect = make_int4(0, -1, 0, -1);
+    if ((uint32_t)lane < n) {
+        nxt_pid = a.pair_prim[start + lane];
+        nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+    }
+    bool wave_alive = __ballot(!done) != 0ull;
+    for (uint32_t b = 0; b < n && wave_alive; b += 64) {
+        const uint32_t cur_pid = nxt_pid;
+        const int4 cur_rect = nxt_rect;
+        if (b + 64 + (uint32_t)lane < n) {
+            nxt_pid = a.pair_prim[start + b + 64 + lane];
+            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        }
+        const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                       cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        uint64_t m = __ballot(rel);
+        while (m != 0ull && wave_alive) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
+            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
+            float dxp, dyp;
+            const bool lane_on = !done && px >= x0 && px <= x1 && py >= y0 && py <= y1 && conic_offsets(w, ray, dxp, dyp);
+            if (__ballot(lane_on) == 0ull) continue;
+            const uint32_t pos1 = b + (uint32_t)j + 1u;
+            if (lane_on) {
+                Prim p;
+                load_prim(w, P, p);
+                Hit H;
+                ++n_eval;
+                if (ray_hit(p, ray, P, dxp, dyp, H)) {
+                    const float G = __expf(-0.5f * H.E);
+                    const float alpha = fminf(P.alpha_max, p.op * G);
+                    if (alpha >= P.alpha_min) {
+                        const float t = (p.Zc + H.s) * ray.enorm;
+                        put(bt, cnt, t);
+                        put(ba, cnt, alpha);
+                        put(bx, cnt, H.x);
+                        put(by, cnt, H.y);
+                        put(bpid, cnt, pj);
+                        put(bpos, cnt, pos1);
+                        ++cnt;
+                        last = pos1;
+                        if (cnt == RS_K) pop_blend();
+                    }
+                }
+            }
+            wave_alive = __ballot(!done) != 0ull;
+        }
+    }
+    // end of the list: blend what is pending, nearest first
+    while (cnt > 0 && !done) pop_blend();
+
+    if (inside) {
+        const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
+        o.color[pix] = c0 + T * P.bg[0];
+        o.color[hw + pix] = c1 + T * P.bg[1];
+        o.color[2 * hw + pix] = c2 + T * P.bg[2];
+        o.depth[pix] = dep;
+        o.normal[pix] = n0;
+        o.normal[hw + pix] = n1;
+        o.normal[2 * hw + pix] = n2;
+        if (o.T_final) o.T_final[pix] = T;
+        // the backward replays the entries up to the last one this pixel took in
+        if (o.last) o.last[pix] = last;
+        if (GEO) {
+            o.curvature[pix] = kk;
+            o.median_depth[pix] = med;
+            o.distortion[pix] = gL;
+            o.median_pos[pix] = med_pos;
+        }
+    }
+    if (o.counters) {
+        uint32_t c[3] = {inside ? (stop_pos ? stop_pos : n) : 0u, n_eval, n_blend};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t v = c[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && v) atomicAdd(o.counters + 2 + k, v);
+        }
+    }
+}
+
+// Backward of the resort mode, front to back (supplement, front-to-back form
+// of the adjoint): each pixel replays the forward's entries and buffer up to
+// its `last`, keeping T_i and the prefix sums P_i = sum_{j<i} w_j X_j, so the
+// suffix after entry i is S_i = X_hat - P_i - w_i X_i with X_hat the forward's
+// output, and dX/dalpha_i = T_i X_i - S_i / (1 - alpha_i).  A blended entry's
+// hit is recomputed from its record (lanes blend different entries at a
+// step), and the lanes of a step that blended the same primitive are reduced
+// together: one reduce-scatter and one 14-lane atomic per distinct primitive
+// (or, DET, an add into the pair's slot for this wave).
+template <bool DET, bool GEO>
+__global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterParams P, BwdIn in,
+                                                         const float4 *__restrict__ recs,
+                                                         float *__restrict__ grad_rec, float *__restrict__ pair_scratch)
+{
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
+    const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < P.width && py < P.height;
+    const uint32_t start = a.ranges[2 * tile], list_len = a.ranges[2 * tile + 1] - start;
+    const PixelRay ray = make_ray(px, py, P);
+
+    const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
+    constexpr int NX = GEO ? 9 : 7;
+    float gc[3] = {0, 0, 0}, gd = 0.0f, gn[3] = {0, 0, 0};
+    float Xh[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Xh[c] = 0.0f;
+    uint32_t last = 0;
+    float T = 1.0f;
+    if (inside) {
+        last = in.last[pix];
+        if (in.dcolor) {
+            gc[0] = in.dcolor[pix];
+            gc[1] = in.dcolor[hw + pix];
+            gc[2] = in.dcolor[2 * hw + pix];
+        }
+        if (in.ddepth) gd = in.ddepth[pix];
+        if (in.dnormal) {
+            gn[0] = in.dnormal[pix];
+            gn[1] = in.dnormal[hw + pix];
+            gn[2] = in.dnormal[2 * hw + pix];
+        }
+        Xh[0] = in.color[pix];
+        Xh[1] = in.color[hw + pix];
+        Xh[2] = in.color[2 * hw + pix];
+        Xh[3] = in.depth[pix];
+        Xh[4] = in.normal[pix];
+        Xh[5] = in.normal[hw + pix];
+        Xh[6] = in.normal[2 * hw + pix];
+    }
+    float gK = 0.0f, gmed = 0.0f, gdist = 0.0f, gW = 0.0f, gm = 0.0f, gLW = 0.0f;
+    uint32_t med_pos = 0;
+    if (GEO && inside) {
+        if (in.dcurvature) gK = in.dcurvature[pix];
+        if (in.dmedian) gmed = in.dmedian[pix];
+        if (in.ddistortion) gdist = in.ddistortion[pix];
+        med_pos = in.median_pos[pix];
+        gW = 1.0f - in.T_final[pix];
+        const float L = in.distortion[pix];
+        if (gW > 0.0f) {
+            const float iW = __builtin_amdgcn_rcpf(gW);
+            gm = in.depth[pix] * iW;
+            gLW = L * iW;
+        }
+        Xh[7] = in.curvature[pix];
+        Xh[8] = 2.0f * L;  // sum_i w_i (L / W + W (t_i - mean)^2)
+    }
+    float Pf[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Pf[c] = 0.0f;
+    bool done = !inside;
+    float bt[RS_K], ba[RS_K];
+    uint32_t bpid[RS_K], bpos[RS_K];
+    int cnt = 0;
+
+    // blend-backward of the nearest pending hit: per-lane gradient in gr
+    auto pop_grad = [&](float (&gr)[NGRAD], uint32_t &g_pid, uint32_t &g_pos) -> bool {
+        const int k = nearest(bt, bpos, cnt);
+        const float alpha = pick(ba, k);
+        const uint32_t pid = pick(bpid, k), pos1 = pick(bpos, k);
+        --cnt;
+        put(bt, k, pick(bt, cnt));
+        put(ba, k, pick(ba, cnt));
+        put(bpid, k, pick(bpid, cnt));
+        put(bpos, k, pick(bpos, cnt));
+        const float om = 1.0f - alpha;
+        const float Tn = T * om;
+        if (Tn < P.T_eps) {
+            done = true;
+            return false;
+        }
+        const float *wr = reinterpret_cast<const float *>(recs + (size_t)pid * 8);
+        Prim p;
+        load_prim(wr, P, p);
+        float dxp, dyp;
+        (void)conic_offsets(wr, ray, dxp, dyp);
+        Hit H;
+        if (!ray_hit(p, ray, P, dxp, dyp, H)) {  // cannot happen: the same hit was accepted before
+            T = Tn;
+            return false;
+        }
+        const float G = __expf(-0.5f * H.E);
+        const float w = alpha * T;
+        const float iom = __builtin_amdgcn_rcpf(om);
+        float X[NX];
+        X[0] = wr[25];
+        X[1] = wr[26];
+        X[2] = wr[27];
+        const float t = (p.Zc + H.s) * ray.enorm;
+        X[3] = t;
+        float nl[3], il;
+        const float f = hit_normal(p, H, nl, il);
+        X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
+        X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
+        X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
+        float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+        float dt = gd * w;
+        if (GEO) {
+            const float dtm = t - gm;
+            X[7] = hit_curvature(p, il);
+            X[8] = __builtin_fmaf(gW * dtm, dtm, gLW);
+            gx[7] = gK;
+            gx[8] = gdist;
+            dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
+            if (pos1 == med_pos) dt += gmed;
+        }
+        float dalpha = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+            const float wx = w * X[c];
+            const float Sx = (Xh[c] - Pf[c]) - wx;  // suffix after this entry
+            dalpha += gx[c] * (T * X[c] - Sx * iom);
+            Pf[c] += wx;
+        }
+        const float rgb[3] = {X[0], X[1], X[2]};
+        entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
+        T = Tn;
+        g_pid = pid;
+        g_pos = pos1;
+        return true;
+    };
+
+    // the lanes of this step that blended the same primitive are reduced together
+    auto flush_grads = [&](const float (&gr)[NGRAD], bool has, uint32_t g_pid, uint32_t g_pos) {
+        uint64_t rem = __ballot(has);
+        while (rem != 0ull) {
+            const int l0 = __builtin_ctzll(rem);
+            const uint32_t pid0 = (uint32_t)__builtin_amdgcn_readlane((int)g_pid, l0);
+            const uint32_t pos0 = (uint32_t)__builtin_amdgcn_readlane((int)g_pos, l0);
+            const bool mine = has && g_pid == pid0;
+            rem &= ~__ballot(mine);
+            float g16[16];
+#pragma unroll
+            for (int f = 0; f < 16; ++f) g16[f] = (mine && f < NGRAD) ? gr[f] : 0.0f;
+            const float tot = wave_reduce_scatter16(g16);
+            const int f = lane >> 2;
+            if ((lane & 3) == 0 && f < NGRAD) {
+                if (DET) {
+                    // the pair's slot for this wave; only this wave adds to it
+                    float *dst = pair_scratch + ((size_t)start + pos0 - 1u) * 64 + wave * 16 + f;
+                    *dst += tot;
+                } else if (tot != 0.0f) {
+                    unsafeAtomicAdd(grad_rec + (size_t)pid0 * 16 + f, tot);
+                }
+            }
+        }
+    };
+
+    const uint32_t wmax = wave_max_u32(last);
+    const uint32_t nmax = wmax < list_len ? wmax : list_len;
+    uint32_t nxt_pid = 0;
+    int4 nxt_rect = make_int4(0, -1, 0, -1);
+    if ((uint32_t)lane < nmax) {
+        nxt_pid = a.pair_prim[start + lane];
+        nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+    }
+    for (uint32_t b = 0; b < nmax; b += 64) {
+        const uint32_t cur_pid = nxt_pid;
+        const int4 cur_rect = nxt_rect;
+        if (b + 64 + (uint32_t)lane < nmax) {
+            nxt_pid = a.pair_prim[start + b + 64 + lane];
+            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        }
+        const bool rel = b + (uint32_t)lane < nmax && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                          cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        uint64_t m = __ballot(rel);
+        while (m != 0ull) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
+            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
+            const uint32_t pos1 = b + (uint32_t)j + 1u;
+            float dxp, dyp;
+            const bool lane_on = !done && pos1 <= last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
+                                 conic_offsets(w, ray, dxp, dyp);
+            if (__ballot(lane_on) == 0ull) continue;
+            float gr[NGRAD];
+#pragma unroll
+            for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
+            bool has = false;
+            uint32_t g_pid = 0, g_pos = 0;
+            if (lane_on) {
+                Prim p;
+                load_prim(w, P, p);
+                Hit H;
+                if (ray_hit(p, ray, P, dxp, dyp, H)) {
+                    const float G = __expf(-0.5f * H.E);
+                    const float alpha = fminf(P.alpha_max, p.op * G);
+                    if (alpha >= P.alpha_min) {
+                        put(bt, cnt, (p.Zc + H.s) * ray.enorm);
+                        put(ba, cnt, alpha);
+                        put(bpid, cnt, pj);
+                        put(bpos, cnt, pos1);
+                        ++cnt;
+                        if (cnt == RS_K) has = pop_grad(gr, g_pid, g_pos);
+                    }
+                }
+            }
+            if (__ballot(has) != 0ull) flush_grads(gr, has, g_pid, g_pos);
+        }
+    }
+    // end of the replay: the pending hits, nearest first
+    while (__ballot(cnt > 0 && !done) != 0ull) {
+        float gr[NGRAD];
+#pragma unroll
+        for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
+        bool has = false;
+        uint32_t g_pid = 0, g_pos = 0;
+        if (cnt > 0 && !done) has = pop_grad(gr, g_pid, g_pos);
+        if (__ballot(has) != 0ull) flush_grads(gr, has, g_pid, g_pos);
+    }
+}
+
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream)
 {
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
     if (ntiles == 0) return hipSuccess;
+    if (o.flags & QGS_RESORT) {
+        if (o.curvature)
+            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        else
+            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        return hipGetLastError();
+    }
     if (o.curvature)
         hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
     else if (o.depth)
@@ -613,6 +1072,30 @@ hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const B
     if (e != hipSuccess) return e;
     if (ntiles == 0) return hipSuccess;
     const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
+    if (in.flags & QGS_RESORT) {
+        if (pair_scratch) {
+            e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
+            if (e != hipSuccess) return e;
+            if (geo)
+                hipLaunchKernelGGL((k_render_bwd_rs<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+                                   grad_rec, pair_scratch);
+            else
+                hipLaunchKernelGGL((k_render_bwd_rs<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                                   recs, grad_rec, pair_scratch);
+            if (n_prims > 0)
+                hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
+                                   (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
+                                   capacity, grad_rec);
+        } else if (geo) {
+            hipLaunchKernelGGL((k_render_bwd_rs<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+                               grad_rec, pair_scratch);
+        } else {
+            hipLaunchKernelGGL((k_render_bwd_rs<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+                               grad_rec, pair_scratch);
+        }
+        return hipGetLastError();
+    }
     if (pair_scratch) {
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
         if (e != hipSuccess) return e;
