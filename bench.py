@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-no-graphs", action="store_true", help="serving with direct launches instead of graphs")
+    ap.add_argument("--full-model", action="store_true",
+                    help="the paper's full-model ordering (per-tile sort depth and the 8-entry resort buffer)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -132,7 +134,8 @@ def main():
     # size the pair capacity once, untimed, from exact counts of the views used
     steps_total = args.warmup + args.steps
     used = sorted({i % len(cams) for i in range(steps_total)})
-    probe = R.Renderer(device=dev)
+    mode = (L.QGS_TILE_DEPTH | L.QGS_RESORT) if args.full_model else 0
+    probe = R.Renderer(device=dev, opts=R.make_opts(flags=mode))
     max_pairs = 0
     for v in used:
         st = probe.preprocess(sc_t, cams[v])
@@ -142,7 +145,7 @@ def main():
     log(f"[bench] max pairs over used views {max_pairs}, capacity {capacity}", q)
 
     # evaluation counts (untimed): list entries processed and blended pairs
-    cnt_r = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=L.QGS_COUNT_EVALS))
+    cnt_r = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=L.QGS_COUNT_EVALS | mode))
     evals_per_view = []
     for v in used[: min(8, len(used))]:
         st = cnt_r.forward(sc_t, cams[v], exact=False)
@@ -150,7 +153,7 @@ def main():
         evals_per_view.append(int(st.counters.cpu().numpy().view(np.uint32)[2]))
     evals_mean = float(np.mean(evals_per_view))
 
-    rend = R.Renderer(device=dev, capacity=capacity)
+    rend = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=mode))
     gen = torch.Generator(device=dev)
     gen.manual_seed(2)
     dLs = [(torch.randn((3, H, W), generator=gen, device=dev), torch.randn((H, W), generator=gen, device=dev),
@@ -254,7 +257,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "500K quadrics on 8 noisy ellipsoids, 1600x1200 ring views (64), fwd+bwd per view, "
                                "N(0,1) upstream gradients",
-                   "n_prims": cfg.scene.n, "width": W, "height": H, "views": len(cams)},
+                   "n_prims": cfg.scene.n, "width": W, "height": H, "views": len(cams),
+                   "ordering": "per-tile depth + 8-entry resort" if args.full_model else "centre depth"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs_per_view": int(np.mean(npairs)),
         "evals_per_view": int(evals_mean),
