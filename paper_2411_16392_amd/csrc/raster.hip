@@ -598,43 +598,56 @@ __global__ __launch_bounds__(256) void k_det_reduce(const float *pair_scratch, c
 // Each lane keeps its accepted hits in a buffer of RS_K entries; when the
 // buffer is full the nearest (smallest t, the earliest list position among
 // equal t) is blended, and at the end of the list the rest in the same way.
-// The buffer lives in registers: fixed-size arrays indexed only by unrolled
-// loops.
+// The buffer lives in registers: it is kept sorted by (t, position) and every
+// access uses a compile-time index (insertion shifts by one slot, the nearest
+// is slot 0), so no array is ever indexed at run time.
 constexpr int RS_K = 8;
 
-template <typename T, int N>
-__device__ inline T pick(const T (&v)[N], int k)
-{
-    T r = v[0];
-#pragma unroll
-    for (int i = 1; i < N; ++i)
-        if (i == k) r = v[i];
-    return r;
-}
+template <int NF>
+struct ResortBuf {
+    float t[RS_K];
+    float f[NF][RS_K];
+    uint32_t pid[RS_K], pos[RS_K];
+    int cnt;
 
-template <typename T, int N>
-__device__ inline void put(T (&v)[N], int k, T x)
-{
+    __device__ inline void insert(float xt, const float (&xf)[NF], uint32_t xpid, uint32_t xpos)
+    {
+        // entries already held come first on equal t (their positions are smaller)
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-        if (i == k) v[i] = x;
-}
-
-// index of the nearest of the first cnt entries
-__device__ inline int nearest(const float (&t)[RS_K], const uint32_t (&pos)[RS_K], int cnt)
-{
-    int best = 0;
-    float bt = t[0];
-    uint32_t bp = pos[0];
+        for (int i = RS_K - 1; i >= 0; --i) {
+            if (i > cnt) continue;
+            const bool keep = i < cnt && t[i] <= xt;
+            if (keep) continue;
+            const int j = i > 0 ? i - 1 : 0;
+            const bool here = i == 0 || t[j] <= xt;
+            t[i] = here ? xt : t[j];
 #pragma unroll
-    for (int i = 1; i < RS_K; ++i)
-        if (i < cnt && (t[i] < bt || (t[i] == bt && pos[i] < bp))) {
-            best = i;
-            bt = t[i];
-            bp = pos[i];
+            for (int k = 0; k < NF; ++k) f[k][i] = here ? xf[k] : f[k][j];
+            pid[i] = here ? xpid : pid[j];
+            pos[i] = here ? xpos : pos[j];
         }
-    return best;
-}
+        ++cnt;
+    }
+
+    // removes the nearest entry (slot 0) into the outputs
+    __device__ inline void pop(float &xt, float (&xf)[NF], uint32_t &xpid, uint32_t &xpos)
+    {
+        xt = t[0];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) xf[k] = f[k][0];
+        xpid = pid[0];
+        xpos = pos[0];
+#pragma unroll
+        for (int i = 0; i + 1 < RS_K; ++i) {
+            t[i] = t[i + 1];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) f[k][i] = f[k][i + 1];
+            pid[i] = pid[i + 1];
+            pos[i] = pos[i + 1];
+        }
+        --cnt;
+    }
+};
 
 // local ray direction e = Rc^T (xn, yn, 1), as in ray_hit
 __device__ inline void local_dir(const Prim &p, const PixelRay &r, float &e0, float &e1, float &e2)
@@ -663,22 +676,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
     bool done = !inside;
     float kk = 0.0f, med = 0.0f, gW = 0.0f, gm = 0.0f, gL = 0.0f;
     uint32_t med_pos = 0;
-    float bt[RS_K], ba[RS_K], bx[RS_K], by[RS_K];
-    uint32_t bpid[RS_K], bpos[RS_K];
-    int cnt = 0;
+    ResortBuf<3> buf;  // fields: alpha, x, y
+    buf.cnt = 0;
 
     // blend the nearest pending hit (per lane)
     auto pop_blend = [&]() {
-        const int k = nearest(bt, bpos, cnt);
-        const float t = pick(bt, k), alpha = pick(ba, k), x = pick(bx, k), y = pick(by, k);
-        const uint32_t pid = pick(bpid, k), pos1 = pick(bpos, k);
-        --cnt;
-        put(bt, k, pick(bt, cnt));
-        put(ba, k, pick(ba, cnt));
-        put(bx, k, pick(bx, cnt));
-        put(by, k, pick(by, cnt));
-        put(bpid, k, pick(bpid, cnt));
-        put(bpos, k, pick(bpos, cnt));
+        float t, fv[3];
+        uint32_t pid, pos1;
+        buf.pop(t, fv, pid, pos1);
+        const float alpha = fv[0], x = fv[1], y = fv[2];
         const float Tn = T * (1.0f - alpha);
         if (Tn < P.T_eps) {
             done = true;
@@ -757,15 +763,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
                         const float t = (p.Zc + H.s) * ray.enorm;
-                        put(bt, cnt, t);
-                        put(ba, cnt, alpha);
-                        put(bx, cnt, H.x);
-                        put(by, cnt, H.y);
-                        put(bpid, cnt, pj);
-                        put(bpos, cnt, pos1);
-                        ++cnt;
+                        const float fv[3] = {alpha, H.x, H.y};
+                        buf.insert(t, fv, pj, pos1);
                         last = pos1;
-                        if (cnt == RS_K) pop_blend();
+                        if (buf.cnt == RS_K) pop_blend();
                     }
                 }
             }
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
         }
     }
     // end of the list: blend what is pending, nearest first
-    while (cnt > 0 && !done) pop_blend();
+    while (buf.cnt > 0 && !done) pop_blend();
 
     if (inside) {
         const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
@@ -880,20 +881,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
 #pragma unroll
     for (int c = 0; c < NX; ++c) Pf[c] = 0.0f;
     bool done = !inside;
-    float bt[RS_K], ba[RS_K];
-    uint32_t bpid[RS_K], bpos[RS_K];
-    int cnt = 0;
+    ResortBuf<1> buf;  // field: alpha
+    buf.cnt = 0;
 
     // blend-backward of the nearest pending hit: per-lane gradient in gr
     auto pop_grad = [&](float (&gr)[NGRAD], uint32_t &g_pid, uint32_t &g_pos) -> bool {
-        const int k = nearest(bt, bpos, cnt);
-        const float alpha = pick(ba, k);
-        const uint32_t pid = pick(bpid, k), pos1 = pick(bpos, k);
-        --cnt;
-        put(bt, k, pick(bt, cnt));
-        put(ba, k, pick(ba, cnt));
-        put(bpid, k, pick(bpid, cnt));
-        put(bpos, k, pick(bpos, cnt));
+        float tq, fv[1];
+        uint32_t pid, pos1;
+        buf.pop(tq, fv, pid, pos1);
+        const float alpha = fv[0];
         const float om = 1.0f - alpha;
         const float Tn = T * om;
         if (Tn < P.T_eps) {
@@ -1020,12 +1016,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
-                        put(bt, cnt, (p.Zc + H.s) * ray.enorm);
-                        put(ba, cnt, alpha);
-                        put(bpid, cnt, pj);
-                        put(bpos, cnt, pos1);
-                        ++cnt;
-                        if (cnt == RS_K) has = pop_grad(gr, g_pid, g_pos);
+                        const float fv[1] = {alpha};
+                        buf.insert((p.Zc + H.s) * ray.enorm, fv, pj, pos1);
+                        if (buf.cnt == RS_K) has = pop_grad(gr, g_pid, g_pos);
                     }
                 }
             }
@@ -1033,13 +1026,13 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         }
     }
     // end of the replay: the pending hits, nearest first
-    while (__ballot(cnt > 0 && !done) != 0ull) {
+    while (__ballot(buf.cnt > 0 && !done) != 0ull) {
         float gr[NGRAD];
 #pragma unroll
         for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
         bool has = false;
         uint32_t g_pid = 0, g_pos = 0;
-        if (cnt > 0 && !done) has = pop_grad(gr, g_pid, g_pos);
+        if (buf.cnt > 0 && !done) has = pop_grad(gr, g_pid, g_pos);
         if (__ballot(has) != 0ull) flush_grads(gr, has, g_pid, g_pos);
     }
 }
