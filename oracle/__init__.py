@@ -58,7 +58,8 @@ def _lib():
         L.oracle_tile_depth_bits.restype = ctypes.c_uint32
         L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                     i32, i32, i32, i32, i32,
-                                    P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+                                    P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
+                                    P, i32, P]
         L.oracle_render.restype = i64
         L.oracle_gfun.argtypes = [f64]
         L.oracle_gfun.restype = f64
@@ -191,7 +192,11 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     x0, y0, w, h = window if window is not None else (0, 0, cam.width, cam.height)
     n = scene.n
     prm = params64 if params64 is not None else scene.arrays()
-    arrs = [_f64(a) for a in prm]
+    arrs = [_f64(a) for a in prm[:6]]
+    # SH colour: params64 may carry the coefficients as a seventh array
+    sh = prm[6] if len(prm) > 6 else scene.sh
+    sh64 = _f64(sh) if sh is not None else None
+    sh_deg = -1 if sh is None else int(round(np.sqrt(np.asarray(sh).shape[1]))) - 1
     camv = cam_array(cam, np.float64) if cam_vec64 is None else _f64(cam_vec64)
     color = np.zeros((3, h, w)); depth = np.zeros((h, w)); normal = np.zeros((3, h, w))
     T = np.zeros((h, w)); nb = np.zeros((h, w), np.int32); margin = np.zeros((h, w))
@@ -208,6 +213,8 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
                  (list(dL[3:6]) + [None] * 3)[:3]]
         grads = dict(center=np.zeros((n, 3)), quat=np.zeros((n, 4)), scale=np.zeros((n, 2)),
                      curv=np.zeros((n, 2)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+        if sh is not None:
+            grads["sh"] = np.zeros(np.asarray(sh).shape)
         gp = ([_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(m) if m is not None else None for m in extra] +
               [_ptr(grads[k]) for k in ("center", "quat", "scale", "curv", "opacity", "rgb")])
     o_d = dict(DEFAULT_OPTS)
@@ -219,7 +226,9 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
                               _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv),
                               x0, y0, w, h, int(nthreads),
                               _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin),
-                              _ptr(curvature), _ptr(median), _ptr(dist), *gp)
+                              _ptr(curvature), _ptr(median), _ptr(dist), *gp,
+                              _ptr(sh64) if sh64 is not None else None, sh_deg,
+                              _ptr(grads["sh"]) if (grads is not None and sh is not None) else None)
     if ev < 0:
         raise ValueError("bad window")
     out = dict(color=color, depth=depth, normal=normal, curvature=curvature, median_depth=median,
@@ -227,6 +236,14 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     if grads is not None:
         out["grads"] = grads
     return out
+
+
+def sh_basis(deg, d):
+    """Real SH basis values Y[16] and their gradients dY[16][3] at direction d."""
+    Y = np.zeros(16)
+    dY = np.zeros((16, 3))
+    _lib().oracle_sh_basis(int(deg), _ptr(_f64(d)), _ptr(Y), _ptr(dY))
+    return Y, dY
 
 
 def ray_hit(center, quat, scale, curv, cam_vec64, dcam, opts=None):

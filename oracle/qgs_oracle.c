@@ -439,6 +439,86 @@ typedef struct {
     double qn[4], qlen;
 } oprim;
 
+/*
+ * Spherical-harmonics colour (the 3DGS colour model the paper keeps, Sec. 3):
+ * rgb_c = max(0, sum_k sh[k][c] Y_k(d) + 1/2) for the unit direction d from
+ * the camera centre to the primitive centre, with the real spherical harmonics
+ * of degree <= 3 written out from their definitions (normalisation
+ * sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!), Condon-Shortley phase), in the order
+ * l = 0..3, m = -l..l.
+ */
+static void sh_basis(int deg, double x, double y, double z, double Y[16], double dY[16][3])
+{
+    const double pi = 3.14159265358979323846;
+    const double c0 = 0.5 * sqrt(1.0 / pi), c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi), c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi);
+    const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi), c3e = 0.25 * sqrt(105.0 / pi);
+    for (int k = 0; k < 16; ++k) {
+        Y[k] = 0.0;
+        dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+    }
+    Y[0] = c0;
+    if (deg < 1) return;
+    Y[1] = -c1 * y; dY[1][1] = -c1;
+    Y[2] = c1 * z;  dY[2][2] = c1;
+    Y[3] = -c1 * x; dY[3][0] = -c1;
+    if (deg < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c2a * x * y;             dY[4][0] = c2a * y;  dY[4][1] = c2a * x;
+    Y[5] = -c2a * y * z;            dY[5][1] = -c2a * z; dY[5][2] = -c2a * y;
+    Y[6] = c2b * (2 * zz - xx - yy); dY[6][0] = -2 * c2b * x; dY[6][1] = -2 * c2b * y; dY[6][2] = 4 * c2b * z;
+    Y[7] = -c2a * x * z;            dY[7][0] = -c2a * z; dY[7][2] = -c2a * x;
+    Y[8] = c2c * (xx - yy);         dY[8][0] = 2 * c2c * x; dY[8][1] = -2 * c2c * y;
+    if (deg < 3) return;
+    Y[9] = -c3a * y * (3 * xx - yy);
+    dY[9][0] = -c3a * 6 * x * y; dY[9][1] = -c3a * (3 * xx - 3 * yy);
+    Y[10] = c3b * x * y * z;
+    dY[10][0] = c3b * y * z; dY[10][1] = c3b * x * z; dY[10][2] = c3b * x * y;
+    Y[11] = -c3c * y * (4 * zz - xx - yy);
+    dY[11][0] = c3c * 2 * x * y; dY[11][1] = -c3c * (4 * zz - xx - 3 * yy); dY[11][2] = -c3c * 8 * y * z;
+    Y[12] = c3d * z * (2 * zz - 3 * xx - 3 * yy);
+    dY[12][0] = -c3d * 6 * x * z; dY[12][1] = -c3d * 6 * y * z; dY[12][2] = c3d * (6 * zz - 3 * xx - 3 * yy);
+    Y[13] = -c3c * x * (4 * zz - xx - yy);
+    dY[13][0] = -c3c * (4 * zz - 3 * xx - yy); dY[13][1] = c3c * 2 * x * y; dY[13][2] = -c3c * 8 * x * z;
+    Y[14] = c3e * z * (xx - yy);
+    dY[14][0] = c3e * 2 * x * z; dY[14][1] = -c3e * 2 * y * z; dY[14][2] = c3e * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3 * yy);
+    dY[15][0] = -c3a * (3 * xx - 3 * yy); dY[15][1] = c3a * 6 * x * y;
+}
+
+void oracle_sh_basis(int32_t deg, const double *d, double *Y, double *dY)
+{
+    double yy[16], dd[16][3];
+    sh_basis(deg, d[0], d[1], d[2], yy, dd);
+    for (int k = 0; k < 16; ++k) {
+        Y[k] = yy[k];
+        for (int j = 0; j < 3; ++j) dY[3 * k + j] = dd[k][j];
+    }
+}
+
+/* colour from SH coefficients sh[K][3] at the primitive centre c (world);
+   also the unit direction, its length and which channels are not clamped */
+static void sh_colour(int deg, const double *sh, const double *c, const double *W, const double *T, double rgb[3],
+                      double dir[3], double *dist, int live[3])
+{
+    /* camera centre o = -W^T t */
+    double v[3];
+    for (int j = 0; j < 3; ++j) v[j] = c[j] + (W[j] * T[0] + W[3 + j] * T[1] + W[6 + j] * T[2]);
+    const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int j = 0; j < 3; ++j) dir[j] = v[j] / r;
+    *dist = r;
+    double Y[16], dY[16][3];
+    sh_basis(deg, dir[0], dir[1], dir[2], Y, dY);
+    const int K = (deg + 1) * (deg + 1);
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.5;
+        for (int k = 0; k < K; ++k) acc += sh[3 * k + ch] * Y[k];
+        live[ch] = acc > 0.0;
+        rgb[ch] = acc > 0.0 ? acc : 0.0;
+    }
+}
+
 static void setup_prim(const double *c, const double *q, const double *s, const double *l,
                        double op, const double *rgb, const double *W, const double *T, oprim *P)
 {
@@ -1021,7 +1101,7 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
                       const double *dL_color, const double *dL_depth, const double *dL_normal,
                       const double *dL_curv, const double *dL_median, const double *dL_dist,
                       double *g_center, double *g_quat, double *g_scale, double *g_curv,
-                      double *g_opac, double *g_rgb)
+                      double *g_opac, double *g_rgb, const double *sh, int32_t sh_deg, double *g_sh)
 {
     if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height) return -1;
     const double *W = cam, *T = cam + 9;
@@ -1044,7 +1124,13 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
     for (int64_t i = 0; i < na; ++i) {
         const int64_t p = ord[i].id;
         oprim P;
-        setup_prim(center + 3 * p, quat + 4 * p, scale + 2 * p, curv + 2 * p, opac[p], rgb + 3 * p, W, T, &P);
+        double shrgb[3], sdir[3], sdist;
+        int slive[3];
+        if (sh)
+            sh_colour(sh_deg, sh + 3 * (sh_deg + 1) * (sh_deg + 1) * p, center + 3 * p, W, T, shrgb, sdir, &sdist,
+                      slive);
+        setup_prim(center + 3 * p, quat + 4 * p, scale + 2 * p, curv + 2 * p, opac[p], sh ? shrgb : rgb + 3 * p, W, T,
+                   &P);
         const double r = opts[O_K] * (P.s1 > P.s2 ? P.s1 : P.s2) * 1.01 + 1e-9;
         int a0, b0, a1, b1;
         if (!ball_box(P.cc, r, cam, opts[O_NEAR], width, height, &a0, &b0, &a1, &b1)) continue;
@@ -1130,6 +1216,7 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
         memset(g_curv, 0, sizeof(double) * 2 * (size_t)n);
         memset(g_opac, 0, sizeof(double) * (size_t)n);
         memset(g_rgb, 0, sizeof(double) * 3 * (size_t)n);
+        if (sh) memset(g_sh, 0, sizeof(double) * 3 * (size_t)((sh_deg + 1) * (sh_deg + 1)) * (size_t)n);
         for (int64_t i = 0; i < nw; ++i) {
             ograd S;
             memset(&S, 0, sizeof S);
@@ -1180,6 +1267,26 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
             g_curv[2 * p + 1] = S.dl[1];
             g_opac[p] = S.dop;
             for (int k = 0; k < 3; ++k) g_rgb[3 * p + k] = S.drgb[k];
+            if (sh) {
+                /* rgb_c = max(0, sum_k sh[k][c] Y_k(d) + 1/2), d = (c - o) / |c - o| */
+                const int K = (sh_deg + 1) * (sh_deg + 1);
+                const double *cf = sh + 3 * K * p;
+                double rgb_[3], d[3], r;
+                int live[3];
+                sh_colour(sh_deg, cf, center + 3 * p, W, T, rgb_, d, &r, live);
+                double Y[16], dY[16][3];
+                sh_basis(sh_deg, d[0], d[1], d[2], Y, dY);
+                double gd[3] = {0, 0, 0};
+                for (int ch = 0; ch < 3; ++ch) {
+                    const double gch = live[ch] ? S.drgb[ch] : 0.0;
+                    for (int k = 0; k < K; ++k) {
+                        g_sh[3 * K * p + 3 * k + ch] = Y[k] * gch;
+                        for (int j = 0; j < 3; ++j) gd[j] += gch * cf[3 * k + ch] * dY[k][j];
+                    }
+                }
+                const double dg = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+                for (int j = 0; j < 3; ++j) g_center[3 * p + j] += (gd[j] - d[j] * dg) / r;
+            }
         }
         free(grads);
     }

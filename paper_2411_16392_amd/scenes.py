@@ -34,16 +34,38 @@ class Scene:
     curv: np.ndarray     # [P,2] float32, lambda_1, lambda_2
     opacity: np.ndarray  # [P]   float32
     rgb: np.ndarray      # [P,3] float32
+    sh: np.ndarray | None = None  # [P,K,3] float32 spherical-harmonics coefficients (K = 1, 4, 9, 16), or None
 
     @property
     def n(self) -> int:
         return int(self.center.shape[0])
 
+    @property
+    def sh_degree(self) -> int:
+        return -1 if self.sh is None else int(round(np.sqrt(self.sh.shape[1]))) - 1
+
     def arrays(self):
         return (self.center, self.quat, self.scale, self.curv, self.opacity, self.rgb)
 
     def subset(self, idx) -> "Scene":
-        return Scene(*(np.ascontiguousarray(a[idx]) for a in self.arrays()))
+        sub = Scene(*(np.ascontiguousarray(a[idx]) for a in self.arrays()))
+        if self.sh is not None:
+            sub.sh = np.ascontiguousarray(self.sh[idx])
+        return sub
+
+
+def with_sh(scene: Scene, degree: int, seed: int, scale: float = 0.3) -> Scene:
+    """The scene with spherical-harmonics colour coefficients of `degree`
+    ((degree + 1)^2 per channel): the constant terms uniform in [-1.5, 1.5],
+    the band-l terms N(0, (scale / (l + 1))^2)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 7]))
+    K = (degree + 1) ** 2
+    sh = np.zeros((scene.n, K, 3), F32)
+    sh[:, 0, :] = rng.uniform(-1.5, 1.5, (scene.n, 3))
+    for k in range(1, K):
+        l = int(np.floor(np.sqrt(k)))
+        sh[:, k, :] = rng.normal(0.0, scale / (l + 1), (scene.n, 3))
+    return Scene(scene.center, scene.quat, scene.scale, scene.curv, scene.opacity, scene.rgb, sh)
 
 
 @dataclass

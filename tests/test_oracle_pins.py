@@ -1055,3 +1055,101 @@ def test_full_model_backward_matches_finite_differences(seed):
         err = np.abs(an.reshape(fd.shape) - fd)
         tol = 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9
         assert np.all(err <= tol), (key, an, fd)
+
+
+# --------------------------------------------------------------------------
+# spherical-harmonics colour (the 3DGS colour model the paper keeps, Sec. 3)
+# --------------------------------------------------------------------------
+
+def test_sh_basis_is_orthonormal_on_the_sphere():
+    # Gauss-Legendre in cos(theta) x uniform phi integrates products of
+    # polynomials of degree <= 6 exactly
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    G = np.zeros((16, 16))
+    for ct, wt in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(nphi):
+            ph = 2 * math.pi * k / nphi
+            Y, _ = oracle.sh_basis(3, [st * math.cos(ph), st * math.sin(ph), ct])
+            G += np.outer(Y, Y) * wt * (2 * math.pi / nphi)
+    assert np.max(np.abs(G - np.eye(16))) < 1e-12
+
+
+def test_sh_basis_gradient_and_addition_theorem():
+    rng = np.random.default_rng(61)
+    for _ in range(20):
+        a = unit(rng.standard_normal(3))
+        b = unit(rng.standard_normal(3))
+        Ya, dYa = oracle.sh_basis(3, a)
+        Yb, _ = oracle.sh_basis(3, b)
+        # addition theorem: sum_m Y_lm(a) Y_lm(b) = (2l + 1) / (4 pi) P_l(a . b)
+        c = float(a @ b)
+        P = [1.0, c, 0.5 * (3 * c * c - 1), 0.5 * (5 * c ** 3 - 3 * c)]
+        for l in range(4):
+            s_ = sum(Ya[k] * Yb[k] for k in range(l * l, (l + 1) * (l + 1)))
+            assert abs(s_ - (2 * l + 1) / (4 * math.pi) * P[l]) < 1e-12
+        # the gradient of each polynomial by central differences
+        for j in range(3):
+            e = np.zeros(3); e[j] = 1e-6
+            Yp, _ = oracle.sh_basis(3, a + e)
+            Ym, _ = oracle.sh_basis(3, a - e)
+            assert np.allclose((Yp - Ym) / 2e-6, dYa[:, j], atol=1e-8)
+    # degree 0: a constant colour Y_0 sh_0 + 1/2
+    Y, _ = oracle.sh_basis(0, [0.0, 0.0, 1.0])
+    assert abs(Y[0] - 0.5 / math.sqrt(math.pi)) < 1e-15 and np.all(Y[1:] == 0)
+
+
+def test_sh_colour_render_and_degree_zero():
+    # degree-0 SH equals direct RGB with rgb = Y_0 sh_0 + 1/2; higher degrees
+    # change the image
+    sc = _small_scene(62)
+    cam = scenes.look_at((0.2, 0.1, -3.0), width=32, height=32, f=40)
+    ks = oracle.keys(sc, cam)
+    sh0 = scenes.with_sh(sc, 0, 62)
+    y0 = 0.5 / math.sqrt(math.pi)
+    rgb_eq = Scene(sc.center, sc.quat, sc.scale, sc.curv, sc.opacity,
+                   np.maximum(sh0.sh[:, 0, :].astype(np.float64) * y0 + 0.5, 0.0))
+    a = oracle.render(sh0, cam, key_stage=ks, nthreads=2)
+    b = oracle.render(rgb_eq, cam, key_stage=ks, params64=[x.astype(np.float64) for x in rgb_eq.arrays()], nthreads=2)
+    assert np.max(np.abs(a["color"] - b["color"])) < 1e-12
+    sh3 = scenes.with_sh(sc, 3, 62)
+    c = oracle.render(sh3, cam, key_stage=ks, nthreads=2)
+    assert np.max(np.abs(c["color"] - a["color"])) > 1e-3
+
+
+@pytest.mark.parametrize("seed,deg", [(63, 1), (64, 3)])
+def test_sh_backward_matches_finite_differences(seed, deg):
+    strict = dict(A=1e-3, D=1e-4, near=1e-4, E=1e-4, alpha_min=1e-4, T=1e-4, normal=1e-4, clamp=1e-4)
+    cam = scenes.look_at((0.1, 0.05, -3.0), width=16, height=16, f=20)
+    for attempt in range(20):
+        s_ = seed + 1000 * attempt
+        n = 3
+        sc = scenes.with_sh(_fd_scene(s_, n), deg, s_)
+        rng = np.random.default_rng(100 + s_)
+        dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)))
+        ks = oracle.keys(sc, cam)
+        base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2)
+        if base["margin"].min() >= 1.0 and base["n_blend"].max() >= 2:
+            break
+    else:
+        pytest.fail("no base point away from decision boundaries")
+    p64 = [a.astype(np.float64) for a in sc.arrays()] + [sc.sh.astype(np.float64)]
+
+    def loss(params):
+        r = oracle.render(sc, cam, params64=params, key_stage=ks, nthreads=2)
+        return float(np.sum(dL[0] * r["color"]) + np.sum(dL[1] * r["depth"]) + np.sum(dL[2] * r["normal"]))
+
+    for ki, key in ((0, "center"), (6, "sh")):
+        an = base["grads"][key]
+        fd = np.zeros_like(an)
+        flat = p64[ki].reshape(-1)
+        for j in range(flat.size):
+            h = 1e-6 * max(1.0, abs(flat[j]))
+            plus = [a.copy() for a in p64]
+            minus = [a.copy() for a in p64]
+            plus[ki].reshape(-1)[j] += h
+            minus[ki].reshape(-1)[j] -= h
+            fd.reshape(-1)[j] = (loss(plus) - loss(minus)) / (2 * h)
+        scale = np.abs(fd).max() + 1e-12
+        assert np.all(np.abs(an - fd) <= 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9), key
