@@ -60,8 +60,15 @@ typedef struct qgs_scene {
     const float *scale;   /* [n][2] sigma_1, sigma_2 > 0: standard deviations along local x, y */
     const float *curv;    /* [n][2] lambda_1, lambda_2: local height z = lambda_1 x^2 + lambda_2 y^2 */
     const float *opacity; /* [n]    opacity in [0, 1] */
-    const float *rgb;     /* [n][3] colour */
+    const float *rgb;     /* [n][3] colour (unused, may be NULL, when sh is set) */
     int64_t n;
+    /* optional view-dependent colour (the 3DGS colour model, kept by the paper,
+       Sec. 3): [n][(sh_degree + 1)^2][3] real spherical-harmonics coefficients,
+       sh_degree 0..3; colour = max(0, sum_k sh[k] Y_k(d) + 1/2) for the unit
+       direction d from the camera centre to the primitive centre.  NULL: rgb. */
+    const float *sh;
+    int32_t sh_degree;
+    int32_t pad;
 } qgs_scene;
 
 /* Pinhole camera (host memory).  R, t map world to camera: x_cam = R x + t,
@@ -221,7 +228,16 @@ typedef struct qgs_scene_grads {
     float *scale;
     float *curv;
     float *opacity;
-    float *rgb;
+    float *rgb;          /* the colour's gradient (after the SH evaluation when sh is set) */
+    float *sh;           /* [n][K][3]; required when the scene has sh */
+    /* optional densification statistics (both or neither), ADDED to, never
+       overwritten: screen_grad[p] += |(W/2 z/fx g_x, H/2 z/fy g_y)| with g the
+       centre gradient in camera axes and z the centre depth, i.e. the gradient
+       with respect to the centre's image position in normalised device units
+       (the 3D centre gradient projected to the screen, Sec. 4 implementation
+       details); visible[p] += 1 when p covers a tile */
+    float *screen_grad;
+    float *visible;
 } qgs_scene_grads;
 
 /* Human-readable text for a status code (static storage). */

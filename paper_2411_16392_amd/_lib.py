@@ -34,7 +34,8 @@ QGS_RESORT = 16
 
 class QgsScene(ctypes.Structure):
     _fields_ = [("center", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("curv", c_void_p),
-                ("opacity", c_void_p), ("rgb", c_void_p), ("n", c_int64)]
+                ("opacity", c_void_p), ("rgb", c_void_p), ("n", c_int64), ("sh", c_void_p), ("sh_degree", c_int32),
+                ("pad", c_int32)]
 
 
 class QgsCamera(ctypes.Structure):
@@ -70,7 +71,8 @@ class QgsImageGrads(ctypes.Structure):
 
 class QgsSceneGrads(ctypes.Structure):
     _fields_ = [("center", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("curv", c_void_p),
-                ("opacity", c_void_p), ("rgb", c_void_p)]
+                ("opacity", c_void_p), ("rgb", c_void_p), ("sh", c_void_p), ("screen_grad", c_void_p),
+                ("visible", c_void_p)]
 
 
 class QgsServeConfig(ctypes.Structure):

@@ -44,7 +44,8 @@ bool scene_ok(const qgs_scene *s)
 {
     if (!s || s->n < 0 || s->n > 0x7FFFFFFFll) return false;
     if (s->n == 0) return true;
-    return s->center && s->quat && s->scale && s->curv && s->opacity && s->rgb;
+    if (s->sh && (s->sh_degree < 0 || s->sh_degree > 3)) return false;
+    return s->center && s->quat && s->scale && s->curv && s->opacity && (s->rgb || s->sh);
 }
 
 bool prims_ok(const qgs_prim_buf *p, int64_t n)
@@ -180,6 +181,8 @@ qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const q
     a.tiles = out->tiles;
     a.conic = out->conic;
     a.frame = out->frame;
+    a.sh = scene->sh;
+    a.sh_degree = scene->sh ? scene->sh_degree : -1;
     return hip_status(launch_preprocess(a, (hipStream_t)stream));
 }
 
@@ -270,6 +273,8 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
         return QGS_ERR_INVALID_ARG;
     if (scene->n > 0 && (!out->center || !out->quat || !out->scale || !out->curv || !out->opacity || !out->rgb))
         return QGS_ERR_INVALID_ARG;
+    if (scene->n > 0 && scene->sh && !out->sh) return QGS_ERR_INVALID_ARG;
+    if ((out->screen_grad == nullptr) != (out->visible == nullptr)) return QGS_ERR_INVALID_ARG;
     const bool geo = dL->dcurvature || dL->dmedian_depth || dL->ddistortion;
     if (geo && (!fwd->depth || !fwd->distortion || !fwd->median_pos)) return QGS_ERR_INVALID_ARG;
     const bool det = (opts->flags & QGS_DETERMINISTIC_BWD) != 0;
@@ -305,6 +310,8 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     b.center = scene->center;
     b.quat = scene->quat;
     b.scale = scene->scale;
+    b.sh = scene->sh;
+    b.sh_degree = scene->sh ? scene->sh_degree : -1;
     b.n = scene->n;
     b.cam = *cam;
     b.grad_rec = grad_rec;

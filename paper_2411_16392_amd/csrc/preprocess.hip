@@ -20,6 +20,78 @@ namespace qgs {
 
 __device__ inline bool finite_f(float v) { return __builtin_isfinite(v); }
 
+// Real spherical harmonics of degree <= 3 at the unit direction (x, y, z)
+// (normalisation sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!), Condon-Shortley phase,
+// order l = 0..3, m = -l..l), and with dY their gradients; the colour model of
+// 3DGS that the paper keeps (Sec. 3).
+__device__ inline void sh_basis(int deg, double x, double y, double z, double *Y, double (*dY)[3])
+{
+    const double pi = 3.14159265358979323846;
+    const double c0 = 0.5 * sqrt(1.0 / pi), c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi), c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi);
+    const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi), c3e = 0.25 * sqrt(105.0 / pi);
+    for (int k = 0; k < 16; ++k) {
+        Y[k] = 0.0;
+        if (dY) dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+    }
+    Y[0] = c0;
+    if (deg >= 1) {
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
+        if (dY) {
+            dY[1][1] = -c1;
+            dY[2][2] = c1;
+            dY[3][0] = -c1;
+        }
+    }
+    if (deg >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = c2a * x * y;
+        Y[5] = -c2a * y * z;
+        Y[6] = c2b * (2 * zz - xx - yy);
+        Y[7] = -c2a * x * z;
+        Y[8] = c2c * (xx - yy);
+        if (dY) {
+            dY[4][0] = c2a * y; dY[4][1] = c2a * x;
+            dY[5][1] = -c2a * z; dY[5][2] = -c2a * y;
+            dY[6][0] = -2 * c2b * x; dY[6][1] = -2 * c2b * y; dY[6][2] = 4 * c2b * z;
+            dY[7][0] = -c2a * z; dY[7][2] = -c2a * x;
+            dY[8][0] = 2 * c2c * x; dY[8][1] = -2 * c2c * y;
+        }
+    }
+    if (deg >= 3) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -c3a * y * (3 * xx - yy);
+        Y[10] = c3b * x * y * z;
+        Y[11] = -c3c * y * (4 * zz - xx - yy);
+        Y[12] = c3d * z * (2 * zz - 3 * xx - 3 * yy);
+        Y[13] = -c3c * x * (4 * zz - xx - yy);
+        Y[14] = c3e * z * (xx - yy);
+        Y[15] = -c3a * x * (xx - 3 * yy);
+        if (dY) {
+            dY[9][0] = -c3a * 6 * x * y; dY[9][1] = -c3a * (3 * xx - 3 * yy);
+            dY[10][0] = c3b * y * z; dY[10][1] = c3b * x * z; dY[10][2] = c3b * x * y;
+            dY[11][0] = c3c * 2 * x * y; dY[11][1] = -c3c * (4 * zz - xx - 3 * yy); dY[11][2] = -c3c * 8 * y * z;
+            dY[12][0] = -c3d * 6 * x * z; dY[12][1] = -c3d * 6 * y * z; dY[12][2] = c3d * (6 * zz - 3 * xx - 3 * yy);
+            dY[13][0] = -c3c * (4 * zz - 3 * xx - yy); dY[13][1] = c3c * 2 * x * y; dY[13][2] = -c3c * 8 * x * z;
+            dY[14][0] = c3e * 2 * x * z; dY[14][1] = -c3e * 2 * y * z; dY[14][2] = c3e * (xx - yy);
+            dY[15][0] = -c3a * (3 * xx - 3 * yy); dY[15][1] = c3a * 6 * x * y;
+        }
+    }
+}
+
+// unit direction from the camera centre -R^T t to the world point c, and its length
+__device__ inline void view_dir(const qgs_camera &cam, const float *c, double d[3], double &r)
+{
+    double v[3];
+    for (int j = 0; j < 3; ++j)
+        v[j] = (double)c[j] + ((double)cam.R[j] * cam.t[0] + (double)cam.R[3 + j] * cam.t[1] + (double)cam.R[6 + j] * cam.t[2]);
+    r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int j = 0; j < 3; ++j) d[j] = v[j] / r;
+}
+
 // Everything of one primitive except its tile count: the record, depth key,
 // rectangle and conic; `cl` receives the tile rectangle and conic for the
 // tile tests (nx = 0 when it covers no tile).
@@ -34,7 +106,25 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     const float sf1 = a.scale[2 * p], sf2 = a.scale[2 * p + 1];
     const float lf1 = a.curv[2 * p], lf2 = a.curv[2 * p + 1];
     const float op = a.opacity[p];
-    const float r0 = a.rgb[3 * p], r1 = a.rgb[3 * p + 1], r2 = a.rgb[3 * p + 2];
+    float r0, r1, r2;
+    if (a.sh) {
+        // view-dependent colour: max(0, sum_k sh[k] Y_k(d) + 1/2)
+        double d[3], r, Y[16];
+        view_dir(a.cam, a.center + 3 * p, d, r);
+        sh_basis(a.sh_degree, d[0], d[1], d[2], Y, nullptr);
+        const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+        const float *cf = a.sh + (size_t)3 * K * p;
+        double acc[3] = {0.5, 0.5, 0.5};
+        for (int k = 0; k < K; ++k)
+            for (int ch = 0; ch < 3; ++ch) acc[ch] += (double)cf[3 * k + ch] * Y[k];
+        r0 = (float)(acc[0] > 0.0 ? acc[0] : 0.0);
+        r1 = (float)(acc[1] > 0.0 ? acc[1] : 0.0);
+        r2 = (float)(acc[2] > 0.0 ? acc[2] : 0.0);
+    } else {
+        r0 = a.rgb[3 * p];
+        r1 = a.rgb[3 * p + 1];
+        r2 = a.rgb[3 * p + 2];
+    }
 
     bool ok = finite_f(cf0) && finite_f(cf1) && finite_f(cf2) && finite_f(qw) && finite_f(qx) && finite_f(qy) &&
               finite_f(qz) && finite_f(sf1) && finite_f(sf2) && finite_f(lf1) && finite_f(lf2) && finite_f(op) &&
@@ -256,6 +346,41 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreprocessBwdArgs a)
         // c_cam = W c + t
         for (int j = 0; j < 3; ++j)
             gc[j] = (double)a.cam.R[j] * dX + (double)a.cam.R[3 + j] * dY + (double)a.cam.R[6 + j] * dZ;
+        if (a.sh) {
+            // rgb_c = max(0, sum_k sh[k][c] Y_k(d) + 1/2), d = (c - o) / |c - o|:
+            // coefficient gradients, and the view direction's share of the centre's
+            double d[3], r, Y[16], dYd[16][3];
+            view_dir(a.cam, a.center + 3 * p, d, r);
+            sh_basis(a.sh_degree, d[0], d[1], d[2], Y, dYd);
+            const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+            const float *cf = a.sh + (size_t)3 * K * p;
+            float *gsh = a.out.sh + (size_t)3 * K * p;
+            double gd[3] = {0, 0, 0};
+            for (int ch = 0; ch < 3; ++ch) {
+                double acc = 0.5;
+                for (int k = 0; k < K; ++k) acc += (double)cf[3 * k + ch] * Y[k];
+                const double gch = acc > 0.0 ? (double)g[G_R + ch] : 0.0;
+                for (int k = 0; k < K; ++k) {
+                    const float v = (float)(Y[k] * gch);
+                    if (a.accumulate) gsh[3 * k + ch] += v;
+                    else gsh[3 * k + ch] = v;
+                    for (int j = 0; j < 3; ++j) gd[j] += gch * (double)cf[3 * k + ch] * dYd[k][j];
+                }
+            }
+            const double dg = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+            for (int j = 0; j < 3; ++j) gc[j] += (gd[j] - d[j] * dg) / r;
+        }
+        if (a.out.screen_grad) {
+            // the centre gradient in camera axes, as a gradient of its image
+            // position in normalised device units
+            double gcam[3];
+            for (int i = 0; i < 3; ++i)
+                gcam[i] = (double)a.cam.R[3 * i] * gc[0] + (double)a.cam.R[3 * i + 1] * gc[1] + (double)a.cam.R[3 * i + 2] * gc[2];
+            const double su = 0.5 * a.cam.width * cc[2] / a.cam.fx * gcam[0];
+            const double sv = 0.5 * a.cam.height * cc[2] / a.cam.fy * gcam[1];
+            a.out.screen_grad[p] += (float)sqrt(su * su + sv * sv);
+            a.out.visible[p] += 1.0f;
+        }
         // rotation: Rm(qhat) -> Rm(qhat (1, phi/2)), so dL/dqhat = (-2 g.v, 2 (w g + v x g))
         const double q0 = a.quat[4 * p], q1 = a.quat[4 * p + 1], q2 = a.quat[4 * p + 2], q3 = a.quat[4 * p + 3];
         const double len = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
@@ -282,6 +407,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreprocessBwdArgs a)
         for (int i = 0; i < 15; ++i) *dst[i] += vals[i];
     } else {
         for (int i = 0; i < 15; ++i) *dst[i] = vals[i];
+        if (a.sh && !active) {
+            const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+            for (int k = 0; k < 3 * K; ++k) a.out.sh[(size_t)3 * K * p + k] = 0.0f;
+        }
     }
 }
 

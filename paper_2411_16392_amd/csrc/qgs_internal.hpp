@@ -27,10 +27,14 @@ struct PreprocessArgs {
     uint32_t *tiles;
     double *conic;
     double *frame;  // optional
+    const float *sh;  // optional SH colour [n][K][3]
+    int sh_degree;
 };
 
 struct PreprocessBwdArgs {
     const float *center, *quat, *scale;
+    const float *sh;  // optional SH colour [n][K][3]
+    int sh_degree;
     int64_t n;
     qgs_camera cam;
     const float *grad_rec;  // [n][16]

@@ -216,6 +216,7 @@ hipError_t enqueue_count(qgs_server *s, Slot &sl, hipStream_t stream)
     PreprocessArgs pa{};
     pa.center = s->scene.center; pa.quat = s->scene.quat; pa.scale = s->scene.scale;
     pa.curv = s->scene.curv; pa.opacity = s->scene.opacity; pa.rgb = s->scene.rgb;
+    pa.sh = s->scene.sh; pa.sh_degree = s->scene.sh ? s->scene.sh_degree : -1;
     pa.n = s->scene.n;
     pa.cam = r.cam;
     pa.near_plane = s->cfg.opts.near_plane;

@@ -52,17 +52,33 @@ def _stream():
 
 
 def scene_to_device(scene, device="cuda") -> dict:
-    """Dict of contiguous FP32 device tensors from a scenes.Scene."""
-    return {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k), np.float32)).to(device) for k in SCENE_KEYS}
+    """Dict of contiguous FP32 device tensors from a scenes.Scene (with "sh"
+    [n, K, 3] when the scene has spherical-harmonics colour)."""
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k), np.float32)).to(device) for k in SCENE_KEYS}
+    if getattr(scene, "sh", None) is not None:
+        t["sh"] = torch.from_numpy(np.ascontiguousarray(scene.sh, np.float32)).to(device)
+    return t
+
+
+def sh_degree_of(t: dict) -> int:
+    """Degree of the SH colour of a device scene dict (-1: plain rgb)."""
+    sh = t.get("sh")
+    if sh is None:
+        return -1
+    deg = int(round(sh.shape[1] ** 0.5)) - 1
+    if (deg + 1) ** 2 != sh.shape[1] or not 0 <= deg <= 3 or sh.shape[-1] != 3:
+        raise ValueError("sh must be [n, (degree + 1)^2, 3] with degree 0..3")
+    return deg
 
 
 def _scene_struct(t: dict) -> L.QgsScene:
     s = L.QgsScene()
-    for k in SCENE_KEYS:
+    for k in SCENE_KEYS + (("sh",) if t.get("sh") is not None else ()):
         x = t[k]
         if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
             raise ValueError(f"scene tensor {k} must be contiguous float32 on the GPU")
         setattr(s, k, x.data_ptr())
+    s.sh_degree = max(sh_degree_of(t), 0)
     s.n = int(t["center"].shape[0])
     return s
 
@@ -218,12 +234,22 @@ class Renderer:
 
     def backward(self, scene_t: dict, st: FrameState, dcolor=None, ddepth=None, dnormal=None,
                  out: dict | None = None, accumulate: bool = False, dcurvature=None, dmedian_depth=None,
-                 ddistortion=None) -> dict:
+                 ddistortion=None, stats: dict | None = None) -> dict:
+        """Parameter gradients (dict like the scene's, "sh" included when the
+        scene has SH colour).  stats: optional {"screen_grad": [n], "visible":
+        [n]} FP32 tensors that the densification statistics are added to."""
+        keys = SCENE_KEYS + (("sh",) if scene_t.get("sh") is not None else ())
         if out is None:
-            out = {k: torch.empty_like(scene_t[k]) for k in SCENE_KEYS}
+            out = {k: torch.empty_like(scene_t[k]) for k in keys}
         g = L.QgsSceneGrads()
-        for k in SCENE_KEYS:
+        for k in keys:
             setattr(g, k, out[k].data_ptr())
+        if stats is not None:
+            for k in ("screen_grad", "visible"):
+                x = stats[k]
+                if x.dtype != torch.float32 or not x.is_contiguous() or x.numel() != st.n:
+                    raise ValueError(f"stats[{k}] must be a contiguous float32 tensor of n entries")
+                setattr(g, k, x.data_ptr())
         dl = L.QgsImageGrads()
         keep = []
         geo = (("dcurvature", dcurvature), ("dmedian_depth", dmedian_depth), ("ddistortion", ddistortion))
@@ -248,36 +274,47 @@ class Renderer:
 
 class QGSRasterize(torch.autograd.Function):
     """colour, depth, normal = QGSRasterize.apply(center, quat, scale, curv,
-    opacity, rgb, renderer, camera); with a geometry renderer also curvature,
-    median depth and depth distortion."""
+    opacity, rgb, sh, renderer, camera); sh is None for plain rgb colour; with
+    a geometry renderer also curvature, median depth and depth distortion."""
 
     @staticmethod
-    def forward(ctx, center, quat, scale, curv, opacity, rgb, renderer: Renderer, cam):
+    def forward(ctx, center, quat, scale, curv, opacity, rgb, sh, renderer: Renderer, cam):
         scene_t = dict(center=center.contiguous(), quat=quat.contiguous(), scale=scale.contiguous(),
                        curv=curv.contiguous(), opacity=opacity.contiguous(), rgb=rgb.contiguous())
+        if sh is not None:
+            scene_t["sh"] = sh.contiguous()
         st = renderer.forward(scene_t, cam)
         ctx.renderer = renderer
         ctx.state = st
-        ctx.save_for_backward(*[scene_t[k] for k in SCENE_KEYS])
+        ctx.has_sh = sh is not None
+        ctx.save_for_backward(*[scene_t[k] for k in SCENE_KEYS + (("sh",) if sh is not None else ())])
         if renderer.geometry:
             return st.color, st.depth, st.normal, st.curvature, st.median_depth, st.distortion
         return st.color, st.depth, st.normal
 
     @staticmethod
     def backward(ctx, dcolor, ddepth, dnormal, *dgeo):
-        scene_t = dict(zip(SCENE_KEYS, ctx.saved_tensors))
+        keys = SCENE_KEYS + (("sh",) if ctx.has_sh else ())
+        scene_t = dict(zip(keys, ctx.saved_tensors))
         dk, dm, dd = (tuple(dgeo) + (None, None, None))[:3]
         g = ctx.renderer.backward(scene_t, ctx.state, dcolor, ddepth, dnormal, dcurvature=dk, dmedian_depth=dm,
                                   ddistortion=dd)
-        return (g["center"], g["quat"], g["scale"], g["curv"], g["opacity"], g["rgb"], None, None)
+        return (g["center"], g["quat"], g["scale"], g["curv"], g["opacity"], g["rgb"], g.get("sh"), None, None)
 
 
 def render(scene_t: dict, cam, renderer: Renderer | None = None, geometry: bool = False):
     """Differentiable render of one view: (colour [3,H,W], depth [H,W], normal [3,H,W]), and with
-    geometry=True also (curvature [H,W], median depth [H,W], depth distortion [H,W])."""
+    geometry=True also (curvature [H,W], median depth [H,W], depth distortion [H,W]).  scene_t may
+    hold "sh" [n, K, 3] for view-dependent colour."""
     r = renderer if renderer is not None else Renderer(device=scene_t["center"].device, geometry=geometry)
     return QGSRasterize.apply(scene_t["center"], scene_t["quat"], scene_t["scale"], scene_t["curv"],
-                              scene_t["opacity"], scene_t["rgb"], r, cam)
+                              scene_t["opacity"], scene_t["rgb"], scene_t.get("sh"), r, cam)
+
+
+def signed_scale(x: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    """The paper's signed-scale activation s = tanh(t) exp(x) (Sec. 3.2): a
+    scale whose sign, and so the paraboloid's type, changes differentiably."""
+    return torch.tanh(t) * torch.exp(x)
 
 
 def signed_scale_to_params(s1, s2, s3):
