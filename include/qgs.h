@@ -107,6 +107,14 @@ typedef struct qgs_render_opts {
                    then walks the lists front to back. */
 #define QGS_TILE_DEPTH        8u
 #define QGS_RESORT            16u
+/* QGS_TIGHT_BOUND  qgs_preprocess bounds the support with the arc-length >=
+                    chord inequality (below) instead of Q <= k^2 alone: a
+                    smaller, still conservative local box, so fewer tiles and
+                    pixel tests for strongly curved primitives and the same
+                    image.  A provably conservative alternative to the paper's
+                    tangent-plane box (supplement, bounding box calculation),
+                    which can miss part of the support. */
+#define QGS_TIGHT_BOUND       32u
 
 /*
  * Per-primitive preprocess output (device memory, caller-allocated, n entries).
@@ -263,12 +271,17 @@ qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t pair_c
  * Projection, culling and conservative screen bounds, one thread per primitive
  * (Sec. 3.2 congruent transform; supplement, bounding boxes).  Writes records,
  * depth_key, rect, tiles and conic of `out`.  The bounds hold every pixel whose
- * ray can meet the primitive inside k_sigma: since the arc-length factor is
+ * ray can meet the primitive inside k_sigma.  Since the arc-length factor is
  * >= 1, an accepted hit has |x| <= k sigma_1, |y| <= k sigma_2 and a height
- * between the extremes of lambda_1 x^2 + lambda_2 y^2 over that ellipse.  The
- * rectangle is the projection of this (slightly inflated) local box; tiles of
- * it are kept only if they meet the projection of an ellipsoid enclosing the
- * box's elliptic cylinder.  Errors: QGS_ERR_INVALID_ARG.
+ * between the extremes of lambda_1 x^2 + lambda_2 y^2 over that ellipse, capped
+ * at k max(sigma).  With QGS_TIGHT_BOUND the arc is also at least its chord, so
+ * Q + z^2 / max(sigma)^2 <= k^2, whose extremes in x, y and z give a smaller
+ * box.  The rectangle is the projection of the part of this (slightly
+ * inflated) local box in front of the near plane -- its corners there and the
+ * points where its edges cross the plane -- and is empty when no corner is in
+ * front; tiles of it are kept only if they meet the projection of an ellipsoid
+ * enclosing the box's elliptic cylinder (when that ellipsoid lies in front of
+ * the near plane).  Errors: QGS_ERR_INVALID_ARG.
  */
 qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const qgs_render_opts *opts,
                           qgs_prim_buf *out, qgs_stream_t stream);

@@ -50,7 +50,7 @@ def _lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
-        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P, P]
+        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P, P, i32]
         L.oracle_keys.restype = None
         L.oracle_bin_sort.argtypes = [i64, P, P, P, P, P, P, i32, i32, i32, i32, i64, P, P, P, P, P, f32]
         L.oracle_bin_sort.restype = i64
@@ -67,6 +67,10 @@ def _lib():
         L.oracle_gprime.restype = f64
         L.oracle_arc_length.argtypes = [f64, f64]
         L.oracle_arc_length.restype = f64
+        L.oracle_local_box.argtypes = [f64, f64, f64, f64, f64, i32, P]
+        L.oracle_local_box.restype = None
+        L.oracle_tb_frustum.argtypes = [f64, f64, f64, f64, f64, P]
+        L.oracle_tb_frustum.restype = None
         L.oracle_ray_hit.argtypes = [P, P, P, P, P, P, P, P]
         L.oracle_ray_hit.restype = None
         _lib_handle = L
@@ -119,8 +123,24 @@ def arc_length(a: float, rho: float) -> float:
     return _lib().oracle_arc_length(float(a), float(rho))
 
 
-def keys(scene, cam, opts=None):
-    """Key stage: cull flag, FP32 depth key bits, pixel and tile rectangles."""
+def local_box(s1, s2, l1, l2, k=3.0, tight=False):
+    """Inflated local box (hx, hy, zlo, zhi) holding a primitive's support."""
+    out = np.zeros(4, np.float64)
+    _lib().oracle_local_box(float(s1), float(s2), float(l1), float(l2), float(k), int(bool(tight)), _ptr(out))
+    return out
+
+
+def tb_frustum(s1, s2, l1, l2, k=3.0):
+    """The paper's tangent-plane frustum (rho1, rho2, x1, x2, h); measurement only."""
+    out = np.zeros(5, np.float64)
+    _lib().oracle_tb_frustum(float(s1), float(s2), float(l1), float(l2), float(k), _ptr(out))
+    return out
+
+
+def keys(scene, cam, opts=None, tight=False, paper_tb=False):
+    """Key stage: cull flag, FP32 depth key bits, pixel and tile rectangles
+    (tight: the chord-bound local box; paper_tb: the rectangle of the paper's
+    tangent-plane frustum instead, with no conic test -- measurement only)."""
     o = opts_array(opts)
     n = scene.n
     culled = np.zeros(n, np.uint8)
@@ -136,7 +156,7 @@ def keys(scene, cam, opts=None):
     _lib().oracle_keys(n, *[_ptr(a) for a in arrs], _ptr(camv), cam.width, cam.height,
                        ctypes.c_float(o[0]), ctypes.c_float(o[1]),
                        _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles),
-                       _ptr(conic), _ptr(conic_ok), _ptr(frame))
+                       _ptr(conic), _ptr(conic_ok), _ptr(frame), 2 if paper_tb else int(bool(tight)))
     return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles,
                 conic=conic, conic_ok=conic_ok, frame=frame, cam=camv, width=cam.width, height=cam.height,
                 near=float(o[0]))

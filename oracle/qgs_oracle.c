@@ -120,19 +120,114 @@ static int oracle_tile_hit(const double *C, int tx, int ty, const float *cam, in
     return 0;
 }
 
+/*
+ * Local box of the support, [-hx, hx] x [-hy, hy] x [zlo, zhi], out = {hx, hy,
+ * zlo, zhi}, inflated by 2^-10 (z also padded by k max(s) / 1024).  A support
+ * point (x, y, z = lambda1 x^2 + lambda2 y^2) has arc length l = rho g(u) <=
+ * k sigma(theta) with rho^2 = x^2 + y^2 and sigma(theta)^2 = rho^2 / Q
+ * (Sec. 3.2, geodesic and sigma(theta) equations).
+ *  tight == 0: g >= 1 gives Q <= k^2, so |x| <= k s1, |y| <= k s2; z lies
+ *    between the extremes of {0, k^2 lambda_i s_i^2} and |z| <= l <= k max(s).
+ *  tight != 0: the arc from the vertex is at least its chord, l^2 >= rho^2 +
+ *    z^2, so (rho^2 + z^2) Q / rho^2 <= k^2 and, as Q / rho^2 >= 1/sm^2
+ *    (sm = max(s1, s2)), Q + z^2 / sm^2 <= k^2.  With X = x^2, Y = y^2 the
+ *    largest admissible X solves min_{Y>=0} [X/s1^2 + Y/s2^2 +
+ *    (lambda1 X + lambda2 Y)^2 / sm^2] = k^2.  For lambda1 lambda2 >= 0 the
+ *    minimum is at Y = 0: lambda1^2 X^2 / sm^2 + X / s1^2 = k^2.  For opposite
+ *    signs Y = 0 is optimal up to Xc = sm^2 / (2 |lambda1 lambda2| s2^2);
+ *    beyond it the minimum is X (1/s1^2 + |lambda1| / (|lambda2| s2^2)) -
+ *    sm^2 / (4 lambda2^2 s2^4).  The height: per direction rho^2 (1 + a^2
+ *    rho^2) <= k^2 sigma^2, so |z| = |a| rho^2 <= 2 k^2 m / (1 + sqrt(1 + 4 k^2
+ *    m^2 / sigma^2)) with m = |a| sigma^2, increasing in m and sigma; a sigma^2
+ *    is a weighted mean of lambda1 s1^2 and lambda2 s2^2, and sigma <= sm.
+ * FP64, the operation order as written (the GPU follows the same sequence).
+ */
+static double chord_x2(double sa, double sb, double la, double lb, double sm, double k2)
+{
+    double ra = ((la * sa) * sa) / sm;
+    double x_root = ((2.0 * k2) * (sa * sa)) / (1.0 + sqrt(1.0 + (4.0 * k2) * (ra * ra)));
+    if (la * lb < 0.0) {
+        double rb = (fabs(lb) * sb) * sb;
+        double x_c = (sm * sm) / ((2.0 * fabs(la)) * rb);
+        if (x_root > x_c) return (k2 + (sm * sm) / (4.0 * (rb * rb))) / (1.0 / (sa * sa) + fabs(la) / rb);
+    }
+    return x_root;
+}
+
+static double chord_z(double m, double sm, double k2)
+{
+    double r = m / sm;
+    return ((2.0 * k2) * m) / (1.0 + sqrt(1.0 + (4.0 * k2) * (r * r)));
+}
+
+void oracle_local_box(double s1, double s2, double l1, double l2, double k, int32_t tight, double *out)
+{
+    const double infl = 1.0 + 1.0 / 1024.0;
+    const double k2 = k * k;
+    const double smax = s1 > s2 ? s1 : s2;
+    const double zcap = k * smax;
+    const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
+    double ex = k * s1, ey = k * s2, zlo, zhi;
+    if (tight) {
+        double bx = sqrt(chord_x2(s1, s2, l1, l2, smax, k2)), by = sqrt(chord_x2(s2, s1, l2, l1, smax, k2));
+        if (bx < ex) ex = bx;
+        if (by < ey) ey = by;
+        zlo = -chord_z(-min3(0.0, m1, m2), smax, k2);
+        zhi = chord_z(max3(0.0, m1, m2), smax, k2);
+    } else {
+        zlo = k2 * min3(0.0, m1, m2);
+        zhi = k2 * max3(0.0, m1, m2);
+    }
+    if (zlo < -zcap) zlo = -zcap;
+    if (zhi > zcap) zhi = zcap;
+    const double zpad = zcap / 1024.0;
+    out[0] = ex * infl;
+    out[1] = ey * infl;
+    out[2] = zlo * infl - zpad;
+    out[3] = zhi * infl + zpad;
+}
+
+/*
+ * The paper's tangent-plane box (supplement, bounding box calculation), for
+ * measurement only: it is not conservative.  Reading of the garbled passage:
+ *  - the arc length is replaced by lhat(a, rho) = (4 |a| rho^2 + 6 rho) / 7 and
+ *    rho_i is the positive root of lhat(lambda_i, rho) = k s_i along each
+ *    principal axis (the k-sigma cut-off), in the cancellation-free form
+ *    rho = 14 k s / (6 + sqrt(36 + 112 |a| k s)); 7 k s / 6 for a = 0;
+ *  - the four points (+-rho1, 0, lambda1 rho1^2), (0, +-rho2, lambda2 rho2^2);
+ *    the tangent plane of z = lambda x^2 at x0 meets z = 0 at x0 / 2, so the
+ *    bottom half-widths are rho_i / 2 (rho_i when lambda_i = 0: the tangent
+ *    plane is z = 0);
+ *  - the frustum has its bottom face [+-x1] x [+-x2] at z = 0 and its top face
+ *    [+-rho1] x [+-rho2] at the height h = lambda_j rho_j^2 of larger magnitude.
+ * out = {rho1, rho2, x1, x2, h}.
+ */
+void oracle_tb_frustum(double s1, double s2, double l1, double l2, double k, double *out)
+{
+    const double sg[2] = {s1, s2}, lm[2] = {l1, l2};
+    double rho[2], h[2];
+    for (int i = 0; i < 2; ++i) {
+        rho[i] = 14.0 * k * sg[i] / (6.0 + sqrt(36.0 + 112.0 * fabs(lm[i]) * k * sg[i]));
+        out[2 + i] = lm[i] == 0.0 ? rho[i] : 0.5 * rho[i];
+        h[i] = lm[i] * rho[i] * rho[i];
+    }
+    out[0] = rho[0];
+    out[1] = rho[1];
+    out[4] = fabs(h[0]) >= fabs(h[1]) ? h[0] : h[1];
+}
+
 void oracle_keys(int64_t n, const float *center, const float *quat, const float *scale,
                  const float *curv, const float *opac, const float *rgb,
                  const float *cam, int32_t width, int32_t height, float near_f, float k_sigma,
                  uint8_t *culled, uint32_t *depth_bits, int32_t *rect_px, int32_t *rect_tile,
-                 uint32_t *tiles, double *conic, uint8_t *conic_ok, double *frame)
+                 uint32_t *tiles, double *conic, uint8_t *conic_ok, double *frame, int32_t tight)
 {
     double W[9], T[3];
     for (int i = 0; i < 9; ++i) W[i] = cam[i];
     for (int i = 0; i < 3; ++i) T[i] = cam[9 + i];
     const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
     const double near_d = near_f;
-    const double infl = 1.0 + 1.0 / 1024.0;
-    const double pad_px = 1.0 / 64.0;
+        const double pad_px = 1.0 / 64.0;
 
     for (int64_t p = 0; p < n; ++p) {
         int32_t *rp = rect_px + 4 * p, *rt = rect_tile + 4 * p;
@@ -174,44 +269,68 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
             for (int j = 0; j < 3; ++j)
                 Rc[3 * i + j] = fma(W[3 * i + 0], Rm[j], fma(W[3 * i + 1], Rm[3 + j], W[3 * i + 2] * Rm[6 + j]));
 
-        /* conservative local box of the support: an accepted hit has
-           g^2 Q <= k^2 with g >= 1, so |x| <= k s1, |y| <= k s2; its height
-           lambda1 x^2 + lambda2 y^2 lies between the simplex vertices
-           {0, k^2 lambda1 s1^2, k^2 lambda2 s2^2}, and |z| <= arc length <= k max(s) */
-        const double k = k_sigma;
-        const double hx = (k * s1) * infl, hy = (k * s2) * infl;
-        const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
-        const double k2 = k * k;
-        const double smax = s1 > s2 ? s1 : s2;
-        const double zcap = k * smax;
-        double zlo = k2 * min3(0.0, m1, m2), zhi = k2 * max3(0.0, m1, m2);
-        if (zlo < -zcap) zlo = -zcap;
-        if (zhi > zcap) zhi = zcap;
-        const double zpad = zcap / 1024.0;
-        zlo = zlo * infl - zpad;
-        zhi = zhi * infl + zpad;
+        /* conservative local box of the support (oracle_local_box) */
+        double box[4];
+        oracle_local_box(s1, s2, l1, l2, (double)k_sigma, tight == 1, box);
+        const double hx = box[0], hy = box[1], zlo = box[2], zhi = box[3];
+        double tb[5];
+        if (tight == 2) oracle_tb_frustum(s1, s2, l1, l2, (double)k_sigma, tb);
 
-        int behind = 0;
-        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        /* The rectangle bounds the projection of the part of the box in front
+           of the near plane (a hit needs a camera depth above it).  That part
+           is a convex polytope whose vertices are the corners in front and the
+           points where edges cross the plane; a central projection maps it to
+           the convex hull of the vertices' images. */
+        double P8[8][3];
+        int in_front[8], n_front = 0;
         for (int c = 0; c < 8; ++c) {
-            const double X = (c & 1) ? hx : -hx, Y = (c & 2) ? hy : -hy, Z = (c & 4) ? zhi : zlo;
-            double P[3];
+            double X = (c & 1) ? hx : -hx, Y = (c & 2) ? hy : -hy, Z = (c & 4) ? zhi : zlo;
+            if (tight == 2) {
+                /* frustum: bottom face at z = 0, top face at the height h */
+                const int top = (c & 4) != 0;
+                X = ((c & 1) ? 1.0 : -1.0) * (top ? tb[0] : tb[2]);
+                Y = ((c & 2) ? 1.0 : -1.0) * (top ? tb[1] : tb[3]);
+                Z = top ? tb[4] : 0.0;
+            }
             for (int i = 0; i < 3; ++i)
-                P[i] = fma(Rc[3 * i + 0], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
-            if (!(P[2] > near_d)) { behind = 1; continue; }
-            const double u = fma(fx, P[0] / P[2], cx), v = fma(fy, P[1] / P[2], cy);
-            if (u < umin) umin = u;
-            if (u > umax) umax = u;
-            if (v < vmin) vmin = v;
-            if (v > vmax) vmax = v;
+                P8[c][i] = fma(Rc[3 * i + 0], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
+            in_front[c] = P8[c][2] > near_d;
+            n_front += in_front[c];
+        }
+        const int behind = n_front < 8;
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        double pts[20][2];
+        int npts = 0;
+        for (int c = 0; c < 8; ++c) {
+            if (!in_front[c]) continue;
+            pts[npts][0] = fma(fx, P8[c][0] / P8[c][2], cx);
+            pts[npts][1] = fma(fy, P8[c][1] / P8[c][2], cy);
+            ++npts;
+        }
+        for (int a = 0; a < 8; ++a)
+            for (int b = a + 1; b < 8; ++b) {
+                const int d = a ^ b;
+                if ((d & (d - 1)) != 0) continue; /* not an edge: corners differ in more than one axis */
+                if (in_front[a] == in_front[b]) continue;
+                const double *F = in_front[a] ? P8[a] : P8[b], *Bk = in_front[a] ? P8[b] : P8[a];
+                const double s_cut = (F[2] - near_d) / (F[2] - Bk[2]);
+                const double xq = F[0] + s_cut * (Bk[0] - F[0]), yq = F[1] + s_cut * (Bk[1] - F[1]);
+                pts[npts][0] = fma(fx, xq / near_d, cx);
+                pts[npts][1] = fma(fy, yq / near_d, cy);
+                ++npts;
+            }
+        for (int i = 0; i < npts; ++i) {
+            if (pts[i][0] < umin) umin = pts[i][0];
+            if (pts[i][0] > umax) umax = pts[i][0];
+            if (pts[i][1] < vmin) vmin = pts[i][1];
+            if (pts[i][1] > vmax) vmax = pts[i][1];
         }
         int px0, px1, py0, py1;
-        if (behind) {
-            px0 = 0; px1 = width - 1; py0 = 0; py1 = height - 1;
-        } else {
+        {
             const double a0 = (umin - 0.5) - pad_px, a1 = (umax - 0.5) + pad_px;
             const double b0 = (vmin - 0.5) - pad_px, b1 = (vmax - 0.5) + pad_px;
-            if (a1 < 0.0 || a0 > (double)(width - 1) || b1 < 0.0 || b0 > (double)(height - 1)) {
+            if (n_front == 0 || a1 < 0.0 || a0 > (double)(width - 1) || b1 < 0.0 || b0 > (double)(height - 1)) {
+                /* nothing in front of the near plane, or off screen */
                 culled[p] = 0;
                 depth_bits[p] = 0;
                 memcpy(&depth_bits[p], &zf, 4);
@@ -243,7 +362,7 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
            hz^2/t about the mid-height zm (a point of the cylinder satisfies
            (1-t) + t = 1), with t = hz / (hz + min(hx, hy)). */
         double *Cq = conic + 6 * p;
-        if (!behind) {
+        if (!behind && tight != 2) {
             const double hz = 0.5 * (zhi - zlo), zm = 0.5 * (zlo + zhi);
             const double mxy = hx < hy ? hx : hy;
             const double t = hz / (hz + mxy);

@@ -30,6 +30,7 @@ QGS_ACCUMULATE_GRADS = 2
 QGS_COUNT_EVALS = 4
 QGS_TILE_DEPTH = 8
 QGS_RESORT = 16
+QGS_TIGHT_BOUND = 32
 
 
 class QgsScene(ctypes.Structure):

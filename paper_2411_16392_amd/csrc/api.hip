@@ -183,6 +183,7 @@ qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const q
     a.frame = out->frame;
     a.sh = scene->sh;
     a.sh_degree = scene->sh ? scene->sh_degree : -1;
+    a.tight = (opts->flags & QGS_TIGHT_BOUND) ? 1 : 0;
     return hip_status(launch_preprocess(a, (hipStream_t)stream));
 }
 

@@ -92,6 +92,70 @@ __device__ inline void view_dir(const qgs_camera &cam, const float *c, double d[
     for (int j = 0; j < 3; ++j) d[j] = v[j] / r;
 }
 
+// Local box [-hx, hx] x [-hy, hy] x [zlo, zhi] holding every point of the
+// support (accepted hits, l <= k sigma(theta)), inflated by 2^-10 (and z by a
+// further k max(sigma) / 1024).  FP64, fixed operation order, no contraction.
+//  default: the arc-length factor is >= 1, so Q <= k^2: |x| <= k s1,
+//           |y| <= k s2; the height lambda1 x^2 + lambda2 y^2 lies between
+//           the extremes of {0, k^2 lambda_i s_i^2} and |z| <= l <= k max(s).
+//  tight:   the arc is at least its chord, so rho^2 + z^2 <= k^2 sigma(theta)^2,
+//           hence Q + z^2 / sm^2 <= k^2 (sm = max(s1, s2)).  |x|'s bound is the
+//           largest X = x^2 with min over Y = y^2 >= 0 of
+//           X/s1^2 + Y/s2^2 + (l1 X + l2 Y)^2 / sm^2 <= k^2: at Y = 0 (root of a
+//           quadratic) unless the curvatures have opposite signs and that root
+//           passes the point Xc beyond which a Y > 0 lowers the height, where
+//           the minimum is linear in X.  The height solves rho^2 (1 + a^2 rho^2)
+//           <= k^2 sigma^2 with a sigma^2 between the lambda_i s_i^2.
+__device__ inline double chord_axis_sq(double sa, double sb, double la, double lb, double sm, double k2)
+{
+    const double ra = ((la * sa) * sa) / sm;
+    const double Xe = ((2.0 * k2) * (sa * sa)) / (1.0 + sqrt(1.0 + (4.0 * k2) * (ra * ra)));
+    if (la * lb < 0.0) {
+        const double rb = (fabs(lb) * sb) * sb;
+        const double Xc = (sm * sm) / ((2.0 * fabs(la)) * rb);
+        if (Xe > Xc) return (k2 + (sm * sm) / (4.0 * (rb * rb))) / (1.0 / (sa * sa) + fabs(la) / rb);
+    }
+    return Xe;
+}
+
+__device__ inline double chord_height(double m, double sm, double k2)
+{
+    const double r = m / sm;
+    return ((2.0 * k2) * m) / (1.0 + sqrt(1.0 + (4.0 * k2) * (r * r)));
+}
+
+__device__ inline void local_box(double s1, double s2, double l1, double l2, double k, bool tight, double &hx,
+                                 double &hy, double &zlo, double &zhi)
+{
+    const double infl = 1.0 + 1.0 / 1024.0;
+    const double k2 = k * k;
+    const double smax = s1 > s2 ? s1 : s2;
+    const double zcap = k * smax;
+    const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
+    double lo = 0.0, hi = 0.0;
+    lo = m1 < lo ? m1 : lo; lo = m2 < lo ? m2 : lo;
+    hi = m1 > hi ? m1 : hi; hi = m2 > hi ? m2 : hi;
+    double ex = k * s1, ey = k * s2;
+    if (tight) {
+        const double bx = sqrt(chord_axis_sq(s1, s2, l1, l2, smax, k2));
+        const double by = sqrt(chord_axis_sq(s2, s1, l2, l1, smax, k2));
+        ex = bx < ex ? bx : ex;
+        ey = by < ey ? by : ey;
+        zlo = -chord_height(-lo, smax, k2);
+        zhi = chord_height(hi, smax, k2);
+    } else {
+        zlo = k2 * lo;
+        zhi = k2 * hi;
+    }
+    if (zlo < -zcap) zlo = -zcap;
+    if (zhi > zcap) zhi = zcap;
+    const double zpad = zcap / 1024.0;
+    hx = ex * infl;
+    hy = ey * infl;
+    zlo = zlo * infl - zpad;
+    zhi = zhi * infl + zpad;
+}
+
 // Everything of one primitive except its tile count: the record, depth key,
 // rectangle and conic; `cl` receives the tile rectangle and conic for the
 // tile tests (nx = 0 when it covers no tile).
@@ -167,46 +231,61 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
 
     // local box of the support (see qgs_preprocess in qgs.h)
     const double s1 = sf1, s2 = sf2, l1 = lf1, l2 = lf2;
-    const double infl = 1.0 + 1.0 / 1024.0;
-    const double k = a.k_sigma;
-    const double hx = (k * s1) * infl, hy = (k * s2) * infl;
-    const double m1 = (l1 * s1) * s1, m2 = (l2 * s2) * s2;
-    const double k2 = k * k;
-    const double smax = s1 > s2 ? s1 : s2;
-    const double zcap = k * smax;
-    double lo = 0.0, hi = 0.0;
-    lo = m1 < lo ? m1 : lo; lo = m2 < lo ? m2 : lo;
-    hi = m1 > hi ? m1 : hi; hi = m2 > hi ? m2 : hi;
-    double zlo = k2 * lo, zhi = k2 * hi;
-    if (zlo < -zcap) zlo = -zcap;
-    if (zhi > zcap) zhi = zcap;
-    const double zpad = zcap / 1024.0;
-    zlo = zlo * infl - zpad;
-    zhi = zhi * infl + zpad;
+    double hx, hy, zlo, zhi;
+    local_box(s1, s2, l1, l2, (double)a.k_sigma, a.tight != 0, hx, hy, zlo, zhi);
 
     const double fx = a.cam.fx, fy = a.cam.fy, cxp = a.cam.cx, cyp = a.cam.cy;
     const double near_d = a.near_plane;
-    bool behind = false;
-    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    // the box's corners in camera space; the rectangle bounds the projection
+    // of the part of the box in front of the near plane (hits need a camera
+    // depth above it): the corners in front and, where an edge crosses the
+    // plane, the crossing point
+    double Pc[8][3];
+    uint32_t front = 0;
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
         const double X = (c & 1) ? hx : -hx, Y = (c & 2) ? hy : -hy, Z = (c & 4) ? zhi : zlo;
-        double P[3];
-        for (int i = 0; i < 3; ++i) P[i] = fma(Rc[3 * i], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
-        if (!(P[2] > near_d)) {
-            behind = true;
-            continue;
-        }
-        const double u = fma(fx, P[0] / P[2], cxp), v = fma(fy, P[1] / P[2], cyp);
+        for (int i = 0; i < 3; ++i) Pc[c][i] = fma(Rc[3 * i], X, fma(Rc[3 * i + 1], Y, fma(Rc[3 * i + 2], Z, cc[i])));
+        if (Pc[c][2] > near_d) front |= 1u << c;
+    }
+    const bool behind = front != 0xFFu;
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!((front >> c) & 1u)) continue;
+        const double u = fma(fx, Pc[c][0] / Pc[c][2], cxp), v = fma(fy, Pc[c][1] / Pc[c][2], cyp);
         umin = u < umin ? u : umin;
         umax = u > umax ? u : umax;
         vmin = v < vmin ? v : vmin;
         vmax = v > vmax ? v : vmax;
     }
+    if (behind && front != 0u) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            // edge e joins corner c and c | bit, c without that bit
+            const int bit = 1 << (e >> 2), low = e & 3;
+            const int c0 = bit == 1 ? (low << 1) : (bit == 2 ? ((low & 2) << 1) | (low & 1) : low);
+            const int c1 = c0 | bit;
+            const bool f0 = (front >> c0) & 1u, f1 = (front >> c1) & 1u;
+            if (f0 == f1) continue;
+            const double *F = f0 ? Pc[c0] : Pc[c1], *B = f0 ? Pc[c1] : Pc[c0];
+            const double sc = (F[2] - near_d) / (F[2] - B[2]);
+            const double xq = F[0] + sc * (B[0] - F[0]), yq = F[1] + sc * (B[1] - F[1]);
+            const double u = fma(fx, xq / near_d, cxp), v = fma(fy, yq / near_d, cyp);
+            umin = u < umin ? u : umin;
+            umax = u > umax ? u : umax;
+            vmin = v < vmin ? v : vmin;
+            vmax = v > vmax ? v : vmax;
+        }
+    }
     const int W = a.cam.width, H = a.cam.height;
     int px0, px1, py0, py1;
     bool empty = false;
-    if (behind) {
-        px0 = 0; px1 = W - 1; py0 = 0; py1 = H - 1;
+    if (front == 0u) {
+        // the whole box is behind the near plane
+        empty = true;
+        px0 = py0 = 0;
+        px1 = py1 = -1;
     } else {
         const double pad_px = 1.0 / 64.0;
         const double a0 = (umin - 0.5) - pad_px, a1 = (umax - 0.5) + pad_px;

@@ -29,6 +29,7 @@ struct PreprocessArgs {
     double *frame;  // optional
     const float *sh;  // optional SH colour [n][K][3]
     int sh_degree;
+    int tight;        // QGS_TIGHT_BOUND: the chord-bound local box
 };
 
 struct PreprocessBwdArgs {

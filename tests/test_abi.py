@@ -31,6 +31,15 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= set(L.exported_symbols())
 
 
+def test_binding_mirrors_every_header_constant():
+    src = open(HEADER).read()
+    consts = re.findall(r"#define\s+(QGS_[A-Z0-9_]+)\s+(-?\d+)u?\b", src)
+    assert len(consts) >= 8
+    for name, val in consts:
+        assert hasattr(L, name), name
+        assert getattr(L, name) == int(val), name
+
+
 def test_status_strings_and_defaults():
     lib = L.lib()
     assert lib.qgs_status_string(L.QGS_ERR_CAPACITY) == b"tile list capacity exceeded"

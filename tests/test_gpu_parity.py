@@ -39,8 +39,8 @@ def cfg(i, **kw):
     return _CFG_CACHE[key]
 
 
-def check_keys(scene, cam, st):
-    ks = oracle.keys(scene, cam)
+def check_keys(scene, cam, st, tight=False):
+    ks = oracle.keys(scene, cam, tight=tight)
     n = scene.n
     dk = to_np(st.depth_key).view(np.uint32)[:n]
     assert np.array_equal(dk, ks["depth_bits"]), "depth keys"

@@ -486,18 +486,23 @@ def _subset_keys(ks, idx):
     return out
 
 
-def test_emitted_tiles_contain_the_support():
+@pytest.mark.parametrize("tight", [False, True])
+def test_emitted_tiles_contain_the_support(tight):
     """Brute force: render every primitive alone (every accepted hit blended)
     and check that each touched pixel lies in its pixel rectangle and in one of
     the tiles emitted for it."""
     rng = np.random.default_rng(21)
     n = 160
     sc = scenes.scene_uniform_cube(n, 21, scale_range=(0.02, 0.4), curv_lim=5.0)
-    # a few primitives straddling the near plane and some off to the side
+    # a few primitives straddling the near plane, some of them well off the
+    # view axis, and some off to the side
     sc.center[:10, 2] = -2.6 + rng.uniform(-0.3, 0.3, 10)
+    sc.center[20:30, 2] = -2.8 + rng.uniform(-0.05, 0.05, 10)
+    sc.center[20:30, 0] = rng.uniform(-0.5, 0.5, 10)
+    sc.center[20:30, 1] = rng.uniform(-0.4, 0.4, 10)
     sc.center[10:20, 0] = rng.uniform(1.5, 2.5, 10)
     cam = scenes.look_at((0.0, 0.0, -3.0), width=96, height=80, f=80)
-    ks = oracle.keys(sc, cam)
+    ks = oracle.keys(sc, cam, tight=tight)
     keys_, prims, ranges = oracle.bin_sort(ks, cam)
     emitted = {}
     for k, p in zip(keys_, prims):
@@ -522,6 +527,11 @@ def test_emitted_tiles_contain_the_support():
         assert tiles_hit <= emitted[p], (p, tiles_hit - emitted[p])
         areas.append(((x1 - x0 + 1) * (y1 - y0 + 1), len(touched), len(emitted[p]), len(tiles_hit)))
     assert n_checked > 80
+    # boxes cut by the near plane are bounded by their part in front of it:
+    # most are smaller than the screen
+    straddle = [p for p in list(range(10)) + list(range(20, 30)) if not ks["culled"][p]]
+    full = [p for p in straddle if tuple(ks["rect_px"][p]) == (0, 0, cam.width - 1, cam.height - 1)]
+    assert len(straddle) >= 10 and len(full) < len(straddle) // 2, (len(straddle), len(full))
     a = np.array(areas)
     # not trivially the full screen, and the conic test removes tiles
     assert np.median(a[:, 0] / a[:, 1]) < 12.0
