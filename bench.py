@@ -79,7 +79,8 @@ def parse():
     ap.add_argument("--workload", type=int, choices=(2, 3), default=2,
                     help="2: 500K quadrics, 1600x1200 (headline); 3: 3M quadrics, shells + background ball, "
                          "1237x822 and 1600x1064 views from inside the scene")
-    ap.add_argument("--tight-bound", action="store_true", help="the chord-bound local box (QGS_TIGHT_BOUND)")
+    ap.add_argument("--loose-bound", action="store_true",
+                    help="the k-sigma local box without the chord bound (QGS_TIGHT_BOUND off)")
     ap.add_argument("--cpu-rows", type=int, default=1200, help="rows of view 0 the CPU oracle renders (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -140,9 +141,7 @@ def main():
     steps_total = args.warmup + args.steps
     used = sorted({i % len(cams) for i in range(steps_total)})
     mode = (L.QGS_TILE_DEPTH | L.QGS_RESORT) if args.full_model else 0
-    if args.tight_bound:
-        mode |= L.QGS_TIGHT_BOUND
-    probe = R.Renderer(device=dev, opts=R.make_opts(flags=mode))
+    probe = R.Renderer(device=dev, opts=R.make_opts(flags=mode, tight_bound=not args.loose_bound))
     max_pairs = 0
     for v in used:
         st = probe.preprocess(sc_t, cams[v])
@@ -152,7 +151,8 @@ def main():
     log(f"[bench] max pairs over used views {max_pairs}, capacity {capacity}", q)
 
     # evaluation counts (untimed): list entries processed and blended pairs
-    cnt_r = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=L.QGS_COUNT_EVALS | mode))
+    cnt_r = R.Renderer(device=dev, capacity=capacity,
+                       opts=R.make_opts(flags=L.QGS_COUNT_EVALS | mode, tight_bound=not args.loose_bound))
     evals_per_view = []
     for v in used[: min(8, len(used))]:
         st = cnt_r.forward(sc_t, cams[v], exact=False)
@@ -160,7 +160,7 @@ def main():
         evals_per_view.append(int(st.counters.cpu().numpy().view(np.uint32)[2]))
     evals_mean = float(np.mean(evals_per_view))
 
-    rend = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=mode))
+    rend = R.Renderer(device=dev, capacity=capacity, opts=R.make_opts(flags=mode, tight_bound=not args.loose_bound))
     gen = torch.Generator(device=dev)
     gen.manual_seed(2)
     dLs = {}
@@ -276,7 +276,7 @@ def main():
                                 "gradients"),
                    "n_prims": cfg.scene.n, "width": W, "height": H, "views": len(cams),
                    "ordering": "per-tile depth + 8-entry resort" if args.full_model else "centre depth",
-                   "bound": "chord (tight)" if args.tight_bound else "default"},
+                   "bound": "k-sigma box" if args.loose_bound else "chord bound"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs_per_view": int(np.mean(npairs)),
         "evals_per_view": int(evals_mean),

@@ -91,7 +91,7 @@ typedef struct qgs_render_opts {
     float A_eps;      /* 1e-6: |A| below it (unit ray) takes the tangent-plane root -C/B (supplement) */
     float bg[3];      /* background colour, added with the final transmittance */
     int32_t tile;     /* must be 16 (16 x 16 tiles) */
-    uint32_t flags;   /* QGS_* flags below */
+    uint32_t flags;   /* QGS_* flags below; default QGS_TIGHT_BOUND */
 } qgs_render_opts;
 
 #define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */

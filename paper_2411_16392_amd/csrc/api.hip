@@ -148,7 +148,7 @@ void qgs_default_opts(qgs_render_opts *o)
     o->A_eps = 1e-6f;
     o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
     o->tile = 16;
-    o->flags = 0u;
+    o->flags = QGS_TIGHT_BOUND;
 }
 
 qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t capacity, uint32_t flags,

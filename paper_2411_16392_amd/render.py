@@ -30,16 +30,21 @@ def make_camera(cam) -> L.QgsCamera:
     return c
 
 
-def make_opts(**kw) -> L.QgsRenderOpts:
+def make_opts(tight_bound: bool = True, **kw) -> L.QgsRenderOpts:
+    """qgs_default_opts() with fields replaced by keyword.  `flags` is added to
+    the default flags; tight_bound=False clears QGS_TIGHT_BOUND (the k-sigma
+    local box without the chord bound)."""
     o = L.qgs_default_opts()
     for k, v in kw.items():
         if k == "bg":
             for i in range(3):
                 o.bg[i] = float(v[i])
         elif k == "flags":
-            o.flags = int(v)
+            o.flags |= int(v)
         else:
             setattr(o, k, float(v))
+    if not tight_bound:
+        o.flags &= ~L.QGS_TIGHT_BOUND
     return o
 
 
@@ -113,6 +118,7 @@ class FrameState:
     distortion: torch.Tensor | None = None
     median_pos: torch.Tensor | None = None
     frame: torch.Tensor | None = None  # per-primitive frames for the per-tile sort depth
+    flags: int = 0  # the renderer's option flags the state was preprocessed with
 
     def prim_buf(self) -> L.QgsPrimBuf:
         p = L.QgsPrimBuf()
@@ -198,6 +204,7 @@ class Renderer:
             normal=torch.empty((3, H, W), dtype=torch.float32, device=dev),
             T_final=torch.empty((H, W), dtype=torch.float32, device=dev),
             last=torch.empty((H, W), dtype=torch.int32, device=dev),
+            flags=int(self.opts.flags),
         )
         if self.opts.flags & L.QGS_TILE_DEPTH:
             st.frame = torch.empty(max(n, 1) * 16, dtype=torch.float64, device=dev)

@@ -39,7 +39,10 @@ def cfg(i, **kw):
     return _CFG_CACHE[key]
 
 
-def check_keys(scene, cam, st, tight=False):
+def check_keys(scene, cam, st, tight=None):
+    # the local box the state was preprocessed with (QGS_TIGHT_BOUND is a default flag)
+    if tight is None:
+        tight = bool(st.flags & L.QGS_TIGHT_BOUND)
     ks = oracle.keys(scene, cam, tight=tight)
     n = scene.n
     dk = to_np(st.depth_key).view(np.uint32)[:n]
@@ -154,7 +157,7 @@ def test_capacity_mode_and_overflow():
     r = R.Renderer(capacity=4_000_000)
     st = r.forward(R.scene_to_device(c.scene), cam, exact=False)
     torch.cuda.synchronize()
-    ks = oracle.keys(c.scene, cam)
+    ks = oracle.keys(c.scene, cam, tight=bool(st.flags & L.QGS_TIGHT_BOUND))
     check_lists(ks, cam, st)
     # too small: status, device flag, empty ranges
     r2 = R.Renderer(capacity=1000)

@@ -68,7 +68,7 @@ def test_sh_backward_and_densification_stats():
     z = (sc.center.astype(np.float64) @ Wr.T + camv[9:12])[:, 2]
     want = np.hypot(0.5 * cam.width * z / camv[12] * gcam[:, 0], 0.5 * cam.height * z / camv[13] * gcam[:, 1])
     vis = to_np(stats["visible"])
-    live = ks["tiles"] > 0
+    live = oracle.keys(sc, cam, tight=bool(st.flags & L.QGS_TIGHT_BOUND))["tiles"] > 0
     assert np.array_equal(vis, 2.0 * live)
     got = to_np(stats["screen_grad"]) / 2.0
     assert np.all(np.abs(got - want) <= 2e-3 * (want + 1e-2 * want.max()))

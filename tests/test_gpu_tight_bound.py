@@ -1,4 +1,4 @@
-"""The chord-bound local box (QGS_TIGHT_BOUND) on the GPU.
+"""The chord-bound local box (QGS_TIGHT_BOUND, a default flag) on the GPU.
 
 Keys, rectangles, conics and sorted lists are bit-exact against the oracle's
 key stage with the same box.  The box is conservative, so the rendered image
@@ -71,7 +71,8 @@ def test_tight_keys_and_lists_bitexact():
     for name, sc, cam in cases():
         print(name, flush=True)
         for det in (False, True):
-            _, st = gpu_forward(sc, cam, opts=dict(flags=TB | (DET if det else 0)))
+            _, st = gpu_forward(sc, cam, opts=dict(flags=DET if det else 0))
+            assert st.flags & TB
             ks = check_keys(sc, cam, st, tight=True)
             check_lists(ks, cam, st)
 
@@ -79,7 +80,7 @@ def test_tight_keys_and_lists_bitexact():
 def test_tight_keys_headline_size():
     c = cfg(2, n_views=64)
     cam = c.cameras[13]
-    _, st = gpu_forward(c.scene, cam, opts=dict(flags=TB))
+    _, st = gpu_forward(c.scene, cam)
     ks = check_keys(c.scene, cam, st, tight=True)
     assert check_lists(ks, cam, st) > 1_000_000
 
@@ -95,7 +96,7 @@ def test_tight_bound_same_image_and_deterministic_gradients():
         dLt = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dL]
         out = {}
         for flags in (DET, DET | TB):
-            r = R.Renderer(opts=R.make_opts(flags=flags))
+            r = R.Renderer(opts=R.make_opts(flags=flags, tight_bound=bool(flags & TB)))
             sc_t = R.scene_to_device(sc)
             st = r.forward(sc_t, cam)
             g = r.backward(sc_t, st, *dLt)
@@ -112,14 +113,14 @@ def test_tight_bound_same_image_and_deterministic_gradients():
 
 def test_tight_bound_fewer_pairs_on_curved_primitives():
     sc, cam = curved_cfg0()
-    _, a = gpu_forward(sc, cam)
-    _, b = gpu_forward(sc, cam, opts=dict(flags=TB))
+    _, a = gpu_forward(sc, cam, opts=dict(tight_bound=False))
+    _, b = gpu_forward(sc, cam)
     assert b.num_pairs < 0.85 * a.num_pairs, (a.num_pairs, b.num_pairs)
 
 
 def test_tight_bound_oracle_parity_curved():
     sc, cam = curved_cfg0()
-    _, st = gpu_forward(sc, cam, opts=dict(flags=TB))
+    _, st = gpu_forward(sc, cam)
     o = oracle.render(sc, cam)
     from gpu_helpers import window_of
     res = compare_forward(window_of(st, (0, 0, cam.width, cam.height)), o, o["margin"] >= 1.0, "curved")
@@ -132,7 +133,7 @@ def test_tight_bound_oracle_parity_curved():
     margin_full, _ = oracle_margin_full(sc, cam, win, ks)
     dLm = masked_dL(dL, margin_full)
     og = oracle.render(sc, cam, window=win, dL=dLm, key_stage=ks)["grads"]
-    r = R.Renderer(opts=R.make_opts(flags=TB))
+    r = R.Renderer()
     sc_t = R.scene_to_device(sc)
     st = r.forward(sc_t, cam)
     g = r.backward(sc_t, st, *(torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dLm))
