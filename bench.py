@@ -45,6 +45,21 @@ FLOPS_BLEND_FWD = 38
 #   frame and projection (re-evaluation of the pair counted by FLOPS_EVAL)
 FLOPS_BLEND_BWD = 230
 
+# Algorithmic HBM bytes of the memory-bound stages (what each kernel must move):
+#   preprocess: 60 B of parameters read; 128 B record, 64 B conic, 16 B tile
+#   rectangle, 4 B depth key and 4 B tile count written per primitive
+BYTES_PRE_PRIM = 60 + 216
+#   binning: depth-key init (16 B) and four 8-bit radix passes over (key, index)
+#   (20 B each), the pair-offset scan (8 B) and the emission's per-primitive
+#   reads (order, rectangle, conic, offset, count: 92 B) per primitive ...
+BYTES_SORT_PRIM = 16 + 80 + 8 + 92
+#   ... and per pair the emitted (tile, primitive) (8 B), two 8-bit radix passes
+#   (20 B each) and the range scan (4 B)
+BYTES_SORT_PAIR = 8 + 40 + 4
+#   preprocess backward (inside the backward stage): record gradient 64 B,
+#   parameters 60 B and tile count 4 B read, 60 B of gradients written
+BYTES_PRE_BWD_PRIM = 64 + 60 + 4 + 60
+
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_render_500k_1600x1200.md")
 
@@ -256,6 +271,25 @@ def main():
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": None, "traffic": None}
 
+    # every stage against its own roofline (algorithmic work / stage time)
+    n_p = cfg.scene.n
+    pairs_mean = float(np.mean(npairs))
+    stage_roofline = {
+        "preprocess": {"bound": "hbm", "bytes": n_p * BYTES_PRE_PRIM},
+        "bin_sort": {"bound": "hbm", "bytes": n_p * BYTES_SORT_PRIM + pairs_mean * BYTES_SORT_PAIR},
+        "render_fwd": {"bound": "alu", "flops": kern["render_fwd"]},
+        "render_bwd": {"bound": "alu", "flops": kern["render_bwd"],
+                       "bytes_preprocess_bwd": n_p * BYTES_PRE_BWD_PRIM},
+    }
+    for k, v in stage_roofline.items():
+        t = stage_ms[k] * 1e-3
+        if v["bound"] == "hbm":
+            v["GB/s"] = round(v["bytes"] / t / 1e9, 1)
+            v["frac"] = round(v["bytes"] / t / 1e9 / PEAK_HBM_GBS, 4)
+        else:
+            v["TFLOP/s"] = round(v["flops"] / t / 1e12, 3)
+            v["frac"] = round(v["flops"] / t / 1e12 / PEAK_FP32_UNPACKED_TFLOPS, 4)
+
     result = {
         "metric": METRIC,
         "value": round(mpix, 3),
@@ -282,6 +316,7 @@ def main():
         "evals_per_view": int(evals_mean),
         "evals_per_s": evals_mean / (stage_ms["render_fwd"] * 1e-3),
         "roofline": roofline,
+        "stages_roofline": stage_roofline,
     }
 
     if not args.no_cpu_baseline and args.cpu_rows > 0:

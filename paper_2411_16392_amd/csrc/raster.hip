@@ -267,6 +267,8 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
                                   const Hit &H, float G, float dalpha, float w, const float gc[3], float dt,
                                   const float gn[3], float dK, float *gr)
 {
+    // gradient arithmetic only (no decisions): products may fuse into fma
+#pragma clang fp contract(fast)
     // colour and depth outputs
     gr[G_R] += gc[0] * w;
     gr[G_G] += gc[1] * w;
@@ -507,6 +509,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
                     if (alpha >= P.alpha_min) {
+#pragma clang fp contract(fast)
                         contrib = true;
                         const float4 cr = *reinterpret_cast<const float4 *>(wr + 24);
                         const float rgb[3] = {cr.y, cr.z, cr.w};
