@@ -150,6 +150,23 @@ def test_keys_and_lists_bitexact_unbounded():
         check_lists(ks, cam, st)
 
 
+def test_keys_lists_and_crops_with_three_tile_passes():
+    # 4112 x 4112: 257 x 257 = 66049 tiles need 17 bits, so the tile sort takes
+    # three 8-bit passes (an odd count ends in the other buffer pair)
+    c = cfg(0)
+    cam = scenes.look_at((0.0, 0.0, -3.0), width=4112, height=4112, f=4112)
+    assert cam.tiles_x * cam.tiles_y > 65536
+    for det in (False, True):
+        r, st = gpu_forward(c.scene, cam, opts=dict(flags=L.QGS_DETERMINISTIC_BWD) if det else None)
+        ks = check_keys(c.scene, cam, st)
+        assert check_lists(ks, cam, st) > 300_000
+    ks = oracle.keys(c.scene, cam)
+    for win in [(4112 - 40, 4112 - 36, 40, 36), (2030, 2040, 48, 40)]:
+        o = oracle.render(c.scene, cam, window=win, key_stage=ks)
+        res = compare_forward(window_of(st, win), o, o["margin"] >= 1.0, f"4112 {win}")
+        print("4112", win, res)
+
+
 def test_capacity_mode_and_overflow():
     c = cfg(1)
     cam = c.cameras[0]
