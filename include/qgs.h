@@ -216,6 +216,17 @@ typedef struct qgs_images {
        accumulated in the running-mean form L += w (L/W + W (t - mean)^2) */
     float *distortion;      /* [H][W] */
     uint32_t *median_pos;   /* [H][W] 1 + tile-list position of the median entry (0: none) */
+    /* optional replay bitmap for the backward (both or neither; not with
+       QGS_RESORT).  For 8 x 8 pixel block b (0..3, row-major) of tile t, whose
+       list is [start_t, start_t + len_t): bit j of word w is set when at least
+       one of the block's pixels blended list entry 64 w + j.  The block's
+       words start at steps[4 (floor(start_t / 64) + t) + b ceil(len_t / 64)];
+       step_count[4 t + b] is the number of words written.  `steps` holds
+       4 (ceil(capacity / 64) + tiles + 1) words.  The backward then visits only
+       the marked entries (the others contribute nothing) and gives the same
+       gradients. */
+    uint64_t *steps;
+    uint32_t *step_count;   /* [4 * tiles] */
 } qgs_images;
 
 /* Upstream gradients, same layouts; a NULL plane means zero.  Any non-NULL
@@ -304,25 +315,28 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
                         qgs_stream_t stream);
 
 /*
- * Forward rasterizer: one 256-thread workgroup per 16 x 16 tile, primitive
- * records staged in LDS in batches, per-pixel ray-paraboloid intersection with
- * near/far root selection and the k_sigma geodesic cut-off, geodesic Gaussian
- * density, front-to-back compositing with stop once T would fall below T_eps.
- * Writes all planes of `out`; the geometry maps only if they are set (all four
- * or none).  With QGS_RESORT, accepted hits pass through the per-pixel buffer
- * (depth and normal planes required) and `last` is 1 + the list position of
- * the last hit the pixel took in.  Errors: QGS_ERR_INVALID_ARG.
+ * Forward rasterizer: one 256-thread workgroup per 16 x 16 tile, each wave64
+ * an 8 x 8 pixel block that walks the tile's list on its own; per-pixel
+ * ray-paraboloid intersection with near/far root selection and the k_sigma
+ * geodesic cut-off, geodesic Gaussian density, front-to-back compositing with
+ * stop once T would fall below T_eps.  Writes all planes of `out`; depth and
+ * normal only if set (both or neither), T_final, last and the replay list only
+ * if set, the geometry maps only if they are set (all four or none).  With
+ * QGS_RESORT, accepted hits pass through the per-pixel buffer (depth and
+ * normal planes required) and `last` is 1 + the list position of the last hit
+ * the pixel took in.  Errors: QGS_ERR_INVALID_ARG.
  */
 qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists, const qgs_camera *cam,
                           const qgs_render_opts *opts, qgs_images *out, qgs_stream_t stream);
 
 /*
  * Backward: adjoint of qgs_render_fwd and qgs_preprocess.  Each tile's list is
- * walked back to front from each pixel's `last` entry, recomputing
- * transmittance by division (supplement, back-to-front adjoint), with
- * per-primitive gradients reduced across the tile's pixels in LDS before one
- * global atomic per field per (tile, primitive); QGS_DETERMINISTIC_BWD instead
- * stores one partial per pair and sums each primitive's partials in a fixed
+ * walked back to front from each pixel's `last` entry (only the replay list's
+ * entries when `fwd` carries one), recomputing transmittance by division
+ * (supplement, back-to-front adjoint), with per-primitive gradients reduced
+ * across each 8 x 8 block's pixels in registers before one global atomic per
+ * field per (block, primitive); QGS_DETERMINISTIC_BWD instead stores one
+ * partial per (pair, block) and sums each primitive's partials in a fixed
  * order.  Then the chain rule to the scene parameters, one thread per
  * primitive.  With QGS_RESORT the lists are walked front to back instead,
  * replaying each pixel's resort buffer up to its `last` (supplement,

@@ -62,7 +62,12 @@ class QgsTileLists(ctypes.Structure):
 class QgsImages(ctypes.Structure):
     _fields_ = [("color", c_void_p), ("depth", c_void_p), ("normal", c_void_p), ("T_final", c_void_p),
                 ("last", c_void_p), ("curvature", c_void_p), ("median_depth", c_void_p),
-                ("distortion", c_void_p), ("median_pos", c_void_p)]
+                ("distortion", c_void_p), ("median_pos", c_void_p), ("steps", c_void_p), ("step_count", c_void_p)]
+
+
+def replay_words(capacity: int, tiles: int) -> int:
+    """64-bit words of the backward replay bitmap for a list capacity and a tile count."""
+    return 4 * ((capacity + 63) // 64 + tiles + 1)
 
 
 class QgsImageGrads(ctypes.Structure):

@@ -248,6 +248,8 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     if (n_geo != 0 && n_geo != 4) return QGS_ERR_INVALID_ARG;
     if (n_geo == 4 && !out->depth) return QGS_ERR_INVALID_ARG;
     if ((opts->flags & QGS_RESORT) && !out->depth) return QGS_ERR_INVALID_ARG;
+    if ((out->steps == nullptr) != (out->step_count == nullptr)) return QGS_ERR_INVALID_ARG;
+    if (out->steps && (opts->flags & QGS_RESORT)) return QGS_ERR_INVALID_ARG;
     FwdOut o;
     o.flags = opts->flags;
     o.color = out->color;
@@ -260,6 +262,8 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     o.median_depth = out->median_depth;
     o.distortion = out->distortion;
     o.median_pos = out->median_pos;
+    o.steps = out->steps;
+    o.step_count = out->step_count;
     return hip_status(launch_render_fwd(raster_args(prims, lists, cam), raster_params(cam, opts), o,
                                         (hipStream_t)stream));
 }
@@ -283,6 +287,7 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     // the front-to-back adjoint of the resort mode needs every composited output
     if ((opts->flags & QGS_RESORT) && (!fwd->color || !fwd->depth || !fwd->normal)) return QGS_ERR_INVALID_ARG;
     if ((opts->flags & QGS_RESORT) && geo && !fwd->curvature) return QGS_ERR_INVALID_ARG;
+    if ((fwd->steps == nullptr) != (fwd->step_count == nullptr)) return QGS_ERR_INVALID_ARG;
     if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags)) return QGS_ERR_WORKSPACE;
     float *grad_rec = reinterpret_cast<float *>(ws);
     size_t off = ((size_t)(scene->n > 0 ? scene->n : 1) * 64 + 255) & ~(size_t)255;
@@ -303,6 +308,10 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.color = fwd->color;
     in.normal = fwd->normal;
     in.curvature = fwd->curvature;
+    // the replay list applies to the walk in list order only
+    const bool replay = fwd->steps && !(opts->flags & QGS_RESORT);
+    in.steps = replay ? fwd->steps : nullptr;
+    in.step_count = replay ? fwd->step_count : nullptr;
     in.flags = opts->flags;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
                                                  grad_rec, scratch, scene->n, lists->capacity, s));

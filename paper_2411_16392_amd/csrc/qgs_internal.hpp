@@ -106,6 +106,9 @@ struct FwdOut {
     // geometry maps: all set or all null
     float *curvature, *median_depth, *distortion;
     uint32_t *median_pos;
+    // replay bitmap for the backward (both or null)
+    uint64_t *steps;
+    uint32_t *step_count;
 };
 
 struct BwdIn {
@@ -119,6 +122,9 @@ struct BwdIn {
     // the forward's colour, normal and curvature (the front-to-back adjoint of
     // the resort mode needs every composited output)
     const float *color, *normal, *curvature;
+    // the forward's replay bitmap (both or null)
+    const uint64_t *steps;
+    const uint32_t *step_count;
     uint32_t flags;
 };
 

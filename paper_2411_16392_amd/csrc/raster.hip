@@ -97,29 +97,44 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
 // GEO: also the curvature, median-depth and depth-distortion maps.  NRM:
 // accumulate depth and normal (off for colour-only rendering).
 //
+// First word of the replay bitmap of 8 x 8 block `wave` of tile `tile`, whose
+// list is [start, start + len): tiles take 4 ceil(len / 64) words each from
+// word 4 (floor(start / 64) + tile) on, which never overlaps the next tile's
+// (its start is at least start + len); at most 4 (capacity / 64 + tiles + 1)
+// words in all.
+__device__ inline size_t replay_base(uint32_t start, uint32_t len, int tile, int wave)
+{
+    return 4 * ((size_t)(start >> 6) + (size_t)tile) + (size_t)wave * ((len + 63u) >> 6);
+}
+
 // Each wave walks its tile's list on its own, with no LDS and no barrier: the
 // list is read 64 entries at a time (lane i fetches entry b + i's primitive id
 // and pixel rectangle, one batch ahead), a ballot selects the entries whose
 // rectangle meets the wave's 8 x 8 block, and only those are visited.  A
 // visited entry's record is read with a wave-uniform address, so it is
 // fetched once for the wave (scalar loads) and sits in scalar registers.
+// `recs` is a.records again and `replay` o.steps, as restrict arguments: the
+// records are never written here, which keeps the scalar loads legal although
+// the loop stores replay words.
 template <bool GEO, bool NRM>
 #if QGS_FWD_MIN_WAVES > 0
-__global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
+__global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o,
+                                                                         const float4 *__restrict__ recs,
+                                                                         uint64_t *__restrict__ replay)
 #else
-__global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o)
+__global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o,
+                                                      const float4 *__restrict__ recs, uint64_t *__restrict__ replay)
 #endif
 {
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
     const uint32_t start = a.ranges[2 * tile], n = a.ranges[2 * tile + 1] - start;
     const PixelRay ray = make_ray(px, py, P);
-    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
     uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0, w_rect = 0, w_eval = 0, w_blend = 0;
@@ -128,6 +143,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     // sum of weights, mean depth and distortion
     float kk = 0.0f, med = 0.0f, gW = 0.0f, gm = 0.0f, gL = 0.0f;
     uint32_t med_pos = 0;
+    // replay bitmap of this block: bit j of word w set when some pixel blended entry 64 w + j
+    uint64_t *bm = replay ? replay + replay_base(start, n, tile, wave) : nullptr;
+    uint32_t n_words = 0;
 
     // batch fetch: lane i holds entry b + i's primitive and rectangle
     uint32_t nxt_pid = 0;
@@ -147,6 +165,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
                                                        cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
         uint64_t m = __ballot(rel);
+        uint64_t blended = 0ull;
         while (m != 0ull && wave_alive) {
             const int j = __builtin_ctzll(m);
             m &= m - 1ull;
@@ -209,11 +228,20 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                     }
                 }
             }
-            if (o.counters) w_blend += __ballot(last == pos1) != 0ull ? 1u : 0u;
+            if (o.counters || bm) {
+                const bool any_blend = __ballot(last == pos1) != 0ull;
+                if (o.counters) w_blend += any_blend ? 1u : 0u;
+                if (any_blend) blended |= 1ull << j;
+            }
             wave_alive = __ballot(!done) != 0ull;
+        }
+        if (bm) {
+            bm[b >> 6] = blended;  // every lane stores the same word
+            n_words = (b >> 6) + 1u;
         }
     }
 
+    if (o.step_count && lane == 0) o.step_count[4 * tile + wave] = n_words;
     if (inside) {
         const size_t hw = (size_t)P.width * P.height, pix = (size_t)py * P.width + px;
         o.color[pix] = c0 + T * P.bg[0];
@@ -415,7 +443,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -463,6 +491,108 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     float S[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) S[c] = c < 3 ? T * P.bg[c] : 0.0f;
+    // adjoint of visited entry `pos` (primitive pj, pixel rectangle x0..x1, y0..y1)
+    auto visit = [&](uint32_t pos, uint32_t pj, int x0, int x1, int y0, int y1) {
+        const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+        float dxp, dyp;
+        const bool lane_on = pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
+                             conic_offsets(wr, ray, dxp, dyp);
+        if (__ballot(lane_on) == 0ull) return;
+        float gr[NGRAD];
+#pragma unroll
+        for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
+        bool contrib = false;
+        if (lane_on) {
+            Prim p;
+            load_prim(wr, P, p);
+            Hit H;
+            if (ray_hit(p, ray, P, dxp, dyp, H)) {
+                const float G = __expf(-0.5f * H.E);
+                const float alpha = fminf(P.alpha_max, p.op * G);
+                if (alpha >= P.alpha_min) {
+#pragma clang fp contract(fast)
+                    contrib = true;
+                    const float4 cr = *reinterpret_cast<const float4 *>(wr + 24);
+                    const float rgb[3] = {cr.y, cr.z, cr.w};
+                    const float om = 1.0f - alpha;
+                    const float iom = __builtin_amdgcn_rcpf(om);
+                    const float Ti = T * iom;
+                    const float w = alpha * Ti;
+                    float X[NX];
+                    X[0] = rgb[0];
+                    X[1] = rgb[1];
+                    X[2] = rgb[2];
+                    const float t = (p.Zc + H.s) * ray.enorm;
+                    X[3] = t;
+                    float nl[3], il;
+                    const float f = hit_normal(p, H, nl, il);
+                    X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
+                    X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
+                    X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
+                    float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+                    float dt = gd * w;
+                    if (GEO) {
+                        const float dtm = t - gm;
+                        X[7] = hit_curvature(p, il);
+                        X[8] = __builtin_fmaf(gW * dtm, dtm, gLW);
+                        gx[7] = gK;
+                        gx[8] = gdist;
+                        dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
+                        if (pos + 1u == med_pos) dt += gmed;
+                    }
+                    float dalpha = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] * iom);
+#pragma unroll
+                    for (int c = 0; c < NX; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
+                    T = Ti;
+                    entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
+                }
+            }
+        }
+        if (__ballot(contrib) != 0ull) {
+            float g16[16];
+#pragma unroll
+            for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD ? gr[f] : 0.0f;
+            // lane 4f (f < NGRAD) ends with the wave total of field f
+            const float tot = wave_reduce_scatter16(g16);
+            const int f = lane >> 2;
+            if ((lane & 3) == 0 && f < NGRAD) {
+                if (DET)
+                    pair_scratch[((size_t)start + pos) * 64 + wave * 16 + f] = tot;
+                else if (tot != 0.0f)
+                    unsafeAtomicAdd(grad_rec + (size_t)pj * 16 + f, tot);
+            }
+        }
+    };
+
+    if (in.steps) {
+        // replay: only the entries some pixel of this block blended, last first
+        const uint32_t nw_max = (list_len + 63u) >> 6;
+        uint32_t nw = in.step_count[4 * tile + wave];
+        nw = nw < nw_max ? nw : nw_max;
+        const uint64_t *bm = in.steps + replay_base(start, list_len, tile, wave);
+        uint32_t nxt_pid = 0;
+        int32_t w = (int32_t)nw - 1;
+        if (w >= 0 && (uint32_t)(64 * w + lane) < list_len) nxt_pid = a.pair_prim[start + 64 * w + lane];
+        for (; w >= 0; --w) {
+            const uint32_t cur_pid = nxt_pid;
+            nxt_pid = 0;
+            if (w >= 1) nxt_pid = a.pair_prim[start + 64 * (w - 1) + lane];  // word w - 1 is full
+            uint64_t m = bm[w];
+            while (m != 0ull) {
+                const int j = 63 - __builtin_clzll(m);
+                m &= ~(1ull << j);
+                const uint32_t pos = 64u * (uint32_t)w + (uint32_t)j;
+                if (pos >= list_len) continue;  // not written by a matching forward
+                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+                const int4 r = *reinterpret_cast<const int4 *>(recs + (size_t)pj * 8);
+                visit(pos, pj, r.x, r.y, r.z, r.w);
+            }
+        }
+        return;
+    }
+
     // never walk past the tile's list, whatever `last` holds
     const uint32_t wmax = wave_max_u32(last);
     const uint32_t nmax = wmax < list_len ? wmax : list_len;
@@ -488,81 +618,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
         while (m != 0ull) {
             const int j = 63 - __builtin_clzll(m);
             m &= ~(1ull << j);
-            const uint32_t pos = (uint32_t)(lo + j);
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-            const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
-            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
-            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
-            float dxp, dyp;
-            const bool lane_on = pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
-                                 conic_offsets(wr, ray, dxp, dyp);
-            if (__ballot(lane_on) == 0ull) continue;
-            float gr[NGRAD];
-#pragma unroll
-            for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
-            bool contrib = false;
-            if (lane_on) {
-                Prim p;
-                load_prim(wr, P, p);
-                Hit H;
-                if (ray_hit(p, ray, P, dxp, dyp, H)) {
-                    const float G = __expf(-0.5f * H.E);
-                    const float alpha = fminf(P.alpha_max, p.op * G);
-                    if (alpha >= P.alpha_min) {
-#pragma clang fp contract(fast)
-                        contrib = true;
-                        const float4 cr = *reinterpret_cast<const float4 *>(wr + 24);
-                        const float rgb[3] = {cr.y, cr.z, cr.w};
-                        const float om = 1.0f - alpha;
-                        const float iom = __builtin_amdgcn_rcpf(om);
-                        const float Ti = T * iom;
-                        const float w = alpha * Ti;
-                        float X[NX];
-                        X[0] = rgb[0];
-                        X[1] = rgb[1];
-                        X[2] = rgb[2];
-                        const float t = (p.Zc + H.s) * ray.enorm;
-                        X[3] = t;
-                        float nl[3], il;
-                        const float f = hit_normal(p, H, nl, il);
-                        X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
-                        X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
-                        X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
-                        float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
-                        float dt = gd * w;
-                        if (GEO) {
-                            const float dtm = t - gm;
-                            X[7] = hit_curvature(p, il);
-                            X[8] = __builtin_fmaf(gW * dtm, dtm, gLW);
-                            gx[7] = gK;
-                            gx[8] = gdist;
-                            dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
-                            if (pos + 1u == med_pos) dt += gmed;
-                        }
-                        float dalpha = 0.0f;
-#pragma unroll
-                        for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] * iom);
-#pragma unroll
-                        for (int c = 0; c < NX; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
-                        T = Ti;
-                        entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
-                    }
-                }
-            }
-            if (__ballot(contrib) != 0ull) {
-                float g16[16];
-#pragma unroll
-                for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD ? gr[f] : 0.0f;
-                // lane 4f (f < NGRAD) ends with the wave total of field f
-                const float tot = wave_reduce_scatter16(g16);
-                const int f = lane >> 2;
-                if ((lane & 3) == 0 && f < NGRAD) {
-                    if (DET)
-                        pair_scratch[((size_t)start + pos) * 64 + wave * 16 + f] = tot;
-                    else if (tot != 0.0f)
-                        unsafeAtomicAdd(grad_rec + (size_t)pj * 16 + f, tot);
-                }
-            }
+            visit((uint32_t)(lo + j), pj, __builtin_amdgcn_readlane(cur_rect.x, j),
+                  __builtin_amdgcn_readlane(cur_rect.y, j), __builtin_amdgcn_readlane(cur_rect.z, j),
+                  __builtin_amdgcn_readlane(cur_rect.w, j));
         }
     }
 }
@@ -666,7 +725,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -827,7 +886,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -1052,11 +1111,14 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
         return hipGetLastError();
     }
     if (o.curvature)
-        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+                           reinterpret_cast<const float4 *>(a.records), o.steps);
     else if (o.depth)
-        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+                           reinterpret_cast<const float4 *>(a.records), o.steps);
     else
-        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+                           reinterpret_cast<const float4 *>(a.records), o.steps);
     return hipGetLastError();
 }
 
