@@ -216,15 +216,16 @@ typedef struct qgs_images {
        accumulated in the running-mean form L += w (L/W + W (t - mean)^2) */
     float *distortion;      /* [H][W] */
     uint32_t *median_pos;   /* [H][W] 1 + tile-list position of the median entry (0: none) */
-    /* optional replay bitmap for the backward (both or neither; not with
-       QGS_RESORT).  For 8 x 8 pixel block b (0..3, row-major) of tile t, whose
-       list is [start_t, start_t + len_t): bit j of word w is set when at least
-       one of the block's pixels blended list entry 64 w + j.  The block's
-       words start at steps[4 (floor(start_t / 64) + t) + b ceil(len_t / 64)];
+    /* optional replay bitmap for the backward (both or neither).  For 8 x 8
+       pixel block b (0..3, row-major) of tile t, whose list is
+       [start_t, start_t + len_t): bit j of word w is set when at least one of
+       the block's pixels blended list entry 64 w + j (with QGS_RESORT: took it
+       into its resort buffer).  The block's words start at
+       steps[4 (floor(start_t / 64) + t) + b ceil(len_t / 64)];
        step_count[4 t + b] is the number of words written.  `steps` holds
        4 (ceil(capacity / 64) + tiles + 1) words.  The backward then visits only
-       the marked entries (the others contribute nothing) and gives the same
-       gradients. */
+       the marked entries (the others change nothing) and gives the same
+       gradients.  The backward must get the bitmap of the same forward. */
     uint64_t *steps;
     uint32_t *step_count;   /* [4 * tiles] */
 } qgs_images;
@@ -331,7 +332,7 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
 
 /*
  * Backward: adjoint of qgs_render_fwd and qgs_preprocess.  Each tile's list is
- * walked back to front from each pixel's `last` entry (only the replay list's
+ * walked back to front from each pixel's `last` entry (only the replay bitmap's
  * entries when `fwd` carries one), recomputing transmittance by division
  * (supplement, back-to-front adjoint), with per-primitive gradients reduced
  * across each 8 x 8 block's pixels in registers before one global atomic per

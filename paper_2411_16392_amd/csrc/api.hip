@@ -249,7 +249,6 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     if (n_geo == 4 && !out->depth) return QGS_ERR_INVALID_ARG;
     if ((opts->flags & QGS_RESORT) && !out->depth) return QGS_ERR_INVALID_ARG;
     if ((out->steps == nullptr) != (out->step_count == nullptr)) return QGS_ERR_INVALID_ARG;
-    if (out->steps && (opts->flags & QGS_RESORT)) return QGS_ERR_INVALID_ARG;
     FwdOut o;
     o.flags = opts->flags;
     o.color = out->color;
@@ -308,10 +307,8 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.color = fwd->color;
     in.normal = fwd->normal;
     in.curvature = fwd->curvature;
-    // the replay list applies to the walk in list order only
-    const bool replay = fwd->steps && !(opts->flags & QGS_RESORT);
-    in.steps = replay ? fwd->steps : nullptr;
-    in.step_count = replay ? fwd->step_count : nullptr;
+    in.steps = fwd->steps;
+    in.step_count = fwd->step_count;
     in.flags = opts->flags;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
                                                  grad_rec, scratch, scene->n, lists->capacity, s));

@@ -720,7 +720,8 @@ __device__ inline void local_dir(const Prim &p, const PixelRay &r, float &e0, fl
 }
 
 template <bool GEO>
-__global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterParams P, FwdOut o)
+__global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterParams P, FwdOut o,
+                                                         const float4 *__restrict__ recs, uint64_t *__restrict__ replay)
 {
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
@@ -731,7 +732,6 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
     const bool inside = px < P.width && py < P.height;
     const uint32_t start = a.ranges[2 * tile], n = a.ranges[2 * tile + 1] - start;
     const PixelRay ray = make_ray(px, py, P);
-    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, dep = 0.0f, n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
     uint32_t last = 0, stop_pos = 0, n_eval = 0, n_blend = 0;
@@ -740,6 +740,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
     uint32_t med_pos = 0;
     ResortBuf<3> buf;  // fields: alpha, x, y
     buf.cnt = 0;
+    // replay bitmap of this block: bit j of word w set when some pixel took entry 64 w + j in
+    uint64_t *bm = replay ? replay + replay_base(start, n, tile, wave) : nullptr;
+    uint32_t n_words = 0;
 
     // blend the nearest pending hit (per lane)
     auto pop_blend = [&]() {
@@ -804,6 +807,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
         const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
                                                        cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
         uint64_t m = __ballot(rel);
+        uint64_t taken = 0ull;
         while (m != 0ull && wave_alive) {
             const int j = __builtin_ctzll(m);
             m &= m - 1ull;
@@ -832,9 +836,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
                     }
                 }
             }
+            if (bm && __ballot(last == pos1) != 0ull) taken |= 1ull << j;
             wave_alive = __ballot(!done) != 0ull;
         }
+        if (bm) {
+            bm[b >> 6] = taken;  // every lane stores the same word
+            n_words = (b >> 6) + 1u;
+        }
     }
+    if (o.step_count && lane == 0) o.step_count[4 * tile + wave] = n_words;
     // end of the list: blend what is pending, nearest first
     while (buf.cnt > 0 && !done) pop_blend();
 
@@ -1035,56 +1045,85 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         }
     };
 
-    const uint32_t wmax = wave_max_u32(last);
-    const uint32_t nmax = wmax < list_len ? wmax : list_len;
-    uint32_t nxt_pid = 0;
-    int4 nxt_rect = make_int4(0, -1, 0, -1);
-    if ((uint32_t)lane < nmax) {
-        nxt_pid = a.pair_prim[start + lane];
-        nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
-    }
-    for (uint32_t b = 0; b < nmax; b += 64) {
-        const uint32_t cur_pid = nxt_pid;
-        const int4 cur_rect = nxt_rect;
-        if (b + 64 + (uint32_t)lane < nmax) {
-            nxt_pid = a.pair_prim[start + b + 64 + lane];
-            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
-        }
-        const bool rel = b + (uint32_t)lane < nmax && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
-                                                          cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
-        uint64_t m = __ballot(rel);
-        while (m != 0ull) {
-            const int j = __builtin_ctzll(m);
-            m &= m - 1ull;
-            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
-            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
-            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
-            const uint32_t pos1 = b + (uint32_t)j + 1u;
-            float dxp, dyp;
-            const bool lane_on = !done && pos1 <= last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
-                                 conic_offsets(w, ray, dxp, dyp);
-            if (__ballot(lane_on) == 0ull) continue;
-            float gr[NGRAD];
+    // replay of visited entry pos1 - 1 (primitive pj, pixel rectangle x0..x1, y0..y1)
+    auto visit = [&](uint32_t pos1, uint32_t pj, int x0, int x1, int y0, int y1) {
+        const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+        float dxp, dyp;
+        const bool lane_on = !done && pos1 <= last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
+                             conic_offsets(w, ray, dxp, dyp);
+        if (__ballot(lane_on) == 0ull) return;
+        float gr[NGRAD];
 #pragma unroll
-            for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
-            bool has = false;
-            uint32_t g_pid = 0, g_pos = 0;
-            if (lane_on) {
-                Prim p;
-                load_prim(w, P, p);
-                Hit H;
-                if (ray_hit(p, ray, P, dxp, dyp, H)) {
-                    const float G = __expf(-0.5f * H.E);
-                    const float alpha = fminf(P.alpha_max, p.op * G);
-                    if (alpha >= P.alpha_min) {
-                        const float fv[1] = {alpha};
-                        buf.insert((p.Zc + H.s) * ray.enorm, fv, pj, pos1);
-                        if (buf.cnt == RS_K) has = pop_grad(gr, g_pid, g_pos);
-                    }
+        for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
+        bool has = false;
+        uint32_t g_pid = 0, g_pos = 0;
+        if (lane_on) {
+            Prim p;
+            load_prim(w, P, p);
+            Hit H;
+            if (ray_hit(p, ray, P, dxp, dyp, H)) {
+                const float G = __expf(-0.5f * H.E);
+                const float alpha = fminf(P.alpha_max, p.op * G);
+                if (alpha >= P.alpha_min) {
+                    const float fv[1] = {alpha};
+                    buf.insert((p.Zc + H.s) * ray.enorm, fv, pj, pos1);
+                    if (buf.cnt == RS_K) has = pop_grad(gr, g_pid, g_pos);
                 }
             }
-            if (__ballot(has) != 0ull) flush_grads(gr, has, g_pid, g_pos);
+        }
+        if (__ballot(has) != 0ull) flush_grads(gr, has, g_pid, g_pos);
+    };
+
+    if (in.steps) {
+        // only the entries some pixel of this block took into its buffer, in list order
+        const uint32_t nw_max = (list_len + 63u) >> 6;
+        uint32_t nw = in.step_count[4 * tile + wave];
+        nw = nw < nw_max ? nw : nw_max;
+        const uint64_t *bm = in.steps + replay_base(start, list_len, tile, wave);
+        uint32_t nxt_pid = 0;
+        if (nw > 0 && (uint32_t)lane < list_len) nxt_pid = a.pair_prim[start + lane];
+        for (uint32_t w = 0; w < nw; ++w) {
+            const uint32_t cur_pid = nxt_pid;
+            nxt_pid = 0;
+            if (w + 1 < nw && 64 * (w + 1) + (uint32_t)lane < list_len) nxt_pid = a.pair_prim[start + 64 * (w + 1) + lane];
+            uint64_t m = bm[w];
+            while (m != 0ull) {
+                const int j = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t pos = 64u * w + (uint32_t)j;
+                if (pos >= list_len) continue;  // not written by a matching forward
+                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+                const int4 r = *reinterpret_cast<const int4 *>(recs + (size_t)pj * 8);
+                visit(pos + 1u, pj, r.x, r.y, r.z, r.w);
+            }
+        }
+    } else {
+        const uint32_t wmax = wave_max_u32(last);
+        const uint32_t nmax = wmax < list_len ? wmax : list_len;
+        uint32_t nxt_pid = 0;
+        int4 nxt_rect = make_int4(0, -1, 0, -1);
+        if ((uint32_t)lane < nmax) {
+            nxt_pid = a.pair_prim[start + lane];
+            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        }
+        for (uint32_t b = 0; b < nmax; b += 64) {
+            const uint32_t cur_pid = nxt_pid;
+            const int4 cur_rect = nxt_rect;
+            if (b + 64 + (uint32_t)lane < nmax) {
+                nxt_pid = a.pair_prim[start + b + 64 + lane];
+                nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+            }
+            const bool rel = b + (uint32_t)lane < nmax && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                              cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+            uint64_t m = __ballot(rel);
+            while (m != 0ull) {
+                const int j = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
+                visit(b + (uint32_t)j + 1u, pj, __builtin_amdgcn_readlane(cur_rect.x, j),
+                      __builtin_amdgcn_readlane(cur_rect.y, j), __builtin_amdgcn_readlane(cur_rect.z, j),
+                      __builtin_amdgcn_readlane(cur_rect.w, j));
+            }
         }
     }
     // end of the replay: the pending hits, nearest first
@@ -1105,9 +1144,11 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
     if (ntiles == 0) return hipSuccess;
     if (o.flags & QGS_RESORT) {
         if (o.curvature)
-            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+                               reinterpret_cast<const float4 *>(a.records), o.steps);
         else
-            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o);
+            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+                               reinterpret_cast<const float4 *>(a.records), o.steps);
         return hipGetLastError();
     }
     if (o.curvature)

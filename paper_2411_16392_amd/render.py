@@ -119,7 +119,7 @@ class FrameState:
     median_pos: torch.Tensor | None = None
     frame: torch.Tensor | None = None  # per-primitive frames for the per-tile sort depth
     flags: int = 0  # the renderer's option flags the state was preprocessed with
-    # replay bitmap of the forward for the backward (not with the resort mode)
+    # replay bitmap of the forward for the backward
     steps: torch.Tensor | None = None
     step_count: torch.Tensor | None = None
 
@@ -184,10 +184,9 @@ class Renderer:
         # the emission map is built only for the deterministic backward
         st.emit_to_sorted = (torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
                              if self.opts.flags & L.QGS_DETERMINISTIC_BWD else None)
-        if not self.opts.flags & L.QGS_RESORT:
-            ntiles = st.ranges.numel() // 2
-            st.steps = torch.empty(L.replay_words(cap, ntiles), dtype=torch.int64, device=self.device)
-            st.step_count = torch.empty(4 * ntiles, dtype=torch.int32, device=self.device)
+        ntiles = st.ranges.numel() // 2
+        st.steps = torch.empty(L.replay_words(cap, ntiles), dtype=torch.int64, device=self.device)
+        st.step_count = torch.empty(4 * ntiles, dtype=torch.int32, device=self.device)
 
     def preprocess(self, scene_t: dict, cam) -> FrameState:
         n = int(scene_t["center"].shape[0])

@@ -439,6 +439,29 @@ def test_deterministic_backward():
         assert np.max(np.abs(g_at[k] - g_det[k])) <= 1e-5 * scale, k
 
 
+@pytest.mark.parametrize("mode", ["centre depth", "full model"])
+def test_replay_bitmap_gives_identical_gradients(mode):
+    # the backward visiting only the entries the forward marked (replay bitmap)
+    # against the full walk: bit-identical in the deterministic mode
+    c = cfg(1)
+    cam = c.cameras[0]
+    flags = L.QGS_DETERMINISTIC_BWD | ((L.QGS_TILE_DEPTH | L.QGS_RESORT) if mode == "full model" else 0)
+    r = R.Renderer(opts=R.make_opts(flags=flags))
+    sc_t = R.scene_to_device(c.scene)
+    st = r.forward(sc_t, cam)
+    assert st.steps is not None
+    dL = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+          for a in scenes.upstream_grads(12, cam.height, cam.width)]
+    g_replay = {k: to_np(v) for k, v in r.backward(sc_t, st, *dL).items()}
+    words = to_np(st.step_count).view(np.uint32)
+    assert words.sum() > 0
+    st.steps, st.step_count = None, None
+    g_walk = {k: to_np(v) for k, v in r.backward(sc_t, st, *dL).items()}
+    torch.cuda.synchronize()
+    for k in g_walk:
+        assert np.array_equal(g_replay[k], g_walk[k]), k
+
+
 def test_autograd_function_matches_direct_backward():
     c = cfg(0)
     cam = c.cameras[0]
