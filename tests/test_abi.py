@@ -82,6 +82,35 @@ def test_invalid_arguments_rejected_before_launch():
         L.qgs_preprocess(sc, cam, o, pb)
 
 
+def test_replay_bitmap_arguments_both_or_neither():
+    # placeholder addresses that are never dereferenced: the call must fail
+    # validation on the host before anything is launched
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check with placeholder pointers")
+    cam = R.make_camera(scenes.look_at((0, 0, -3), width=16, height=16, f=16))
+    pb = L.QgsPrimBuf()
+    pb.n = 1
+    pb.records = pb.depth_key = pb.rect = pb.tiles = pb.pair_offset = pb.conic = 0x1000
+    lists = L.QgsTileLists()
+    lists.pair_tile = lists.pair_prim = lists.ranges = lists.counters = lists.tile_order = 0x1000
+    lists.capacity = 16
+    im = L.QgsImages()
+    im.color = im.depth = im.normal = im.T_final = im.last = 0x1000
+    im.steps = 0x1000  # without step_count
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_render_fwd(pb, lists, cam, L.qgs_default_opts(), im)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+    sc = L.QgsScene()
+    sc.n = 0
+    dl = L.QgsImageGrads()
+    g = L.QgsSceneGrads()
+    pb.n = 0
+    with pytest.raises(L.QgsError) as e:
+        L.qgs_render_bwd(sc, pb, lists, cam, L.qgs_default_opts(), im, dl, g, 0x1000, 1 << 20)
+    assert e.value.status == L.QGS_ERR_INVALID_ARG
+
+
 def test_binding_struct_layouts_match_the_header(tmp_path):
     """sizeof and every field offset of the header's structs, as compiled by the
     C compiler, against the ctypes mirrors of the binding."""
