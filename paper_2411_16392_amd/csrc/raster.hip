@@ -172,10 +172,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             ++w_rect;
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
             const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
-            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
-            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
             float dxp, dyp;
-            const bool lane_on = !done && px >= x0 && px <= x1 && py >= y0 && py <= y1 && conic_offsets(w, ray, dxp, dyp);
+            const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
             ++w_eval;
             const uint32_t pos1 = b + (uint32_t)j + 1u;
@@ -491,12 +489,11 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
     float S[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) S[c] = c < 3 ? T * P.bg[c] : 0.0f;
-    // adjoint of visited entry `pos` (primitive pj, pixel rectangle x0..x1, y0..y1)
-    auto visit = [&](uint32_t pos, uint32_t pj, int x0, int x1, int y0, int y1) {
+    // adjoint of visited entry `pos` (primitive pj)
+    auto visit = [&](uint32_t pos, uint32_t pj) {
         const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
         float dxp, dyp;
-        const bool lane_on = pos < last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
-                             conic_offsets(wr, ray, dxp, dyp);
+        const bool lane_on = pos < last && conic_offsets(wr, ray, dxp, dyp);
         if (__ballot(lane_on) == 0ull) return;
         float gr[NGRAD];
 #pragma unroll
@@ -585,9 +582,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                 m &= ~(1ull << j);
                 const uint32_t pos = 64u * (uint32_t)w + (uint32_t)j;
                 if (pos >= list_len) continue;  // not written by a matching forward
-                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-                const int4 r = *reinterpret_cast<const int4 *>(recs + (size_t)pj * 8);
-                visit(pos, pj, r.x, r.y, r.z, r.w);
+                visit(pos, (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j));
             }
         }
         return;
@@ -618,10 +613,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
         while (m != 0ull) {
             const int j = 63 - __builtin_clzll(m);
             m &= ~(1ull << j);
-            const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-            visit((uint32_t)(lo + j), pj, __builtin_amdgcn_readlane(cur_rect.x, j),
-                  __builtin_amdgcn_readlane(cur_rect.y, j), __builtin_amdgcn_readlane(cur_rect.z, j),
-                  __builtin_amdgcn_readlane(cur_rect.w, j));
+            visit((uint32_t)(lo + j), (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j));
         }
     }
 }
@@ -813,10 +805,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
             m &= m - 1ull;
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
             const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
-            const int x0 = __builtin_amdgcn_readlane(cur_rect.x, j), x1 = __builtin_amdgcn_readlane(cur_rect.y, j);
-            const int y0 = __builtin_amdgcn_readlane(cur_rect.z, j), y1 = __builtin_amdgcn_readlane(cur_rect.w, j);
             float dxp, dyp;
-            const bool lane_on = !done && px >= x0 && px <= x1 && py >= y0 && py <= y1 && conic_offsets(w, ray, dxp, dyp);
+            const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
             const uint32_t pos1 = b + (uint32_t)j + 1u;
             if (lane_on) {
@@ -1045,12 +1035,11 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         }
     };
 
-    // replay of visited entry pos1 - 1 (primitive pj, pixel rectangle x0..x1, y0..y1)
-    auto visit = [&](uint32_t pos1, uint32_t pj, int x0, int x1, int y0, int y1) {
+    // replay of visited entry pos1 - 1 (primitive pj)
+    auto visit = [&](uint32_t pos1, uint32_t pj) {
         const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
         float dxp, dyp;
-        const bool lane_on = !done && pos1 <= last && px >= x0 && px <= x1 && py >= y0 && py <= y1 &&
-                             conic_offsets(w, ray, dxp, dyp);
+        const bool lane_on = !done && pos1 <= last && conic_offsets(w, ray, dxp, dyp);
         if (__ballot(lane_on) == 0ull) return;
         float gr[NGRAD];
 #pragma unroll
@@ -1092,9 +1081,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
                 m &= m - 1ull;
                 const uint32_t pos = 64u * w + (uint32_t)j;
                 if (pos >= list_len) continue;  // not written by a matching forward
-                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-                const int4 r = *reinterpret_cast<const int4 *>(recs + (size_t)pj * 8);
-                visit(pos + 1u, pj, r.x, r.y, r.z, r.w);
+                visit(pos + 1u, (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j));
             }
         }
     } else {
@@ -1119,10 +1106,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
             while (m != 0ull) {
                 const int j = __builtin_ctzll(m);
                 m &= m - 1ull;
-                const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-                visit(b + (uint32_t)j + 1u, pj, __builtin_amdgcn_readlane(cur_rect.x, j),
-                      __builtin_amdgcn_readlane(cur_rect.y, j), __builtin_amdgcn_readlane(cur_rect.z, j),
-                      __builtin_amdgcn_readlane(cur_rect.w, j));
+                visit(b + (uint32_t)j + 1u, (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j));
             }
         }
     }
