@@ -206,7 +206,10 @@ __device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterPar
             nc = 2;
         }
     }
-    for (int k = 0; k < nc; ++k) {
+    // unrolled: a loop over the two candidates costs selects and branches per step
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k >= nc) break;
         const float s = k == 0 ? cand0 : cand1;
         const float z = p.Zc + s;
         if (!(z > P.near_plane)) continue;
