@@ -8,17 +8,23 @@
 // meets the wave's block, and only those are visited.  A visited entry's
 // 128-byte record is read with a wave-uniform address, i.e. by scalar loads
 // into scalar registers, once per wave.  Each lane first applies the conic
-// pre-test; the intersection runs only if some lane passes it.
+// pre-test (no per-lane rectangle test: it removed almost nothing the conic
+// keeps); the intersection runs only if some lane passes it.
 //
 // Forward (Eq. 1, compositing front to back): a wave stops once every lane is
-// done (ballot).
+// done (ballot).  It can also mark, per block and 64-entry batch, the entries
+// some pixel blended (the replay bitmap).
 // Backward (supplement, back-to-front adjoint): each pixel starts at its last
 // blended entry, recovers T_i = T_{i+1} / (1 - alpha_i), and keeps the suffix
 // sum S_i = sum_{j>i} w_j X_j + T_final bg, so dX/dalpha_i = T_i X_i - S_i /
-// (1 - alpha_i).  A visited entry's 14 per-primitive gradient fields are
-// reduce-scattered over the wave and added to global memory by 14 lanes with
-// one atomic instruction; the deterministic variant stores them into the
-// pair's slot for the wave and a second pass sums the slots in a fixed order.
+// (1 - alpha_i).  With the replay bitmap a wave visits only the marked
+// entries (the others change nothing).  A visited entry's 14 per-primitive
+// gradient fields are reduce-scattered over the wave and added to global
+// memory by 14 lanes with one atomic instruction; the deterministic variant
+// stores them into the pair's slot for the wave and a second pass sums the
+// slots in a fixed order.  The gradient arithmetic, which takes no decision,
+// may contract into fma; everything that decides (hit, root, cut-off,
+// alpha) is evaluated without contraction, identically in both passes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
