@@ -80,7 +80,8 @@ __device__ inline T block_excl_scan(T v, T *s_wave /* [4] */, T &total)
 }
 
 // ---------------------------------------------------------------------------
-// device-wide exclusive scan: partial sums, scan of partials, apply
+// device-wide exclusive scan: partial sums per 4096-element chunk, then each
+// chunk's scan plus the sum of the partials before it
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_scan_partials(const T *in, uint64_t n, T *part)
@@ -97,26 +98,20 @@ __global__ __launch_bounds__(256) void k_scan_partials(const T *in, uint64_t n, 
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
+// Each block adds the sum of the partials before it (its own short reduction:
+// there are n / 4096 partials) to the exclusive scan of its chunk; the last
+// block also writes the grand total.
 template <typename T>
-__global__ __launch_bounds__(256) void k_scan_top(T *part, uint64_t nparts, T *grand_total)
+__global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_t n, const T *part, T *grand_total)
 {
     __shared__ T s_wave[4];
-    T carry = 0;
-    for (uint64_t base = 0; base < nparts; base += 256) {
-        const uint64_t i = base + threadIdx.x;
-        const T v = i < nparts ? part[i] : 0;
-        T total;
-        const T ex = block_excl_scan(v, s_wave, total);
-        if (i < nparts) part[i] = carry + ex;
-        carry += total;
+    T pre = 0;
+    for (uint64_t k0 = 0; k0 < blockIdx.x; k0 += 256) {
+        const uint64_t k = k0 + threadIdx.x;
+        T tot;
+        (void)block_excl_scan(k < blockIdx.x ? part[k] : (T)0, s_wave, tot);
+        pre += tot;
     }
-    if (threadIdx.x == 0 && grand_total) *grand_total = carry;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_t n, const T *part)
-{
-    __shared__ T s_wave[4];
     // blocked arrangement: thread t owns items [t*16, t*16 + 16) of the chunk
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_CHUNK + (uint64_t)threadIdx.x * (SCAN_CHUNK / 256);
     T v[SCAN_CHUNK / 256];
@@ -128,13 +123,14 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_
         acc += v[k];
     }
     T total;
-    T run = block_excl_scan(acc, s_wave, total) + part[blockIdx.x];
+    T run = block_excl_scan(acc, s_wave, total) + pre;
 #pragma unroll
     for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
         const uint64_t i = base + k;
         if (i < n) out[i] = run;
         run += v[k];
     }
+    if (grand_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *grand_total = pre + total;
 }
 
 // exclusive scan of a small array by one 1024-thread workgroup: each thread
@@ -171,8 +167,8 @@ static hipError_t device_excl_scan(const T *in, T *out, uint64_t n, T *part, T *
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_partials<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, n, part);
-    hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(256), 0, stream, part, nb, grand_total);
-    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, out, n, (const T *)part);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(256), 0, stream, in, out, n, (const T *)part,
+                       grand_total);
     return hipGetLastError();
 }
 
