@@ -98,23 +98,31 @@ static double conic_f(const double *C, double x, double y)
 
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+/* Does tile (tx, ty) -- its pixel centres widened by 1/64 pixel -- meet the
+   interior f <= 0 of the convex conic C?  Yes iff the conic's centre lies in
+   the rectangle or f's minimum along one of the four edges is <= 0 (the edge
+   minimiser clamped to the edge).  The divisions are written as products with
+   reciprocals (1/fx, 1/fy, 1/det, 1/a, 1/c), each rounded once; the GPU
+   evaluates the same sequence. */
 static int oracle_tile_hit(const double *C, int tx, int ty, const float *cam, int width, int height)
 {
     const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const double ifx = 1.0 / fx, ify = 1.0 / fy;
     const double pad_px = 1.0 / 64.0;
     const int ux0 = tx * OT, ux1 = (tx * OT + OT - 1) < width - 1 ? tx * OT + OT - 1 : width - 1;
     const int vy0 = ty * OT, vy1 = (ty * OT + OT - 1) < height - 1 ? ty * OT + OT - 1 : height - 1;
-    const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) / fx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) / fx;
-    const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) / fy, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) / fy;
+    const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) * ifx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) * ifx;
+    const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) * ify, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) * ify;
     const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
-    const double det = a * c - b * b;
-    const double mx = (b * e - c * d) / det, my = (b * d - a * e) / det;
+    const double inv_det = 1.0 / (a * c - b * b);
+    const double mx = (b * e - c * d) * inv_det, my = (b * d - a * e) * inv_det;
+    const double inv_a = 1.0 / a, inv_c = 1.0 / c;
     if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 1;
     const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
     for (int k = 0; k < 2; ++k) {
-        const double y = clampd(-(b * xs[k] + e) / c, y0, y1);
+        const double y = clampd(-(b * xs[k] + e) * inv_c, y0, y1);
         if (conic_f(C, xs[k], y) <= 0.0) return 1;
-        const double x = clampd(-(b * ys[k] + d) / a, x0, x1);
+        const double x = clampd(-(b * ys[k] + d) * inv_a, x0, x1);
         if (conic_f(C, x, ys[k]) <= 0.0) return 1;
     }
     return 0;

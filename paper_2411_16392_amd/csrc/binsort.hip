@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
             const double *C = conic + 8 * (size_t)p;
             for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
             cl.cok = C[6] != 0.0 ? 1u : 0u;
-            if (cl.cok) conic_center(cl.C, cl.mx, cl.my);
+            if (cl.cok) conic_center(cl.C, cl.mx, cl.my, cl.ia, cl.ic);
             cl.base = base;
             cl.cnt = (uint32_t)cnt;
             cl.prim = p;

@@ -353,7 +353,7 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     for (int i = 0; i < 6; ++i) cq[i] = C[i];
     cq[6] = cok ? 1.0 : 0.0;
     for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
-    if (cok) conic_center(C, cl.mx, cl.my);
+    if (cok) conic_center(C, cl.mx, cl.my, cl.ia, cl.ic);
     cl.cok = cok ? 1u : 0u;
     cl.tx0 = tx0;
     cl.ty0 = ty0;

@@ -8,7 +8,9 @@
 // inside.  f is a convex quadratic on the image plane, so the tile's rectangle
 // of pixel centres (widened by 1/64 pixel) meets the interior iff f's
 // minimiser lies in the rectangle or the minimum of f along one of the four
-// edges is <= 0.  FP64, fixed operation order, no contraction.
+// edges is <= 0.  FP64, fixed operation order, no contraction.  Divisions are
+// taken once per primitive (1/det, 1/a, 1/c) and once per camera (1/fx,
+// 1/fy); the per-tile test multiplies.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -24,32 +26,37 @@ __device__ inline double conic_eval(const double *C, double x, double y)
 
 __device__ inline double clamp_d(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// The conic's centre (minimiser of f), a per-primitive constant of the test.
-__device__ inline void conic_center(const double *C, double &mx, double &my)
+// Per-primitive constants of the test: the conic's centre (minimiser of f)
+// and the reciprocals 1/a, 1/c of the edge minimisers.
+__device__ inline void conic_center(const double *C, double &mx, double &my, double &ia, double &ic)
 {
 #pragma clang fp contract(off)
     const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
-    const double det = a * c - b * b;
-    mx = (b * e - c * d) / det;
-    my = (b * d - a * e) / det;
+    const double idet = 1.0 / (a * c - b * b);
+    mx = (b * e - c * d) * idet;
+    my = (b * d - a * e) * idet;
+    ia = 1.0 / a;
+    ic = 1.0 / c;
 }
 
-__device__ inline bool conic_tile_hit(const double *C, double mx, double my, int tx, int ty, const qgs_camera &cam)
+// ifx = 1/fx, ify = 1/fy
+__device__ inline bool conic_tile_hit(const double *C, double mx, double my, double ia, double ic, int tx, int ty,
+                                      const qgs_camera &cam, double ifx, double ify)
 {
 #pragma clang fp contract(off)
-    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+    const double cx = cam.cx, cy = cam.cy;
     const double pad_px = 1.0 / 64.0;
     const int ux0 = tx * 16, ux1 = (tx * 16 + 15) < cam.width - 1 ? tx * 16 + 15 : cam.width - 1;
     const int vy0 = ty * 16, vy1 = (ty * 16 + 15) < cam.height - 1 ? ty * 16 + 15 : cam.height - 1;
-    const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) / fx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) / fx;
-    const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) / fy, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) / fy;
-    const double a = C[0], b = C[1], c = C[2], d = C[3], e = C[4];
+    const double x0 = ((((double)ux0 + 0.5) - pad_px) - cx) * ifx, x1 = ((((double)ux1 + 0.5) + pad_px) - cx) * ifx;
+    const double y0 = ((((double)vy0 + 0.5) - pad_px) - cy) * ify, y1 = ((((double)vy1 + 0.5) + pad_px) - cy) * ify;
+    const double b = C[1], d = C[3], e = C[4];
     if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
     const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
     for (int k = 0; k < 2; ++k) {
-        const double y = clamp_d(-(b * xs[k] + e) / c, y0, y1);
+        const double y = clamp_d(-(b * xs[k] + e) * ic, y0, y1);
         if (conic_eval(C, xs[k], y) <= 0.0) return true;
-        const double x = clamp_d(-(b * ys[k] + d) / a, x0, x1);
+        const double x = clamp_d(-(b * ys[k] + d) * ia, x0, x1);
         if (conic_eval(C, x, ys[k]) <= 0.0) return true;
     }
     return false;
@@ -122,7 +129,7 @@ __device__ inline uint32_t tile_depth_bits(const double *F, int tx, int ty, cons
 // ---------------------------------------------------------------------------
 struct ConicLane {
     double C[6];
-    double mx, my;
+    double mx, my, ia, ic;
     uint64_t base;               // first emission index (emission only)
     int32_t tx0, ty0, nx, ny;    // tile rectangle, nx * ny candidates (0: none)
     uint32_t excl, cnt, prim, cok;
@@ -175,6 +182,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
 {
     const int lane = threadIdx.x & 63;
     const uint32_t R = (me.nx > 0 && me.ny > 0) ? (uint32_t)me.nx * (uint32_t)me.ny : 0u;
+    const double ifx = 1.0 / (double)cam.fx, ify = 1.0 / (double)cam.fy;
     const uint32_t incl = wave_incl_scan_u32(R), excl = incl - R;
     const uint32_t total = __shfl(incl, 63, 64);
     s_wave[lane] = me;
@@ -192,7 +200,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
             const uint32_t loc = c - q.excl;
             tx = q.tx0 + (int)(loc % (uint32_t)q.nx);
             ty = q.ty0 + (int)(loc / (uint32_t)q.nx);
-            hit = q.cok == 0u || conic_tile_hit(q.C, q.mx, q.my, tx, ty, cam);
+            hit = q.cok == 0u || conic_tile_hit(q.C, q.mx, q.my, q.ia, q.ic, tx, ty, cam, ifx, ify);
         }
         const uint64_t bal = __ballot(hit);
         if (EMIT && hit) {
