@@ -200,11 +200,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *ke
                                                               uint32_t *keys_out, uint32_t *vals_out, Count cnt,
                                                               int shift, const uint32_t *hist_scan, uint32_t nblocks)
 {
+    // Each wave ranks its own contiguous segment of RS_ITEMS * 64 elements
+    // (element base + 64 (RS_ITEMS wave + k) + lane): lanes holding the same
+    // digit are found with eight ballots, the lowest of them adds the group to
+    // the wave's running digit count in LDS, so the wave needs no barrier.
+    // The block then offsets each wave by the counts of the waves before it.
     constexpr int RS_CHUNK = RS_THREADS * RS_ITEMS;
+    constexpr int NW = RS_THREADS / 64;
     __shared__ uint32_t s_keys[RS_CHUNK];
     __shared__ uint32_t s_vals[RS_CHUNK];
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[NW][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t s_wave[4];
@@ -212,20 +217,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *ke
     const uint64_t n = cnt.get();
     const uint64_t base = (uint64_t)blockIdx.x * RS_CHUNK;
     if (base >= n) return;  // uniform for the block
-    const int tid = threadIdx.x, wave = tid >> 6;
-    run[tid] = 0;
-    wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
     goff[tid] = hist_scan[(uint64_t)tid * nblocks + blockIdx.x];
     __syncthreads();
 
+    const uint64_t seg = base + (uint64_t)wave * (RS_ITEMS * 64);
     uint32_t key[RS_ITEMS], val[RS_ITEMS], rank[RS_ITEMS];
+#pragma unroll
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const uint64_t i = seg + (uint64_t)k * 64 + lane;
+        key[k] = i < n ? keys_in[i] : 0u;
+        val[k] = i < n ? vals_in[i] : 0u;
+    }
     const uint64_t lt = __lanemask_lt();
 #pragma unroll
     for (int k = 0; k < RS_ITEMS; ++k) {
-        const uint64_t i = base + (uint64_t)k * RS_THREADS + tid;
+        const uint64_t i = seg + (uint64_t)k * 64 + lane;
         const bool valid = i < n;
-        const uint32_t kk = valid ? keys_in[i] : 0u;
-        const uint32_t d = (kk >> shift) & 255u;
+        const uint32_t d = (key[k] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -235,27 +246,31 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t *ke
         }
         if (!valid) peers = 0;
         const uint32_t r_in = (uint32_t)__popcll(peers & lt);
-        if (valid && r_in == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t pre = run[d];
-        for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-        rank[k] = pre + r_in;
-        key[k] = kk;
-        val[k] = valid ? vals_in[i] : 0u;
-        __syncthreads();
-        run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
-        __syncthreads();
+        const uint32_t before = valid ? wcnt[wave][d] : 0u;
+        rank[k] = before + r_in;
+        // every lane has read the running count before the leader adds
+        __builtin_amdgcn_wave_barrier();
+        if (valid && r_in == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digit d: offsets of the waves within the block's run of d, and the run's start
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t c = wcnt[w][tid];
+        wcnt[w][tid] = tot;
+        tot += c;
     }
     uint32_t total;
-    lstart[tid] = block_excl_scan(run[tid], s_wave, total);
+    lstart[tid] = block_excl_scan(tot, s_wave, total);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < RS_ITEMS; ++k) {
-        const uint64_t i = base + (uint64_t)k * RS_THREADS + tid;
+        const uint64_t i = seg + (uint64_t)k * 64 + lane;
         if (i < n) {
             const uint32_t d = (key[k] >> shift) & 255u;
-            const uint32_t pos = lstart[d] + rank[k];
+            const uint32_t pos = lstart[d] + wcnt[wave][d] + rank[k];
             s_keys[pos] = key[k];
             s_vals[pos] = val[k];
         }
