@@ -489,12 +489,14 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
             gLW = in.distortion[pix] * iW;
         }
     }
-    // suffix sums S (colour starts with the background term); GEO adds the
-    // curvature and distortion channels
+    // composited channels: colour, depth, normal; GEO adds curvature and
+    // distortion
     constexpr int NX = GEO ? 9 : 7;
-    float S[NX];
-#pragma unroll
-    for (int c = 0; c < NX; ++c) S[c] = c < 3 ? T * P.bg[c] : 0.0f;
+    // The upstream gradients gx are fixed per pixel, so only the contraction
+    // gS = sum_c gx_c S_c of the suffix sums is needed: dX/dalpha_i contracted
+    // with gx is T_i gX_i - gS_i / (1 - alpha_i), gX_i = sum_c gx_c X_c, and
+    // gS grows by w_i gX_i (colour starts with the background term).
+    float gS = T * ((gc[0] * P.bg[0] + gc[1] * P.bg[1]) + gc[2] * P.bg[2]);
     // adjoint of visited entry `pos` (primitive pj)
     auto visit = [&](uint32_t pos, uint32_t pj) {
         const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
@@ -543,11 +545,11 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                         dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
                         if (pos + 1u == med_pos) dt += gmed;
                     }
-                    float dalpha = 0.0f;
+                    float gX = 0.0f;
 #pragma unroll
-                    for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] * iom);
-#pragma unroll
-                    for (int c = 0; c < NX; ++c) S[c] = __builtin_fmaf(w, X[c], S[c]);
+                    for (int c = 0; c < NX; ++c) gX += gx[c] * X[c];
+                    const float dalpha = Ti * gX - gS * iom;
+                    gS = __builtin_fmaf(w, gX, gS);
                     T = Ti;
                     entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
                 }
@@ -945,9 +947,12 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         Xh[7] = in.curvature[pix];
         Xh[8] = 2.0f * L;  // sum_i w_i (L / W + W (t_i - mean)^2)
     }
-    float Pf[NX];
-#pragma unroll
-    for (int c = 0; c < NX; ++c) Pf[c] = 0.0f;
+    // the forward's outputs and the prefix sums contracted with the upstream
+    // gradients: gXh = sum_c gx_c Xhat_c, gPf = sum_c gx_c sum_{j<i} w_j X_jc
+    float gXh = ((gc[0] * Xh[0] + gc[1] * Xh[1]) + gc[2] * Xh[2]) + gd * Xh[3] +
+                ((gn[0] * Xh[4] + gn[1] * Xh[5]) + gn[2] * Xh[6]);
+    if (GEO) gXh += gK * Xh[7] + gdist * Xh[8];
+    float gPf = 0.0f;
     bool done = !inside;
     ResortBuf<1> buf;  // field: alpha
     buf.cnt = 0;
@@ -999,14 +1004,13 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
             dt = __builtin_fmaf(gdist * 2.0f * w * gW, dtm, dt);
             if (pos1 == med_pos) dt += gmed;
         }
-        float dalpha = 0.0f;
+        // contracted with the fixed upstream gradients: the suffix after this
+        // entry is gXh - gPf - w gX
+        float gX = 0.0f;
 #pragma unroll
-        for (int c = 0; c < NX; ++c) {
-            const float wx = w * X[c];
-            const float Sx = (Xh[c] - Pf[c]) - wx;  // suffix after this entry
-            dalpha += gx[c] * (T * X[c] - Sx * iom);
-            Pf[c] += wx;
-        }
+        for (int c = 0; c < NX; ++c) gX += gx[c] * X[c];
+        const float dalpha = T * gX - ((gXh - gPf) - w * gX) * iom;
+        gPf = __builtin_fmaf(w, gX, gPf);
         const float rgb[3] = {X[0], X[1], X[2]};
         entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
         T = Tn;
