@@ -292,12 +292,13 @@ struct PixGrad {
 };
 
 // adjoint of one blended entry; adds into gr (the primitive's record
-// gradient).  dt: gradient with respect to the hit depth t; dK (GEO): with
-// respect to the curvature value K at the hit.
+// gradient).  dt: gradient with respect to the hit depth t; qn: the normal
+// map's upstream gradient in the local frame, Rc^T gn; dK (GEO): with respect
+// to the curvature value K at the hit.
 template <bool GEO>
 __device__ inline void entry_grad(const Prim &p, const float rgb[3], const PixelRay &ray, const RasterParams &P,
                                   const Hit &H, float G, float dalpha, float w, const float gc[3], float dt,
-                                  const float gn[3], float dK, float *gr)
+                                  const float qn[3], float dK, float *gr)
 {
     // gradient arithmetic only (no decisions): products may fuse into fma
 #pragma clang fp contract(fast)
@@ -312,11 +313,8 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     {
         float nl[3], il;
         const float f = hit_normal(p, H, nl, il);
-        const float g0 = gn[0] * w, g1 = gn[1] * w, g2 = gn[2] * w;
-        // Rc^T g
-        const float q0 = __builtin_fmaf(p.R[0], g0, __builtin_fmaf(p.R[3], g1, p.R[6] * g2));
-        const float q1 = __builtin_fmaf(p.R[1], g0, __builtin_fmaf(p.R[4], g1, p.R[7] * g2));
-        const float q2 = __builtin_fmaf(p.R[2], g0, __builtin_fmaf(p.R[5], g1, p.R[8] * g2));
+        // Rc^T (w gn)
+        const float q0 = qn[0] * w, q1 = qn[1] * w, q2 = qn[2] * w;
         // rotation: dphi += n_f x (Rc^T g), n_f = f nl
         const float nf0 = f * nl[0], nf1 = f * nl[1], nf2 = f * nl[2];
         dphi0 += nf1 * q2 - nf2 * q1;
@@ -531,10 +529,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                     X[3] = t;
                     float nl[3], il;
                     const float f = hit_normal(p, H, nl, il);
-                    X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
-                    X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
-                    X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
-                    float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+                    // gn . (f Rc nl) = f (Rc^T gn) . nl
+                    float qn[3];
+                    qn[0] = __builtin_fmaf(p.R[0], gn[0], __builtin_fmaf(p.R[3], gn[1], p.R[6] * gn[2]));
+                    qn[1] = __builtin_fmaf(p.R[1], gn[0], __builtin_fmaf(p.R[4], gn[1], p.R[7] * gn[2]));
+                    qn[2] = __builtin_fmaf(p.R[2], gn[0], __builtin_fmaf(p.R[5], gn[1], p.R[8] * gn[2]));
+                    X[4] = f * __builtin_fmaf(qn[0], nl[0], __builtin_fmaf(qn[1], nl[1], qn[2] * nl[2]));
+                    X[5] = 0.0f;
+                    X[6] = 0.0f;
+                    float gx[NX] = {gc[0], gc[1], gc[2], gd, 1.0f, 0.0f, 0.0f};
                     float dt = gd * w;
                     if (GEO) {
                         const float dtm = t - gm;
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
                     const float dalpha = Ti * gX - gS * iom;
                     gS = __builtin_fmaf(w, gX, gS);
                     T = Ti;
-                    entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
+                    entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, qn, GEO ? gK * w : 0.0f, gr);
                 }
             }
         }
@@ -990,10 +993,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         X[3] = t;
         float nl[3], il;
         const float f = hit_normal(p, H, nl, il);
-        X[4] = f * __builtin_fmaf(p.R[0], nl[0], __builtin_fmaf(p.R[1], nl[1], p.R[2] * nl[2]));
-        X[5] = f * __builtin_fmaf(p.R[3], nl[0], __builtin_fmaf(p.R[4], nl[1], p.R[5] * nl[2]));
-        X[6] = f * __builtin_fmaf(p.R[6], nl[0], __builtin_fmaf(p.R[7], nl[1], p.R[8] * nl[2]));
-        float gx[NX] = {gc[0], gc[1], gc[2], gd, gn[0], gn[1], gn[2]};
+        // gn . (f Rc nl) = f (Rc^T gn) . nl
+        float qn[3];
+        qn[0] = __builtin_fmaf(p.R[0], gn[0], __builtin_fmaf(p.R[3], gn[1], p.R[6] * gn[2]));
+        qn[1] = __builtin_fmaf(p.R[1], gn[0], __builtin_fmaf(p.R[4], gn[1], p.R[7] * gn[2]));
+        qn[2] = __builtin_fmaf(p.R[2], gn[0], __builtin_fmaf(p.R[5], gn[1], p.R[8] * gn[2]));
+        X[4] = f * __builtin_fmaf(qn[0], nl[0], __builtin_fmaf(qn[1], nl[1], qn[2] * nl[2]));
+        X[5] = 0.0f;
+        X[6] = 0.0f;
+        float gx[NX] = {gc[0], gc[1], gc[2], gd, 1.0f, 0.0f, 0.0f};
         float dt = gd * w;
         if (GEO) {
             const float dtm = t - gm;
@@ -1012,7 +1020,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
         const float dalpha = T * gX - ((gXh - gPf) - w * gX) * iom;
         gPf = __builtin_fmaf(w, gX, gPf);
         const float rgb[3] = {X[0], X[1], X[2]};
-        entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, gn, GEO ? gK * w : 0.0f, gr);
+        entry_grad<GEO>(p, rgb, ray, P, H, G, dalpha, w, gc, dt, qn, GEO ? gK * w : 0.0f, gr);
         T = Tn;
         g_pid = pid;
         g_pos = pos1;
