@@ -108,10 +108,11 @@ typedef struct qgs_render_opts {
 #define QGS_TILE_DEPTH        8u
 #define QGS_RESORT            16u
 /* QGS_TIGHT_BOUND  qgs_preprocess bounds the support with the arc-length >=
-                    chord inequality (below) instead of Q <= k^2 alone: a
-                    smaller, still conservative local box, so fewer tiles and
-                    pixel tests for strongly curved primitives and the same
-                    image.  A provably conservative alternative to the paper's
+                    chord inequality (below) instead of Q <= k^2 alone, and
+                    with the cut-off where o G can still reach alpha_min for
+                    faint primitives: a smaller, still conservative local box,
+                    so fewer tiles and pixel tests for strongly curved or
+                    faint primitives and the same image.  A provably conservative alternative to the paper's
                     tangent-plane box (supplement, bounding box calculation),
                     which can miss part of the support. */
 #define QGS_TIGHT_BOUND       32u

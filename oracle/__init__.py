@@ -50,7 +50,7 @@ def _lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
-        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P, P, i32]
+        L.oracle_keys.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, f32, f32, P, P, P, P, P, P, P, P, i32, f32]
         L.oracle_keys.restype = None
         L.oracle_bin_sort.argtypes = [i64, P, P, P, P, P, P, i32, i32, i32, i32, i64, P, P, P, P, P, f32]
         L.oracle_bin_sort.restype = i64
@@ -71,6 +71,8 @@ def _lib():
         L.oracle_local_box.restype = None
         L.oracle_tb_frustum.argtypes = [f64, f64, f64, f64, f64, P]
         L.oracle_tb_frustum.restype = None
+        L.oracle_blend_k.argtypes = [f32, f32, f32]
+        L.oracle_blend_k.restype = f64
         L.oracle_ray_hit.argtypes = [P, P, P, P, P, P, P, P]
         L.oracle_ray_hit.restype = None
         _lib_handle = L
@@ -130,6 +132,12 @@ def local_box(s1, s2, l1, l2, k=3.0, tight=False):
     return out
 
 
+def blend_k(opacity, alpha_min=1.0 / 255.0, k=3.0):
+    """Cut-off of the tight bounds for a primitive of this opacity (it blends
+    only where o G >= alpha_min)."""
+    return _lib().oracle_blend_k(float(opacity), float(alpha_min), float(k))
+
+
 def tb_frustum(s1, s2, l1, l2, k=3.0):
     """The paper's tangent-plane frustum (rho1, rho2, x1, x2, h); measurement only."""
     out = np.zeros(5, np.float64)
@@ -156,7 +164,8 @@ def keys(scene, cam, opts=None, tight=False, paper_tb=False):
     _lib().oracle_keys(n, *[_ptr(a) for a in arrs], _ptr(camv), cam.width, cam.height,
                        ctypes.c_float(o[0]), ctypes.c_float(o[1]),
                        _ptr(culled), _ptr(depth_bits), _ptr(rect_px), _ptr(rect_tile), _ptr(tiles),
-                       _ptr(conic), _ptr(conic_ok), _ptr(frame), 2 if paper_tb else int(bool(tight)))
+                       _ptr(conic), _ptr(conic_ok), _ptr(frame), 2 if paper_tb else int(bool(tight)),
+                       ctypes.c_float(o[2]))
     return dict(culled=culled, depth_bits=depth_bits, rect_px=rect_px, rect_tile=rect_tile, tiles=tiles,
                 conic=conic, conic_ok=conic_ok, frame=frame, cam=camv, width=cam.width, height=cam.height,
                 near=float(o[0]))

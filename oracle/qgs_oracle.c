@@ -168,6 +168,26 @@ static double chord_z(double m, double sm, double k2)
     return ((2.0 * k2) * m) / (1.0 + sqrt(1.0 + (4.0 * k2) * (r * r)));
 }
 
+/*
+ * The cut-off the tight bounds use for a primitive of opacity o.  It blends
+ * only where alpha = min(alpha_max, o G) >= alpha_min (R7), so G >=
+ * alpha_min / o and E <= 2 ln x with x = o / alpha_min.  ln x = 64 ln x^(1/64)
+ * <= 64 (x^(1/64) - 1) (ln y <= y - 1); x^(1/64) by six correctly rounded
+ * square roots; a relative margin of 2^-20 covers their rounding.  Returns
+ * min(k, sqrt(that bound)), or k when alpha_min <= 0 or x <= 1.
+ */
+double oracle_blend_k(float o, float alpha_min, float k_sigma)
+{
+    const double k = k_sigma;
+    if (!(alpha_min > 0.0f)) return k;
+    const double x = (double)o / (double)alpha_min;
+    if (!(x > 1.0)) return k;
+    double r = x;
+    for (int i = 0; i < 6; ++i) r = sqrt(r);
+    const double e2 = (128.0 * (r - 1.0)) * (1.0 + 1.0 / 1048576.0);
+    return e2 < k * k ? sqrt(e2) : k;
+}
+
 void oracle_local_box(double s1, double s2, double l1, double l2, double k, int32_t tight, double *out)
 {
     const double infl = 1.0 + 1.0 / 1024.0;
@@ -228,7 +248,7 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
                  const float *curv, const float *opac, const float *rgb,
                  const float *cam, int32_t width, int32_t height, float near_f, float k_sigma,
                  uint8_t *culled, uint32_t *depth_bits, int32_t *rect_px, int32_t *rect_tile,
-                 uint32_t *tiles, double *conic, uint8_t *conic_ok, double *frame, int32_t tight)
+                 uint32_t *tiles, double *conic, uint8_t *conic_ok, double *frame, int32_t tight, float alpha_min)
 {
     double W[9], T[3];
     for (int i = 0; i < 9; ++i) W[i] = cam[i];
@@ -279,7 +299,8 @@ void oracle_keys(int64_t n, const float *center, const float *quat, const float 
 
         /* conservative local box of the support (oracle_local_box) */
         double box[4];
-        oracle_local_box(s1, s2, l1, l2, (double)k_sigma, tight == 1, box);
+        oracle_local_box(s1, s2, l1, l2, tight == 1 ? oracle_blend_k(opac[p], alpha_min, k_sigma) : (double)k_sigma,
+                         tight == 1, box);
         const double hx = box[0], hy = box[1], zlo = box[2], zhi = box[3];
         double tb[5];
         if (tight == 2) oracle_tb_frustum(s1, s2, l1, l2, (double)k_sigma, tb);

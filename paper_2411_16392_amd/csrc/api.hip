@@ -175,6 +175,7 @@ qgs_status qgs_preprocess(const qgs_scene *scene, const qgs_camera *cam, const q
     a.cam = *cam;
     a.near_plane = opts->near_plane;
     a.k_sigma = opts->k_sigma;
+    a.alpha_min = opts->alpha_min;
     a.records = out->records;
     a.depth_key = out->depth_key;
     a.rect = out->rect;

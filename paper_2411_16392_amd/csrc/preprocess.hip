@@ -124,6 +124,24 @@ __device__ inline double chord_height(double m, double sm, double k2)
     return ((2.0 * k2) * m) / (1.0 + sqrt(1.0 + (4.0 * k2) * (r * r)));
 }
 
+// Cut-off for the bounds of a primitive that blends only where alpha =
+// min(alpha_max, o G) >= alpha_min, i.e. G >= alpha_min / o, i.e.
+// E <= 2 ln(o / alpha_min): the smaller of k and sqrt(2 ln x), x = o /
+// alpha_min, with ln x bounded from above by 64 (x^(1/64) - 1) (ln y <= y - 1
+// at y = x^(1/64); six correctly rounded square roots) and a relative margin
+// of 2^-20.  k itself when alpha_min is not positive or x <= 1.
+__device__ inline double blend_k(float op, float alpha_min, float k_sigma)
+{
+    const double k = k_sigma;
+    if (!(alpha_min > 0.0f)) return k;
+    const double x = (double)op / (double)alpha_min;
+    if (!(x > 1.0)) return k;
+    double r = x;
+    for (int i = 0; i < 6; ++i) r = sqrt(r);
+    const double e2 = (128.0 * (r - 1.0)) * (1.0 + 1.0 / 1048576.0);
+    return e2 < k * k ? sqrt(e2) : k;
+}
+
 __device__ inline void local_box(double s1, double s2, double l1, double l2, double k, bool tight, double &hx,
                                  double &hy, double &zlo, double &zhi)
 {
@@ -232,7 +250,8 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     // local box of the support (see qgs_preprocess in qgs.h)
     const double s1 = sf1, s2 = sf2, l1 = lf1, l2 = lf2;
     double hx, hy, zlo, zhi;
-    local_box(s1, s2, l1, l2, (double)a.k_sigma, a.tight != 0, hx, hy, zlo, zhi);
+    local_box(s1, s2, l1, l2, a.tight ? blend_k(op, a.alpha_min, a.k_sigma) : (double)a.k_sigma, a.tight != 0, hx, hy,
+              zlo, zhi);
 
     const double fx = a.cam.fx, fy = a.cam.fy, cxp = a.cam.cx, cyp = a.cam.cy;
     const double near_d = a.near_plane;

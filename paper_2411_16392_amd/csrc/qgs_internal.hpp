@@ -20,7 +20,7 @@ struct PreprocessArgs {
     const float *center, *quat, *scale, *curv, *opacity, *rgb;
     int64_t n;
     qgs_camera cam;
-    float near_plane, k_sigma;
+    float near_plane, k_sigma, alpha_min;
     void *records;
     uint32_t *depth_key;
     int32_t *rect;

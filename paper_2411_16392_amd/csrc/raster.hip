@@ -287,10 +287,6 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-struct PixGrad {
-    float g[NGRAD];
-};
-
 // adjoint of one blended entry; adds into gr (the primitive's record
 // gradient).  dt: gradient with respect to the hit depth t; qn: the normal
 // map's upstream gradient in the local frame, Rc^T gn; dK (GEO): with respect

@@ -221,6 +221,7 @@ hipError_t enqueue_count(qgs_server *s, Slot &sl, hipStream_t stream)
     pa.cam = r.cam;
     pa.near_plane = s->cfg.opts.near_plane;
     pa.k_sigma = s->cfg.opts.k_sigma;
+    pa.alpha_min = s->cfg.opts.alpha_min;
     pa.tight = (s->cfg.opts.flags & QGS_TIGHT_BOUND) ? 1 : 0;
     pa.records = sl.records; pa.depth_key = sl.depth_key; pa.rect = sl.rect; pa.tiles = sl.tiles;
     pa.conic = sl.conic;

@@ -10,6 +10,9 @@ the oracle for measurement only.  Pins here:
   asinh -- lies inside both boxes, for random and extreme primitives;
 * on screen, every pixel whose ray the FP64 renderer accepts lies in the tight
   rectangle and in a tile the tight key stage emits;
+* the blending cut-off the tight bounds use for faint primitives,
+  min(3, sqrt(2 ln(o / alpha_min))) bounded from above, holds every point
+  that can blend, in the local frame and on screen;
 * the paper's box misses support: the principal-axis radii of the two
   examples worked out by hand, and a nonzero screen miss rate on strongly
   curved primitives.
@@ -87,6 +90,43 @@ def test_local_boxes_contain_the_support():
     assert min(gain) < 0.2  # strongly curved primitives shrink a lot
 
 
+def test_blend_cutoff_bounds_the_blending_support():
+    """A primitive blends only where o exp(-E/2) >= alpha_min; the tight bounds
+    use k_b = min(3, sqrt(2 ln(o / alpha_min))) from above (ln by square roots)."""
+    amin = 1.0 / 255.0
+    for o in np.concatenate([np.linspace(0.004, 0.99, 200), [amin * (1 + 1e-6), 0.3529, 0.3530, 1.0]]):
+        kb = oracle.blend_k(np.float32(o), np.float32(amin))
+        x = float(np.float32(o)) / float(np.float32(amin))
+        if x <= 1.0:
+            assert kb == 3.0
+            continue
+        exact = np.sqrt(2.0 * np.log(x))
+        assert kb >= min(3.0, exact)
+        assert kb <= 3.0 and (kb == 3.0 or kb <= exact * 1.03)
+    # the local box at the blending cut-off holds every point that can blend
+    rng = np.random.Generator(np.random.PCG64(13))
+    s, l = random_prims(rng, 120)
+    for (s1, s2), (l1, l2), o in zip(s, l, rng.uniform(0.005, 0.6, len(s))):
+        kb = oracle.blend_k(np.float32(o), np.float32(amin))
+        e_max = 2.0 * np.log(float(np.float32(o)) / float(np.float32(amin)))
+        if e_max <= 0.0:
+            continue
+        kk = min(3.0, np.sqrt(e_max))
+        th = np.linspace(0.0, 2.0 * np.pi, 2048, endpoint=False)
+        c, sn = np.cos(th), np.sin(th)
+        a = l1 * c * c + l2 * sn * sn
+        sig = 1.0 / np.sqrt(c * c / (s1 * s1) + sn * sn / (s2 * s2))
+        lo, hi = np.zeros_like(th), kk * sig
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            inside = mid * g_np(2.0 * np.abs(a) * mid) <= kk * sig
+            lo = np.where(inside, mid, lo)
+            hi = np.where(inside, hi, mid)
+        x, y, z = lo * c, lo * sn, a * lo * lo
+        hx, hy, zlo, zhi = oracle.local_box(s1, s2, l1, l2, kb, True)
+        assert np.abs(x).max() <= hx and np.abs(y).max() <= hy and z.min() >= zlo and z.max() <= zhi, (o, s1, l1)
+
+
 def test_tight_box_closed_forms():
     # flat: both boxes are the k-sigma box
     for tight in (False, True):
@@ -121,6 +161,7 @@ def test_paper_tb_radii_hand_examples():
 
 
 def curved(sc, rng, lim, planar_frac=0.1):
+    """A copy with curvatures U[-lim, lim] (planar_frac exactly 0) and opacity 0.99."""
     out = scenes.Scene(*(a.copy() for a in sc.arrays()))
     l = rng.uniform(-lim, lim, (sc.n, 2)).astype(np.float32)
     l[rng.random(sc.n) < planar_frac] = 0.0
@@ -130,9 +171,9 @@ def curved(sc, rng, lim, planar_frac=0.1):
 
 
 def screen_bounds(sc, cam, n_prims):
-    """Per primitive: support pixels (accepted hits of the FP64 renderer, alone,
-    opacity 0.99 so every accepted hit blends), checked against the tight
-    rectangle and tiles; counts the support pixels outside the paper's box."""
+    """Per primitive: the pixels it blends when rendered alone by the FP64
+    renderer (with opacity 0.99 every accepted hit blends), checked against the
+    tight rectangle and tiles; counts those outside the paper's box."""
     W, H = cam.width, cam.height
     stats = dict(support=0, tb_miss=0, prims=0, prims_missed=0, tiles_default=0, tiles_tight=0, tiles_tb=0)
     for p in range(n_prims):
@@ -177,6 +218,12 @@ def test_screen_support_inside_tight_bounds_and_paper_tb_misses():
     rng = np.random.Generator(np.random.PCG64(5))
     mild = curved(cfg.scene, rng, 2.0)
     strong = curved(cfg.scene, rng, 60.0)
+    # low opacities: the pixels that blend (o G >= alpha_min) lie in the tight
+    # bounds, which shrink to the blending cut-off
+    faint = curved(cfg.scene, rng, 2.0)
+    faint.opacity = rng.uniform(0.005, 0.35, faint.n).astype(np.float32)
+    f = screen_bounds(faint, cam, 250)
+    assert f["prims"] > 100 and f["tiles_tight"] < 0.95 * f["tiles_default"], f
     a = screen_bounds(mild, cam, 250)
     b = screen_bounds(strong, cam, 250)
     assert a["prims"] > 100 and b["prims"] > 100
