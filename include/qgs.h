@@ -167,7 +167,8 @@ typedef struct qgs_prim_buf {
  *                        costs a random gather and scatter over all pairs.
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
  *  tile_order            [tiles_x * tiles_y] tiles by decreasing list length
- *                        (log2 buckets): the order in which the rasterizer's
+ *                        (exact below 2048 entries, then classes 16 entries
+ *                        wide up to 34800): the order in which the rasterizer's
  *                        workgroups take tiles, so the longest start first
  *  counters              [8] uint32: [0] number of pairs, [1] overflow flag
  *                        (1 when [0] > capacity: lists and ranges are then empty

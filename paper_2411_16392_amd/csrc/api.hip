@@ -107,11 +107,15 @@ RasterArgs raster_args(const qgs_prim_buf *prims, const qgs_tile_lists *lists, c
     return a;
 }
 
-size_t bwd_bytes(int64_t n, uint64_t capacity, uint32_t flags)
+// backward workspace: record gradients [n][16] f32; the backward's tile cost
+// and order [2][tiles] u32; deterministic mode: one 16-float partial per
+// (pair, wave of the tile)
+size_t bwd_grad_bytes(int64_t n) { return ((size_t)(n > 0 ? n : 1) * 64 + 255) & ~(size_t)255; }
+size_t bwd_order_bytes(uint64_t ntiles) { return ((size_t)(ntiles > 0 ? ntiles : 1) * 8 + 255) & ~(size_t)255; }
+
+size_t bwd_bytes(int64_t n, uint64_t capacity, uint32_t flags, uint64_t ntiles)
 {
-    size_t b = (size_t)(n > 0 ? n : 1) * 64;
-    b = (b + 255) & ~(size_t)255;
-    // deterministic mode: one 16-float partial per (pair, wave of the tile)
+    size_t b = bwd_grad_bytes(n) + bwd_order_bytes(ntiles);
     if (flags & QGS_DETERMINISTIC_BWD) b += (size_t)(capacity > 0 ? capacity : 1) * 256;
     return b;
 }
@@ -155,8 +159,9 @@ qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t capaci
                                size_t *sort_ws_bytes, size_t *bwd_ws_bytes)
 {
     if (n < 0 || n > 0x7FFFFFFFll || !cam_ok(cam) || capacity > 0xFFFFFFFFull) return QGS_ERR_INVALID_ARG;
+    const uint64_t ntiles = (uint64_t)((cam->width + 15) / 16) * (uint64_t)((cam->height + 15) / 16);
     if (sort_ws_bytes) *sort_ws_bytes = sort_workspace_layout(nullptr, n, capacity).bytes;
-    if (bwd_ws_bytes) *bwd_ws_bytes = bwd_bytes(n, capacity, flags);
+    if (bwd_ws_bytes) *bwd_ws_bytes = bwd_bytes(n, capacity, flags, ntiles);
     return QGS_OK;
 }
 
@@ -288,10 +293,13 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     if ((opts->flags & QGS_RESORT) && (!fwd->color || !fwd->depth || !fwd->normal)) return QGS_ERR_INVALID_ARG;
     if ((opts->flags & QGS_RESORT) && geo && !fwd->curvature) return QGS_ERR_INVALID_ARG;
     if ((fwd->steps == nullptr) != (fwd->step_count == nullptr)) return QGS_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags)) return QGS_ERR_WORKSPACE;
+    const uint64_t ntiles = (uint64_t)((cam->width + 15) / 16) * (uint64_t)((cam->height + 15) / 16);
+    if (!ws || ws_bytes < bwd_bytes(scene->n, lists->capacity, opts->flags, ntiles)) return QGS_ERR_WORKSPACE;
     float *grad_rec = reinterpret_cast<float *>(ws);
-    size_t off = ((size_t)(scene->n > 0 ? scene->n : 1) * 64 + 255) & ~(size_t)255;
-    float *scratch = det ? reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + off) : nullptr;
+    const size_t off = bwd_grad_bytes(scene->n);
+    uint32_t *order_ws = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ws) + off);
+    const size_t off2 = off + bwd_order_bytes(ntiles);
+    float *scratch = det ? reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + off2) : nullptr;
     hipStream_t s = (hipStream_t)stream;
     BwdIn in;
     in.T_final = fwd->T_final;
@@ -312,7 +320,7 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.step_count = fwd->step_count;
     in.flags = opts->flags;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
-                                                 grad_rec, scratch, scene->n, lists->capacity, s));
+                                                 grad_rec, scratch, order_ws, scene->n, lists->capacity, s));
     if (st != QGS_OK) return st;
     PreprocessBwdArgs b;
     b.center = scene->center;

@@ -428,32 +428,58 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt,
     if (i == n - 1 || tile[i + 1] != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
 }
 
-// Tiles in decreasing order of list length (buckets of floor(log2(len + 1)),
-// largest first; order inside a bucket is arbitrary): the rasterizer's
-// workgroups take tiles in this order so the longest lists start first.
-__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *ranges, uint32_t ntiles, uint32_t *order)
+// Tiles in decreasing order of cost: the rasterizer's workgroups take tiles in
+// this order, so that the costliest start first and the ones that start last
+// are the cheapest (longest-processing-time-first order).  The cost is cost[t]
+// or, with no cost array, the tile's list length.  Counting sort over 4096
+// cost classes: one per value below 2048, then classes 16 wide up to 34800
+// (higher costs share the top class); order inside a class is arbitrary.
+constexpr int TO_CLASSES = 4096;
+__device__ inline uint32_t cost_class(uint32_t c)
 {
-    __shared__ uint32_t cnt[32], pos[32];
-    const int tid = threadIdx.x;
-    if (tid < 32) cnt[tid] = 0;
+    uint32_t b = c < 2048u ? c : 2048u + ((c - 2048u) >> 4);
+    b = b < (uint32_t)TO_CLASSES - 1u ? b : (uint32_t)TO_CLASSES - 1u;
+    return (uint32_t)TO_CLASSES - 1u - b;  // costliest first
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles,
+                                                     uint32_t *order)
+{
+    auto tile_cost = [&](uint32_t t) { return cost ? cost[t] : ranges[2 * t + 1] - ranges[2 * t]; };
+    __shared__ uint32_t cnt[TO_CLASSES];
+    __shared__ uint32_t s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < TO_CLASSES; i += 1024) cnt[i] = 0;
     __syncthreads();
-    for (uint32_t t = tid; t < ntiles; t += blockDim.x) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        atomicAdd(&cnt[__clz((int)(len + 1u))], 1u);  // 31 - floor(log2(len + 1)): longest first
+    for (uint32_t t = tid; t < ntiles; t += blockDim.x) atomicAdd(&cnt[cost_class(tile_cost(t))], 1u);
+    __syncthreads();
+    // exclusive scan of the class counts: thread t owns classes 4t .. 4t + 3
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = cnt[4 * tid + k];
+        sum += v[k];
+    }
+    const uint32_t inc = wave_incl_scan(sum, lane);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cnt[4 * tid + k] = run;
+        run += v[k];
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int b = 0; b < 32; ++b) {
-            pos[b] = run;
-            run += cnt[b];
-        }
-    }
-    __syncthreads();
-    for (uint32_t t = tid; t < ntiles; t += blockDim.x) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        order[atomicAdd(&pos[__clz((int)(len + 1u))], 1u)] = t;
-    }
+    for (uint32_t t = tid; t < ntiles; t += blockDim.x) order[atomicAdd(&cnt[cost_class(tile_cost(t))], 1u)] = t;
+}
+
+hipError_t launch_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles, uint32_t *order,
+                             hipStream_t stream)
+{
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, ranges, cost, ntiles, order);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stream)
@@ -541,9 +567,8 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
     if (e != hipSuccess) return e;
     // the tile order is written on every path: the rasterizer reads it for
     // every workgroup, also when there are no pairs
-    if (a.tile_order)
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, (const uint32_t *)a.ranges, (uint32_t)ntiles,
-                           a.tile_order);
+    if (a.tile_order) e = launch_tile_order(a.ranges, nullptr, (uint32_t)ntiles, a.tile_order, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

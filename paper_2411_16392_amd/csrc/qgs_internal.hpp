@@ -69,6 +69,11 @@ struct SortWorkspace {
 // Layout of the bin_sort workspace inside `base` (NULL base: sizes only).
 SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity);
 
+// Tiles by decreasing cost[t] (null cost: by list length, from ranges), the
+// longest-processing-time-first order; one workgroup.
+hipError_t launch_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles, uint32_t *order,
+                             hipStream_t stream);
+
 struct BinSortArgs {
     int64_t n;
     const uint32_t *depth_key, *tiles;
@@ -129,8 +134,11 @@ struct BwdIn {
 };
 
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream);
+// order_ws: [2][tiles] u32 for the backward's own tile order (by the entries
+// the replay bitmap makes each tile visit); null: the lists' tile order.
 hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const BwdIn &in, float *grad_rec,
-                             float *pair_scratch, int64_t n_prims, uint64_t capacity, hipStream_t stream);
+                             float *pair_scratch, uint32_t *order_ws, int64_t n_prims, uint64_t capacity,
+                             hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stream);
 

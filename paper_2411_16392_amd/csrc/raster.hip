@@ -1161,13 +1161,44 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const RasterArgs &a, const RasterParams &p, const BwdIn &in, float *grad_rec,
-                             float *pair_scratch, int64_t n_prims, uint64_t capacity, hipStream_t stream)
+// Backward work of each tile: the largest number of entries one of its four
+// 8 x 8 blocks visits, i.e. the set bits of that block's replay words.
+__global__ __launch_bounds__(256) void k_bwd_cost(const uint32_t *ranges, const uint64_t *steps,
+                                                  const uint32_t *step_count, uint32_t ntiles, uint32_t *cost)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const uint32_t start = ranges[2 * t], len = ranges[2 * t + 1] - start;
+    const uint32_t nw_max = (len + 63u) >> 6;
+    uint32_t c = 0;
+    for (int w = 0; w < 4; ++w) {
+        uint32_t nw = step_count[4 * t + w];
+        nw = nw < nw_max ? nw : nw_max;
+        const uint64_t *bm = steps + replay_base(start, len, (int)t, w);
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < nw; ++k) v += (uint32_t)__popcll(bm[k]);
+        c = v > c ? v : c;
+    }
+    cost[t] = c;
+}
+
+hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, const BwdIn &in, float *grad_rec,
+                             float *pair_scratch, uint32_t *order_ws, int64_t n_prims, uint64_t capacity,
+                             hipStream_t stream)
 {
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grad_rec), 0u, (uint64_t)n_prims * 16, stream);
     if (e != hipSuccess) return e;
     if (ntiles == 0) return hipSuccess;
+    RasterArgs a = a_in;
+    if (order_ws && in.steps && !(in.flags & QGS_RESORT)) {
+        // the tiles in decreasing order of the entries they will visit
+        hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 255) / 256), dim3(256), 0, stream, a.ranges, in.steps,
+                           in.step_count, ntiles, order_ws);
+        e = launch_tile_order(a.ranges, order_ws, ntiles, order_ws + ntiles, stream);
+        if (e != hipSuccess) return e;
+        a.tile_order = order_ws + ntiles;
+    }
     const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
     const float4 *recs = reinterpret_cast<const float4 *>(a.records);
     if (in.flags & QGS_RESORT) {

@@ -85,8 +85,9 @@ def check_lists(ks, cam, st, tile_depth=False):
     order = to_np(st.tile_order).view(np.uint32)
     assert np.array_equal(np.sort(order), np.arange(len(ranges), dtype=np.uint32)), "tile order is a permutation"
     lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)[order]
-    bucket = np.floor(np.log2(lens + 1.0)).astype(np.int64)
-    assert np.all(np.diff(bucket) <= 0), "longest lists first"
+    # length classes: exact below 2048, 16 entries wide above, capped
+    cls = np.minimum(np.where(lens < 2048, lens, 2048 + (lens - 2048) // 16), 4095)
+    assert np.all(np.diff(cls) <= 0), "longest lists first"
     return npairs
 
 
