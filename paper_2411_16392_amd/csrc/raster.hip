@@ -1165,12 +1165,14 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
 }
 
 // Backward work of each tile: the largest number of entries one of its four
-// 8 x 8 blocks visits, i.e. the set bits of that block's replay words.
+// 8 x 8 blocks visits, i.e. the set bits of that block's replay words.  One
+// wave per tile, its lanes striding over each block's words.
 __global__ __launch_bounds__(256) void k_bwd_cost(const uint32_t *ranges, const uint64_t *steps,
                                                   const uint32_t *step_count, uint32_t ntiles, uint32_t *cost)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+    const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (t >= ntiles) return;  // whole wave
     const uint32_t start = ranges[2 * t], len = ranges[2 * t + 1] - start;
     const uint32_t nw_max = (len + 63u) >> 6;
     uint32_t c = 0;
@@ -1179,10 +1181,12 @@ __global__ __launch_bounds__(256) void k_bwd_cost(const uint32_t *ranges, const 
         nw = nw < nw_max ? nw : nw_max;
         const uint64_t *bm = steps + replay_base(start, len, (int)t, w);
         uint32_t v = 0;
-        for (uint32_t k = 0; k < nw; ++k) v += (uint32_t)__popcll(bm[k]);
+        for (uint32_t k = lane; k < nw; k += 64u) v += (uint32_t)__popcll(bm[k]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         c = v > c ? v : c;
     }
-    cost[t] = c;
+    if (lane == 0) cost[t] = c;
 }
 
 hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, const BwdIn &in, float *grad_rec,
@@ -1196,7 +1200,7 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
     RasterArgs a = a_in;
     if (order_ws && in.steps && !(in.flags & QGS_RESORT)) {
         // the tiles in decreasing order of the entries they will visit
-        hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 255) / 256), dim3(256), 0, stream, a.ranges, in.steps,
+        hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 3) / 4), dim3(256), 0, stream, a.ranges, in.steps,
                            in.step_count, ntiles, order_ws);
         e = launch_tile_order(a.ranges, order_ws, ntiles, order_ws + ntiles, stream);
         if (e != hipSuccess) return e;
