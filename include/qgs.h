@@ -274,8 +274,10 @@ void qgs_default_opts(qgs_render_opts *opts);
 /*
  * Host-only size query.  For n primitives, a camera and a pair capacity:
  *  sort_ws_bytes  workspace of qgs_bin_sort
- *  bwd_ws_bytes   workspace of qgs_render_bwd for `flags` (QGS_DETERMINISTIC_BWD
- *                 adds capacity * 256 bytes: one partial per pair and 8 x 8 block)
+ *  bwd_ws_bytes   workspace of qgs_render_bwd for `flags`: the record
+ *                 gradients (64 bytes per primitive) and the backward's tile
+ *                 order (8 bytes per tile of the camera); QGS_DETERMINISTIC_BWD
+ *                 adds capacity * 256 bytes: one partial per pair and 8 x 8 block
  * Any output pointer may be NULL.
  */
 qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t pair_capacity, uint32_t flags,
@@ -335,7 +337,8 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
 /*
  * Backward: adjoint of qgs_render_fwd and qgs_preprocess.  Each tile's list is
  * walked back to front from each pixel's `last` entry (only the replay bitmap's
- * entries when `fwd` carries one), recomputing transmittance by division
+ * entries when `fwd` carries one; the tiles then run in decreasing order of
+ * the entries their blocks' bitmaps hold), recomputing transmittance by division
  * (supplement, back-to-front adjoint), with per-primitive gradients reduced
  * across each 8 x 8 block's pixels in registers before one global atomic per
  * field per (block, primitive); QGS_DETERMINISTIC_BWD instead stores one
