@@ -463,6 +463,45 @@ def test_replay_bitmap_gives_identical_gradients(mode):
         assert np.array_equal(g_replay[k], g_walk[k]), k
 
 
+def test_backward_tile_order_follows_replay_visits():
+    # the backward's own tile order (kept in its workspace after the record
+    # gradients): each tile's cost is the largest number of entries one of its
+    # four 8 x 8 blocks visits, i.e. the set bits of that block's replay words,
+    # and the tiles run in decreasing cost class
+    c = cfg(1)
+    cam = c.cameras[0]
+    r = R.Renderer()
+    sc_t = R.scene_to_device(c.scene)
+    st = r.forward(sc_t, cam)
+    assert st.steps is not None
+    dL = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+          for a in scenes.upstream_grads(5, cam.height, cam.width)]
+    r.backward(sc_t, st, *dL)
+    torch.cuda.synchronize()
+    ntiles = cam.tiles_x * cam.tiles_y
+    off = (max(st.n, 1) * 64 + 255) // 256 * 256
+    ws = to_np(r._bwd_ws)[off:off + 8 * ntiles].view(np.uint32)
+    cost, order = ws[:ntiles], ws[ntiles:2 * ntiles]
+    ranges = to_np(st.ranges).view(np.uint32).reshape(-1, 2).astype(np.int64)
+    steps = to_np(st.steps).view(np.uint64)
+    nwords = to_np(st.step_count).view(np.uint32).astype(np.int64)
+    want = np.zeros(ntiles, np.int64)
+    for t in range(ntiles):
+        start, ln = ranges[t, 0], ranges[t, 1] - ranges[t, 0]
+        nw_max = (ln + 63) // 64
+        for w in range(4):
+            base = 4 * (start // 64 + t) + w * nw_max
+            nw = min(nwords[4 * t + w], nw_max)
+            bits = sum(bin(int(x)).count("1") for x in steps[base:base + nw])
+            want[t] = max(want[t], bits)
+    assert want.sum() > 0
+    assert np.array_equal(cost.astype(np.int64), want), "tile costs"
+    assert np.array_equal(np.sort(order), np.arange(ntiles, dtype=np.uint32)), "order is a permutation"
+    cw = want[order]
+    cls = np.minimum(np.where(cw < 2048, cw, 2048 + (cw - 2048) // 16), 4095)
+    assert np.all(np.diff(cls) <= 0), "costliest tiles first"
+
+
 def test_autograd_function_matches_direct_backward():
     c = cfg(0)
     cam = c.cameras[0]
