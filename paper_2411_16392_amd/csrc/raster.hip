@@ -1198,7 +1198,7 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
     if (e != hipSuccess) return e;
     if (ntiles == 0) return hipSuccess;
     RasterArgs a = a_in;
-    if (order_ws && in.steps && !(in.flags & QGS_RESORT)) {
+    if (order_ws && in.steps) {
         // the tiles in decreasing order of the entries they will visit
         hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 3) / 4), dim3(256), 0, stream, a.ranges, in.steps,
                            in.step_count, ntiles, order_ws);
