@@ -90,6 +90,26 @@ __device__ inline float wave_reduce_scatter16(const float (&v)[16])
     return d;
 }
 
+// Words 4..31 of primitive pj's record (everything past the rectangle) into
+// rw[4..31], fetched in one round of scalar loads before any is used: the
+// empty asm makes the values live in scalar registers here, so the pre-test,
+// the primitive and the colour words then need no further wait (the compiler
+// otherwise issues them as three dependent rounds, one per use).
+__device__ inline void load_record_words(const float4 *__restrict__ recs, uint32_t pj, float (&rw)[32])
+{
+    float4 rv[8];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) rv[q] = recs[(size_t)pj * 8 + q];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) {
+        __asm__ volatile("" : : "s"(rv[q].x), "s"(rv[q].y), "s"(rv[q].z), "s"(rv[q].w));
+        rw[4 * q] = rv[q].x;
+        rw[4 * q + 1] = rv[q].y;
+        rw[4 * q + 2] = rv[q].z;
+        rw[4 * q + 3] = rv[q].w;
+    }
+}
+
 __device__ inline uint32_t wave_max_u32(uint32_t v)
 {
 #pragma unroll
@@ -180,7 +200,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             m &= m - 1ull;
             ++w_rect;
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            float rw[32];
+            load_record_words(recs, pj, rw);
+            const float *w = rw;
             float dxp, dyp;
             const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
@@ -814,7 +836,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
             const int j = __builtin_ctzll(m);
             m &= m - 1ull;
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
-            const float *w = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
+            float rw[32];
+            load_record_words(recs, pj, rw);
+            const float *w = rw;
             float dxp, dyp;
             const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
