@@ -463,14 +463,16 @@ def test_replay_bitmap_gives_identical_gradients(mode):
         assert np.array_equal(g_replay[k], g_walk[k]), k
 
 
-def test_backward_tile_order_follows_replay_visits():
+@pytest.mark.parametrize("mode", ["centre depth", "full model"])
+def test_backward_tile_order_follows_replay_visits(mode):
     # the backward's own tile order (kept in its workspace after the record
     # gradients): each tile's cost is the largest number of entries one of its
     # four 8 x 8 blocks visits, i.e. the set bits of that block's replay words,
     # and the tiles run in decreasing cost class
     c = cfg(1)
     cam = c.cameras[0]
-    r = R.Renderer()
+    flags = (L.QGS_TILE_DEPTH | L.QGS_RESORT) if mode == "full model" else 0
+    r = R.Renderer(opts=R.make_opts(flags=flags))
     sc_t = R.scene_to_device(c.scene)
     st = r.forward(sc_t, cam)
     assert st.steps is not None
