@@ -31,7 +31,6 @@ constexpr int RS_ITEMS_DEPTH = (int)(DEPTH_SORT_CHUNK / RS_THREADS);
 constexpr int RS_ITEMS_TILE = (int)(TILE_SORT_CHUNK / RS_THREADS);
 static_assert(RS_ITEMS_DEPTH * RS_THREADS == (int)DEPTH_SORT_CHUNK && RS_ITEMS_TILE * RS_THREADS == (int)TILE_SORT_CHUNK,
               "radix chunks");
-constexpr int SCAN_CHUNK = 4096;
 // arrays up to this size are scanned by a single workgroup (one kernel
 // instead of three; a workgroup's sequential chunks are slow for more)
 constexpr uint64_t SCAN_SINGLE_MAX = 8192;
@@ -80,7 +79,7 @@ __device__ inline T block_excl_scan(T v, T *s_wave /* [4] */, T &total)
 }
 
 // ---------------------------------------------------------------------------
-// device-wide exclusive scan: partial sums per 4096-element chunk, then each
+// device-wide exclusive scan: partial sums per SCAN_CHUNK-element chunk, then each
 // chunk's scan plus the sum of the partials before it
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -99,7 +98,7 @@ __global__ __launch_bounds__(256) void k_scan_partials(const T *in, uint64_t n, 
 }
 
 // Each block adds the sum of the partials before it (its own short reduction:
-// there are n / 4096 partials) to the exclusive scan of its chunk; the last
+// there are n / SCAN_CHUNK partials) to the exclusive scan of its chunk; the last
 // block also writes the grand total.
 template <typename T>
 __global__ __launch_bounds__(256) void k_scan_apply(const T *in, T *out, uint64_t n, const T *part, T *grand_total)

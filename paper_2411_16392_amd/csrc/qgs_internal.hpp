@@ -54,6 +54,9 @@ hipError_t launch_preprocess_bwd(const PreprocessBwdArgs &a, hipStream_t stream)
 // 256 * ceil(m / chunk) entries (SortWorkspace::hist).
 constexpr uint64_t DEPTH_SORT_CHUNK = 1024;
 constexpr uint64_t TILE_SORT_CHUNK = 4096;
+// Elements per workgroup of the device-wide scans (count tables, offsets): a
+// scan of m elements keeps ceil(m / SCAN_CHUNK) partial sums.
+constexpr int SCAN_CHUNK = 1024;
 
 struct SortWorkspace {
     uint32_t *dkA, *dvA, *dkB, *dvB;  // depth keys / primitive ids, ping-pong [n]

@@ -41,7 +41,7 @@ size_t list_bytes(uint64_t pairs)
     const uint64_t nb = cdiv64(c, TILE_SORT_CHUNK) + 1;
     // pair_tile, pair_prim and their two sort buffers (no emission map: the
     // server runs no deterministic backward)
-    return 4 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, 4096) + 64));
+    return 4 * a256(4 * c) + a256(4 * 256 * nb) + a256(8 * (cdiv64(256 * nb, SCAN_CHUNK) + 64));
 }
 
 enum Phase { IDLE = 0, COUNTING = 1, WAITING = 2, RENDERING = 3 };
@@ -262,7 +262,7 @@ hipError_t enqueue_render(qgs_server *s, Slot &sl, hipStream_t stream)
     w.primT = (uint32_t *)take(4 * c);
     w.emit_prim = nullptr;
     w.hist = (uint32_t *)take(4 * 256 * nb);
-    w.part = (uint64_t *)take(8 * (cdiv64(256 * nb, 4096) + 64));
+    w.part = (uint64_t *)take(8 * (cdiv64(256 * nb, SCAN_CHUNK) + 64));
     BinSortArgs a = sort_args(s, sl, r.cam);
     a.pair_tile = pair_tile;
     a.pair_prim = pair_prim;
@@ -474,7 +474,9 @@ qgs_status qgs_serve_create(const qgs_scene *scene, const qgs_serve_config *cfg,
         sl.dvB = sl.dkA + 3 * n;
         if ((e = dev_alloc(s, &p, 8 * (n + 1))) != hipSuccess) break;
         sl.off = (uint64_t *)p;
-        if ((e = dev_alloc(s, &p, 8 * (cdiv64(n + 1, 4096) + cdiv64(256 * nb_n, 4096) + 64))) != hipSuccess) break;
+        if ((e = dev_alloc(s, &p, 8 * (cdiv64(n + 1, SCAN_CHUNK) + cdiv64(256 * nb_n, SCAN_CHUNK) + 64))) !=
+            hipSuccess)
+            break;
         sl.part = (uint64_t *)p;
         if ((e = dev_alloc(s, &p, 4 * 256 * nb_n)) != hipSuccess) break;
         sl.hist = (uint32_t *)p;
