@@ -268,6 +268,11 @@ const char *qgs_status_string(qgs_status status);
 /* Last HIP error code seen by this thread (0 if none). */
 int32_t qgs_last_hip_error(void);
 
+/* Build stamp: a hash of the sources and flags the library was compiled from
+   (static storage; "unstamped" when built without one).  Bindings compare it
+   with the sources they ship beside, so that a stale binary is refused. */
+const char *qgs_build_id(void);
+
 /* Fill *opts with the defaults listed in qgs_render_opts. Host only. */
 void qgs_default_opts(qgs_render_opts *opts);
 

@@ -119,6 +119,7 @@ _handle = None
 _SIGS = {
     "qgs_status_string": ([c_int32], ctypes.c_char_p),
     "qgs_last_hip_error": ([], c_int32),
+    "qgs_build_id": ([], ctypes.c_char_p),
     "qgs_default_opts": ([ctypes.POINTER(QgsRenderOpts)], None),
     "qgs_workspace_query": ([c_int64, ctypes.POINTER(QgsCamera), c_uint64, c_uint32,
                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], c_int32),
@@ -145,8 +146,21 @@ _SIGS = {
 }
 
 
+def verify_build(handle, expected: str | None = None) -> str:
+    """Raises unless the library's build stamp equals the hash of the sources
+    beside it (or `expected`); returns the stamp."""
+    from paper_2411_16392_amd import build as _build
+    want = expected if expected is not None else _build.source_hash()
+    got = handle.qgs_build_id().decode()
+    if got != want:
+        raise RuntimeError(f"{LIB_PATH} was built from other sources (stamp {got[:16]}, sources {want[:16]}): "
+                           "rebuild it with `python -m paper_2411_16392_amd.build`")
+    return got
+
+
 def lib():
-    """The loaded libqgs.so; raises if it has not been built."""
+    """The loaded libqgs.so; raises if it has not been built or was built from
+    other sources than the ones beside it."""
     global _handle
     if _handle is None:
         if not os.path.exists(LIB_PATH):
@@ -156,6 +170,7 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = res
+        verify_build(L)
         _handle = L
     return _handle
 

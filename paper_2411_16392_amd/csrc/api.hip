@@ -141,6 +141,12 @@ const char *qgs_status_string(qgs_status s)
 
 int32_t qgs_last_hip_error(void) { return g_last_hip; }
 
+#ifndef QGS_BUILD_ID
+#define QGS_BUILD_ID "unstamped"
+#endif
+
+const char *qgs_build_id(void) { return QGS_BUILD_ID; }
+
 void qgs_default_opts(qgs_render_opts *o)
 {
     if (!o) return;

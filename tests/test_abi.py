@@ -141,3 +141,41 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_library_stamp_matches_its_sources():
+    # the binding loaded the library, so its stamp is the hash of the sources
+    from paper_2411_16392_amd import build as B
+    lib = L.lib()
+    assert L.verify_build(lib) == B.source_hash()
+    assert len(B.source_hash()) == 64
+
+
+def test_stale_library_is_refused():
+    # a library stamped from other sources is refused with a clear message
+    lib = L.lib()
+    with pytest.raises(RuntimeError, match="built from other sources"):
+        L.verify_build(lib, expected="0" * 64)
+
+
+def test_source_hash_follows_every_source(tmp_path, monkeypatch):
+    # changing any stamped file changes the hash
+    from paper_2411_16392_amd import build as B
+    files = B.stamped_files()
+    assert any(f.endswith("qgs.h") for f in files) and any(f.endswith(".hip") for f in files)
+    copies = []
+    for f in files:
+        dst = tmp_path / os.path.basename(f)
+        dst.write_bytes(open(f, "rb").read())
+        copies.append(str(dst))
+    monkeypatch.setattr(B, "stamped_files", lambda: copies)
+    monkeypatch.setattr(B, "ROOT", str(tmp_path))
+    h0 = B.source_hash()
+    with open(copies[0], "ab") as fh:
+        fh.write(b"\n// edit\n")
+    assert B.source_hash() != h0
+
+
+def test_device_code_has_no_packed_fp32_arithmetic():
+    from paper_2411_16392_amd import build as B
+    assert B.check_no_packed_fp32(L.LIB_PATH) > 10_000
