@@ -365,6 +365,28 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
                           const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
                           qgs_stream_t stream);
 
+/*
+ * Backward without a caller workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * qgs_render_bwd; the workspace is instead a static device array of
+ * QGS_BWD_STATIC_BYTES that the library holds on each device it runs on until
+ * the process ends.  Allocates nothing.
+ * Limit: bwd_ws_bytes of qgs_workspace_query for (n, camera, capacity, flags)
+ * must not exceed QGS_BWD_STATIC_BYTES (64 MiB: about 1M primitives at 1080p
+ * without QGS_DETERMINISTIC_BWD, whose pair partials add 256 bytes per pair of
+ * capacity); larger calls return QGS_ERR_WORKSPACE and launch nothing.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the backward clears what it accumulates into): calls that
+ * overlap on one device, on different streams or from different threads, race
+ * and must be serialised by the caller.
+ * Errors: QGS_ERR_INVALID_ARG, QGS_ERR_WORKSPACE, QGS_ERR_HIP.
+ */
+#define QGS_BWD_STATIC_BYTES ((size_t)64 << 20)
+qgs_status qgs_render_bwd_static(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
+                                 const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
+                                 const qgs_image_grads *dL, qgs_scene_grads *out, qgs_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of novel-view render requests               */
 /* ------------------------------------------------------------------------ */

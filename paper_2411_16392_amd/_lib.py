@@ -31,6 +31,7 @@ QGS_COUNT_EVALS = 4
 QGS_TILE_DEPTH = 8
 QGS_RESORT = 16
 QGS_TIGHT_BOUND = 32
+QGS_BWD_STATIC_BYTES = 64 << 20
 
 
 class QgsScene(ctypes.Structure):
@@ -134,6 +135,9 @@ _SIGS = {
                         ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts), ctypes.POINTER(QgsImages),
                         ctypes.POINTER(QgsImageGrads), ctypes.POINTER(QgsSceneGrads), c_void_p, ctypes.c_size_t,
                         c_void_p], c_int32),
+    "qgs_render_bwd_static": ([ctypes.POINTER(QgsScene), ctypes.POINTER(QgsPrimBuf), ctypes.POINTER(QgsTileLists),
+                               ctypes.POINTER(QgsCamera), ctypes.POINTER(QgsRenderOpts), ctypes.POINTER(QgsImages),
+                               ctypes.POINTER(QgsImageGrads), ctypes.POINTER(QgsSceneGrads), c_void_p], c_int32),
     "qgs_serve_create": ([ctypes.POINTER(QgsScene), ctypes.POINTER(QgsServeConfig), ctypes.POINTER(c_void_p)],
                          c_int32),
     "qgs_serve_submit": ([c_void_p, ctypes.POINTER(QgsCamera), c_void_p, ctypes.POINTER(c_uint64)], c_int32),
@@ -225,6 +229,14 @@ def qgs_render_bwd(scene: QgsScene, prims: QgsPrimBuf, lists: QgsTileLists, cam:
     _check(lib().qgs_render_bwd(ctypes.byref(scene), ctypes.byref(prims), ctypes.byref(lists), ctypes.byref(cam),
                                 ctypes.byref(opts), ctypes.byref(fwd), ctypes.byref(dL), ctypes.byref(out), ws,
                                 ws_bytes, stream), "qgs_render_bwd")
+
+
+def qgs_render_bwd_static(scene: QgsScene, prims: QgsPrimBuf, lists: QgsTileLists, cam: QgsCamera,
+                          opts: QgsRenderOpts, fwd: QgsImages, dL: QgsImageGrads, out: QgsSceneGrads, stream=None):
+    """qgs_render_bwd with the library's static per-device workspace (no allocation)."""
+    _check(lib().qgs_render_bwd_static(ctypes.byref(scene), ctypes.byref(prims), ctypes.byref(lists),
+                                       ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(fwd), ctypes.byref(dL),
+                                       ctypes.byref(out), stream), "qgs_render_bwd_static")
 
 
 def qgs_serve_create(scene: QgsScene, cfg: QgsServeConfig) -> int:

@@ -4,6 +4,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "qgs.h"
 #include "qgs_internal.hpp"
 
@@ -279,10 +281,14 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
                                         (hipStream_t)stream));
 }
 
-qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
-                          const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
-                          const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
-                          qgs_stream_t stream)
+}  // extern "C"
+
+namespace {
+
+qgs_status render_bwd_impl(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
+                           const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
+                           const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
+                           qgs_stream_t stream)
 {
     if (!scene_ok(scene) || !prims || !prims_ok(prims, scene->n) || !lists_ok(lists) || !cam_ok(cam) ||
         !opts_ok(opts) || !fwd || !fwd->T_final || !fwd->last || !dL || !out)
@@ -305,7 +311,7 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     const size_t off = bwd_grad_bytes(scene->n);
     uint32_t *order_ws = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ws) + off);
     const size_t off2 = off + bwd_order_bytes(ntiles);
-    float *scratch = det ? reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + off2) : nullptr;
+    float *pair_partials = det ? reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + off2) : nullptr;
     hipStream_t s = (hipStream_t)stream;
     BwdIn in;
     in.T_final = fwd->T_final;
@@ -326,7 +332,7 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     in.step_count = fwd->step_count;
     in.flags = opts->flags;
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
-                                                 grad_rec, scratch, order_ws, scene->n, lists->capacity, s));
+                                                 grad_rec, pair_partials, order_ws, scene->n, lists->capacity, s));
     if (st != QGS_OK) return st;
     PreprocessBwdArgs b;
     b.center = scene->center;
@@ -341,6 +347,58 @@ qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, con
     b.out = *out;
     b.accumulate = (opts->flags & QGS_ACCUMULATE_GRADS) ? 1 : 0;
     return hip_status(launch_preprocess_bwd(b, s));
+}
+
+// Backward workspace of qgs_render_bwd_static: one copy per device, held until
+// the process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[QGS_BWD_STATIC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+qgs_status static_scratch(void **out)
+{
+    int dev = -1;
+    qgs_status st = hip_status(hipGetDevice(&dev));
+    if (st != QGS_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) return QGS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (st != QGS_OK) return st;
+        if (!p) return QGS_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qgs_status qgs_render_bwd(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
+                          const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
+                          const qgs_image_grads *dL, qgs_scene_grads *out, void *ws, size_t ws_bytes,
+                          qgs_stream_t stream)
+{
+    return render_bwd_impl(scene, prims, lists, cam, opts, fwd, dL, out, ws, ws_bytes, stream);
+}
+
+qgs_status qgs_render_bwd_static(const qgs_scene *scene, const qgs_prim_buf *prims, const qgs_tile_lists *lists,
+                                 const qgs_camera *cam, const qgs_render_opts *opts, const qgs_images *fwd,
+                                 const qgs_image_grads *dL, qgs_scene_grads *out, qgs_stream_t stream)
+{
+    if (!scene_ok(scene) || !lists_ok(lists) || !cam_ok(cam) || !opts_ok(opts)) return QGS_ERR_INVALID_ARG;
+    const uint64_t ntiles = (uint64_t)((cam->width + 15) / 16) * (uint64_t)((cam->height + 15) / 16);
+    if (bwd_bytes(scene->n, lists->capacity, opts->flags, ntiles) > QGS_BWD_STATIC_BYTES) return QGS_ERR_WORKSPACE;
+    void *ws = nullptr;
+    const qgs_status st = static_scratch(&ws);
+    if (st != QGS_OK) return st;
+    return render_bwd_impl(scene, prims, lists, cam, opts, fwd, dL, out, ws, QGS_BWD_STATIC_BYTES, stream);
 }
 
 }  // extern "C"
