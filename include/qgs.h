@@ -88,7 +88,8 @@ typedef struct qgs_render_opts {
     float alpha_min;  /* 1/255: hits with smaller alpha are skipped */
     float alpha_max;  /* 0.99: alpha = min(alpha_max, opacity * G) */
     float T_eps;      /* 1e-4: a pixel stops before blending a hit that would take T below it */
-    float A_eps;      /* 1e-6: |A| below it (unit ray) takes the tangent-plane root -C/B (supplement) */
+    float A_eps;      /* 1e-6: |A| below it (unit ray): nearly flat case (supplement), only the root
+                         that tends to the tangent-plane intersection -C/B as A -> 0 is a candidate */
     float bg[3];      /* background colour, added with the final transmittance */
     int32_t tile;     /* must be 16 (16 x 16 tiles) */
     uint32_t flags;   /* QGS_* flags below; default QGS_TIGHT_BOUND */
@@ -128,7 +129,8 @@ typedef struct qgs_render_opts {
  *              of the enclosing ellipsoid (below) in pixels relative to the
  *              projected centre, f = a dx^2 + b dx dy + c dy^2 + d dx + e dy - 1,
  *              [16..24] camera-from-local rotation row-major, [25..27] rgb,
- *              [31] unused.
+ *              [31] zl: the centre's camera depth is Zc + zl, Zc its FP32
+ *              rounding; u_c, v_c are projected at depth Zc.
  *  conic       [n][8] FP64: the image of an ellipsoid enclosing the support
  *              (c00, c01, c11, c02, c12, c22 in normalised camera coordinates),
  *              [6] 1 when it bounds the support on screen (ellipsoid in front of

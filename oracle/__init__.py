@@ -26,10 +26,15 @@ DEFAULT_OPTS = dict(near=0.2, k_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99
                     T_eps=1e-4, A_eps=1e-6, bg=(0.0, 0.0, 0.0), resort=0, tile_depth=False)
 
 # Margin scales for the discrete decisions: a pixel whose relative distance to a
-# decision boundary is below its scale is reported with margin < 1.
+# decision boundary is below its scale is reported with margin < 1.  Dcond is
+# the conditioning of an accepted root's derivative (D relative to B^2 + 4|AC|),
+# which matters for gradients only.
 DEFAULT_DELTA = dict(A=1e-3, D=1e-6, near=1e-5, E=1e-5, alpha_min=1e-4, T=1e-4,
-                     normal=1e-4, clamp=1e-4, median=1e-5, sort=3e-6)
-_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median", "sort"]
+                     normal=1e-4, clamp=1e-4, median=1e-5, sort=3e-6, Dcond=1e-3)
+_DELTA_ORDER = ["A", "D", "near", "E", "alpha_min", "T", "normal", "clamp", "median", "sort", "Dcond"]
+KINDS = _DELTA_ORDER
+# longest recorded decision path per result of alternatives()
+PATH_MAX = 24
 
 
 def build() -> str:
@@ -59,8 +64,13 @@ def _lib():
         L.oracle_render.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                     i32, i32, i32, i32, i32,
                                     P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
-                                    P, i32, P]
+                                    P, i32, P,
+                                    i32, i64, P, P, P, P, P, i32]
         L.oracle_render.restype = i64
+        L.oracle_render_alts.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
+                                         i32, i32, i32, i32, i32, P, i32, i32,
+                                         i64, P, i32, P, P, P, P, P]
+        L.oracle_render_alts.restype = i64
         L.oracle_gfun.argtypes = [f64]
         L.oracle_gfun.restype = f64
         L.oracle_gprime.argtypes = [f64]
@@ -200,26 +210,12 @@ def bin_sort(k, cam, with_seq=False, tile_depth=False):
     return keys_out[:total], prims[:total], ranges
 
 
-def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=None,
-           key_stage=None, delta=None, cam_vec64=None):
-    """FP64 render of a pixel window (x0, y0, w, h) (default: the full view).
-
-    params64: optional tuple of FP64 parameter arrays overriding the scene's
-    (used for finite differences; order and culling still come from the key
-    stage of the FP32 scene).  cam_vec64: optional FP64 camera vector
-    {R[9], t[3], fx, fy, cx, cy} overriding the FP32 one.  dL: optional (dcolor[3,H,W], ddepth[H,W],
-    dnormal[3,H,W]) or (..., dcurvature[H,W], dmedian[H,W], ddistortion[H,W]) over the full view;
-    runs the backward.
-    Returns a dict of window-sized FP64 maps (colour, depth, normal, curvature, median depth,
-    depth distortion, final transmittance, blend count, decision margin) and, with dL,
-    parameter gradients.
-    """
+def _render_inputs(scene, cam, opts, window, params64, key_stage, delta, cam_vec64):
     o = opts_array(opts)
     dv = delta_array(delta)
     if key_stage is None:
         key_stage = keys(scene, cam, opts)
     x0, y0, w, h = window if window is not None else (0, 0, cam.width, cam.height)
-    n = scene.n
     prm = params64 if params64 is not None else scene.arrays()
     arrs = [_f64(a) for a in prm[:6]]
     # SH colour: params64 may carry the coefficients as a seventh array
@@ -227,8 +223,42 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     sh64 = _f64(sh) if sh is not None else None
     sh_deg = -1 if sh is None else int(round(np.sqrt(np.asarray(sh).shape[1]))) - 1
     camv = cam_array(cam, np.float64) if cam_vec64 is None else _f64(cam_vec64)
+    o_d = dict(DEFAULT_OPTS)
+    o_d.update(opts or {})
+    keycam = _f64(key_stage["cam"].astype(np.float64))
+    fr = _ptr(key_stage["frame"]) if o_d["tile_depth"] else None
+    head = [scene.n, *[_ptr(a) for a in arrs], _ptr(key_stage["culled"]), _ptr(key_stage["depth_bits"]),
+            fr, _ptr(keycam), _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv), x0, y0, w, h]
+    # keep the arrays the pointers refer to alive for the call
+    keep = (arrs, sh64, camv, keycam, o, dv, key_stage)
+    return head, (x0, y0, w, h), sh, sh64, sh_deg, keep
+
+
+def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=None,
+           key_stage=None, delta=None, cam_vec64=None, branch_median=False, forced=None, grad_skip=False):
+    """FP64 render of a pixel window (x0, y0, w, h) (default: the full view).
+
+    params64: optional tuple of FP64 parameter arrays overriding the scene's
+    (used for finite differences; order and culling still come from the key
+    stage of the FP32 scene).  cam_vec64: optional FP64 camera vector
+    {R[9], t[3], fx, fy, cx, cy} overriding the FP32 one.  dL: optional (dcolor[3,H,W], ddepth[H,W],
+    dnormal[3,H,W]) or (..., dcurvature[H,W], dmedian[H,W], ddistortion[H,W]) over the full view;
+    runs the backward.  branch_median: the median depth's decisions count in
+    the margin (and branch).  forced: optional (pixels, paths, lengths) -- row-major window pixel
+    indices, their decision paths [k, PATH_MAX] and path lengths, as
+    alternatives() returns them -- whose near-tied decisions take those outcomes.
+    grad_skip: pixels whose gradient margin is below 1 (an ill-conditioned or
+    ambiguous derivative) contribute no gradient.
+    Returns a dict of window-sized FP64 maps (colour, depth, normal, curvature, median depth,
+    depth distortion, final transmittance, blend count, decision margin, gradient margin,
+    near-tie kinds as bits of KINDS) and, with dL, parameter gradients.
+    """
+    head, (x0, y0, w, h), sh, sh64, sh_deg, keep = _render_inputs(scene, cam, opts, window, params64, key_stage,
+                                                                  delta, cam_vec64)
+    n = scene.n
     color = np.zeros((3, h, w)); depth = np.zeros((h, w)); normal = np.zeros((3, h, w))
     T = np.zeros((h, w)); nb = np.zeros((h, w), np.int32); margin = np.zeros((h, w))
+    gmargin = np.zeros((h, w)); kinds = np.zeros((h, w), np.uint16)
     curvature = np.zeros((h, w)); median = np.zeros((h, w)); dist = np.zeros((h, w))
     if nthreads is None:
         nthreads = os.cpu_count() or 1
@@ -246,25 +276,62 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
             grads["sh"] = np.zeros(np.asarray(sh).shape)
         gp = ([_ptr(dc), _ptr(dd), _ptr(dn)] + [_ptr(m) if m is not None else None for m in extra] +
               [_ptr(grads[k]) for k in ("center", "quat", "scale", "curv", "opacity", "rgb")])
-    o_d = dict(DEFAULT_OPTS)
-    o_d.update(opts or {})
-    keycam = _f64(key_stage["cam"].astype(np.float64))
-    fr = _ptr(key_stage["frame"]) if o_d["tile_depth"] else None
-    ev = _lib().oracle_render(n, *[_ptr(a) for a in arrs], _ptr(key_stage["culled"]), _ptr(key_stage["depth_bits"]),
-                              fr, _ptr(keycam),
-                              _ptr(camv), cam.width, cam.height, _ptr(o), _ptr(dv),
-                              x0, y0, w, h, int(nthreads),
+    if forced is not None and len(forced[0]) > 0:
+        fpix = np.ascontiguousarray(forced[0], np.int32)
+        fpath = np.ascontiguousarray(forced[1], np.uint8).reshape(len(fpix), PATH_MAX)
+        flen = np.ascontiguousarray(forced[2], np.int32)
+        fargs = [len(fpix), _ptr(fpix), _ptr(fpath), _ptr(flen)]
+    else:
+        fargs = [0, None, None, None]
+    ev = _lib().oracle_render(*head, int(nthreads),
                               _ptr(color), _ptr(depth), _ptr(normal), _ptr(T), _ptr(nb), _ptr(margin),
                               _ptr(curvature), _ptr(median), _ptr(dist), *gp,
                               _ptr(sh64) if sh64 is not None else None, sh_deg,
-                              _ptr(grads["sh"]) if (grads is not None and sh is not None) else None)
+                              _ptr(grads["sh"]) if (grads is not None and sh is not None) else None,
+                              int(bool(branch_median)), *fargs, _ptr(gmargin), _ptr(kinds), int(bool(grad_skip)))
+    del keep
     if ev < 0:
         raise ValueError("bad window")
     out = dict(color=color, depth=depth, normal=normal, curvature=curvature, median_depth=median,
-               distortion=dist, T_final=T, n_blend=nb, margin=margin, evals=int(ev))
+               distortion=dist, T_final=T, n_blend=nb, margin=margin, gmargin=gmargin, kinds=kinds,
+               evals=int(ev))
     if grads is not None:
         out["grads"] = grads
     return out
+
+
+# channel order of the results of alternatives()
+ALT_CHANNELS = ("color0", "color1", "color2", "depth", "normal0", "normal1", "normal2", "curvature",
+                "median_depth", "distortion", "T_final")
+
+
+def alternatives(scene, cam, pixels, opts=None, window=None, nthreads=None, key_stage=None, delta=None,
+                 branch_median=False, max_leaves=256):
+    """Every result the window pixels `pixels` (row-major indices in the window)
+    may take when their near-tied decisions go either way (reading R19: FP32 and
+    FP64 may decide differently there, and either outcome is correct).
+    Returns dict: n[k] results per pixel, overflow[k] (the enumeration was cut
+    short), vals[k, max_leaves, 11] (ALT_CHANNELS), paths[k, max_leaves,
+    PATH_MAX] and plen[k, max_leaves] (the decision path of each result, for
+    render(forced=...)).  Result 0 is the one render() gives."""
+    head, _, sh, sh64, sh_deg, keep = _render_inputs(scene, cam, opts, window, None, key_stage, delta, None)
+    pix = np.ascontiguousarray(pixels, np.int32).reshape(-1)
+    k = len(pix)
+    nl = np.zeros(k, np.int32)
+    ovf = np.zeros(k, np.uint8)
+    vals = np.zeros((k, max_leaves, len(ALT_CHANNELS)))
+    paths = np.zeros((k, max_leaves, PATH_MAX), np.uint8)
+    plen = np.zeros((k, max_leaves), np.int32)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    if k > 0:
+        ev = _lib().oracle_render_alts(*head, int(nthreads), _ptr(sh64) if sh64 is not None else None, sh_deg,
+                                       int(bool(branch_median)), k, _ptr(pix), int(max_leaves), _ptr(nl), _ptr(ovf),
+                                       _ptr(vals), _ptr(paths), _ptr(plen))
+        if ev < 0:
+            raise ValueError("bad window or pixel index")
+    del keep
+    return dict(n=nl, overflow=ovf, vals=vals, paths=paths, plen=plen)
 
 
 def sh_basis(deg, d):

@@ -30,7 +30,8 @@
  *                      (explicit form, Sec. 3.2; lambda_i = sign(s_i) s_3 / s_i^2)
  *   ray                phat = ohat + t dhat, |dhat| = 1  (supplement, ray-splat intersection)
  *   quadratic          A t^2 + B t + C = 0              (supplement, intersection equation)
- *   small |A|          t = -C/B (tangent-plane intersection, |A| < 1e-6)
+ *   small |A|          |A| < 1e-6: the root that diverges as A -> 0 is dropped; the
+ *                      other tends to the tangent-plane intersection t = -C/B
  *   arc length         l = rho g(u), u = 2|a| rho, g(u) = (asinh u + u sqrt(1+u^2)) / (2u)
  *                      (geodesic equation, Sec. 3.2, and its derivation in the supplement)
  *   density            G = exp(-l^2 / (2 sigma(theta)^2)), and l^2/sigma^2 = g^2 Q with
@@ -570,9 +571,15 @@ double oracle_gfun(double u);
 
 /* options: near, k_sigma, alpha_min, alpha_max, T_eps, A_eps, bg[3] */
 enum { O_NEAR = 0, O_K, O_AMIN, O_AMAX, O_TEPS, O_AEPS, O_BG, O_RESORT = O_BG + 3, O_NOPTS };
-/* margin scales: |A| vs A_eps, D vs 0, near test, E vs k^2, alpha_min, T_eps,
-   normal facing, alpha clamp */
-enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_MED, M_SORT, M_COUNT };
+/* Discrete decisions of the per-pixel sequence, each with a margin scale in
+   delta[]: |A| vs A_eps, the sign of D, the near test, E vs k^2, alpha vs
+   alpha_min, T' vs T_eps, the normal's facing, the alpha clamp, the median's
+   choices, the resort buffer's choice of the nearest.  M_DCOND is no decision
+   but the conditioning of an accepted root's derivative, 1 / (2 A t + B) =
+   1 / sqrt(D): the ratio of D to the change rounding its terms makes in it
+   (ray_hit), relative to its scale (FP32 carries the derivative with a
+   relative error of about 1e-7 / that ratio). */
+enum { M_A = 0, M_D, M_NEAR, M_E, M_AMIN, M_T, M_N, M_CLAMP, M_MED, M_SORT, M_DCOND, M_COUNT };
 
 /* per-pixel channels: colour[3], depth, normal[3], curvature, median depth,
    depth distortion */
@@ -726,14 +733,63 @@ double oracle_arc_length(double a, double rho)
 
 typedef struct {
     int ok;
-    int linear;     /* 1: small-|A| branch t = -C/B */
+    int linear;     /* 1: |A| < A_eps, the diverging root dropped */
     double d[3];    /* dhat */
-    double A, B, F1;/* F1 = dF/dt at the root (quadratic) or B (linear) */
+    double A, B, F1;/* F1 = dF/dt = 2 A t + B at the root */
     double t, x, y, Q, rho, h, u, g, E;
-    double margin;
 } ohit;
 
+/*
+ * Near-ties of the discrete decisions.  FP32 and FP64 may decide differently
+ * where a quantity lies within its margin scale of a decision boundary, so
+ * both outcomes are correct results there.  Every decision records its scaled
+ * margin (distance to the boundary over the scale) per kind.  A decision of a
+ * kind in `branch` whose margin is below 1 is a branch point: the first `len`
+ * branch points met take the outcome `path` gives (1 = the other side of the
+ * boundary), later ones their own side.  Enumerating paths gives every result
+ * a correct implementation of the same arithmetic may produce.
+ */
+#define OPATH_MAX 24
+typedef struct {
+    unsigned branch;        /* kinds (bit k = kind k) that branch */
+    const uint8_t *path;
+    int len;
+    int seen;               /* branch points met so far */
+    double kmin[M_COUNT];   /* smallest scaled margin per kind */
+} octl;
+
+static void ctl_init(octl *c, unsigned branch, const uint8_t *path, int len)
+{
+    c->branch = branch;
+    c->path = path;
+    c->len = len;
+    c->seen = 0;
+    for (int k = 0; k < M_COUNT; ++k) c->kmin[k] = INFINITY;
+}
+
+/* record a decision's margin m (already scaled); 1 if it takes the other side */
+static int ctl_flip(octl *c, double m, int kind)
+{
+    if (m < c->kmin[kind]) c->kmin[kind] = m;
+    if (!((c->branch >> kind) & 1u) || !(m < 1.0)) return 0;
+    const int j = c->seen++;
+    return j < c->len && j < OPATH_MAX && c->path[j] != 0;
+}
+
+static double ctl_margin(const octl *c, unsigned kinds)
+{
+    double m = INFINITY;
+    for (int k = 0; k < M_COUNT; ++k)
+        if (((kinds >> k) & 1u) && c->kmin[k] < m) m = c->kmin[k];
+    return m;
+}
+
 static inline double mscale(double v, const double *delta, int k) { return v / delta[k]; }
+
+/* kinds whose near-ties leave the forward (nearly) unchanged but not its
+   derivative: the alpha clamp, the small-|A| branch, and an accepted root's
+   conditioning */
+#define GRAD_KINDS ((1u << M_CLAMP) | (1u << M_DCOND) | (1u << M_A))
 
 /* l^2 / sigma^2 at ray parameter t (used only to decide which margins matter) */
 static double support_E(const oprim *P, double t, const double dcam[3])
@@ -750,7 +806,8 @@ static double support_E(const oprim *P, double t, const double dcam[3])
 }
 
 /* ray-splat intersection with root selection (Sec. 3.2.1 and supplement) */
-static void ray_hit(const oprim *P, const double dcam[3], const double *opts, const double *delta, ohit *H)
+static void ray_hit(const oprim *P, const double dcam[3], const double *opts, const double *delta, octl *ctl,
+                    ohit *H)
 {
     double *d = H->d;
     for (int j = 0; j < 3; ++j) d[j] = P->Rc[j] * dcam[0] + P->Rc[3 + j] * dcam[1] + P->Rc[6 + j] * dcam[2];
@@ -760,43 +817,73 @@ static void ray_hit(const oprim *P, const double dcam[3], const double *opts, co
     const double C = P->C;
     const double near_ = opts[O_NEAR], k2 = opts[O_K] * opts[O_K], Aeps = opts[O_AEPS];
     H->A = A; H->B = B; H->ok = 0;
-    double margin = INFINITY, m;
-    m = mscale(fabs(fabs(A) - Aeps) / Aeps, delta, M_A);
-    if (m < margin) margin = m;
 
+    /* Roots in the cancellation-free form (Press et al., Numerical Recipes,
+       5.6): q = -(B + sgn(B) sqrt(D)) / 2, roots q / A and C / q.  As A -> 0
+       the root q / A runs off to infinity while C / q tends to the
+       tangent-plane intersection -C / B (exactly that at A = 0).  Reading of
+       the supplement's small-|A| case: for |A| < A_eps the diverging root is
+       dropped and C / q is the one candidate. */
+    const double D = B * B - 4.0 * A * C;
+    /* D relative to its sensitivity to rounding in the quadratic re-centred
+       where the ray reaches the centre's depth, t = t0 + s (D does not change
+       under the shift): the form a renderer working relative to the
+       primitive's centre evaluates.  The camera-origin coefficients carry the
+       whole distance to the camera and would overstate the cancellation by
+       |ohat| / sigma and more.  Rounding moves D = Bs^2 - 4 A Cs by about
+       eps (2 |Bs| SB + 4 |Cs| SA + 4 |A| SC), where SA, SB, SC bound the
+       rounding of A, Bs and Cs in units of eps: each local component of the
+       ray and of the offset p0 carries an error of about eps times the whole
+       vector's length (it comes out of a rotation), even when the component
+       itself is small, as for a ray grazing the surface. */
+    const double t0 = P->cc[2] / dcam[2];
+    const double p0x = o[0] + t0 * d[0], p0y = o[1] + t0 * d[1], p0z = o[2] + t0 * d[2];
+    const double Bs = 2.0 * (l1 * p0x * d[0] + l2 * p0y * d[1]) - d[2];
+    const double Cs = l1 * p0x * p0x + l2 * p0y * p0y - p0z;
+    const double pn = sqrt(p0x * p0x + p0y * p0y + p0z * p0z);  /* |d| = 1 */
+    const double SA = 2.0 * (fabs(l1 * d[0]) + fabs(l2 * d[1]));
+    const double SB = 2.0 * (fabs(l1) * (fabs(p0x) + fabs(d[0]) * pn) + fabs(l2) * (fabs(p0y) + fabs(d[1]) * pn)) + 1.0;
+    const double SC = 2.0 * (fabs(l1 * p0x) + fabs(l2 * p0y)) * pn + pn;
+    const double Drel =
+        fabs(Bs * Bs - 4.0 * A * Cs) / (2.0 * fabs(Bs) * SB + 4.0 * fabs(Cs) * SA + 4.0 * fabs(A) * SC);
+    /* the sign of D only matters where the double root t* = -B/(2A) would be
+       inside (or at the edge of) the support */
+    int hit = D >= 0.0;
+    if (A != 0.0 && support_E(P, -B / (2.0 * A), dcam) <= 1.01 * k2)
+        hit ^= ctl_flip(ctl, mscale(Drel, delta, M_D), M_D);
     double cand[2];
     int nc = 0;
-    if (fabs(A) < Aeps) {
-        H->linear = 1;
-        if (B != 0.0) cand[nc++] = -C / B;
-    } else {
-        H->linear = 0;
-        const double D = B * B - 4.0 * A * C;
-        /* the sign of D only matters where the double root t* = -B/(2A)
-           would be inside (or at the edge of) the support */
-        if (support_E(P, -B / (2.0 * A), dcam) <= 1.01 * k2) {
-            m = mscale(fabs(D) / (B * B + 4.0 * fabs(A * C)), delta, M_D);
-            if (m < margin) margin = m;
-        }
-        if (D >= 0.0) {
-            const double sq = sqrt(D);
-            const double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
-            double r1, r2;
-            if (qq == 0.0) { r1 = r2 = 0.0; }
-            else { r1 = qq / A; r2 = C / qq; }
-            cand[0] = r1 < r2 ? r1 : r2;
-            cand[1] = r1 < r2 ? r2 : r1;
-            nc = 2;
+    H->linear = fabs(A) < Aeps;
+    if (hit) {
+        /* a hit taken on the other side of D = 0 is the double root */
+        const double sq = D > 0.0 ? sqrt(D) : 0.0;
+        const double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+        if (qq != 0.0) {
+            const double rfin = C / qq;
+            cand[nc++] = rfin;
+            if (A != 0.0) {
+                /* dropping the diverging root only matters where it could be
+                   accepted */
+                const double rdiv = qq / A;
+                int keep = !H->linear;
+                if (support_E(P, rdiv, dcam) <= 1.01 * k2)
+                    keep ^= ctl_flip(ctl, mscale(fabs(fabs(A) - Aeps) / Aeps, delta, M_A), M_A);
+                if (keep) {
+                    cand[nc++] = rdiv;
+                    if (rdiv < rfin) { cand[0] = rdiv; cand[1] = rfin; }
+                }
+            }
+        } else if (A != 0.0) {
+            cand[nc++] = 0.0;  /* B = D = 0: the double root at t = 0 */
         }
     }
     for (int ci = 0; ci < nc; ++ci) {
         const double t = cand[ci];
         const double zc = t * dcam[2];
-        if (support_E(P, t, dcam) <= 1.01 * k2) {
-            m = mscale(fabs(zc - near_) / near_, delta, M_NEAR);
-            if (m < margin) margin = m;
-        }
-        if (!(zc > near_)) continue;
+        int front = zc > near_;
+        if (support_E(P, t, dcam) <= 1.01 * k2)
+            front ^= ctl_flip(ctl, mscale(fabs(zc - near_) / near_, delta, M_NEAR), M_NEAR);
+        if (!front) continue;
         const double x = o[0] + t * d[0], y = o[1] + t * d[1];
         const double Q = x * x / (P->s1 * P->s1) + y * y / (P->s2 * P->s2);
         const double r2 = x * x + y * y;
@@ -805,16 +892,15 @@ static void ray_hit(const oprim *P, const double dcam[3], const double *opts, co
         const double u = rho > 0.0 ? 2.0 * fabs(h) / rho : 0.0;
         const double g = oracle_gfun(u);
         const double E = g * g * Q;
-        m = mscale(fabs(E - k2) / k2, delta, M_E);
-        if (m < margin) margin = m;
-        if (E <= k2) {
+        const int inside = (E <= k2) ^ ctl_flip(ctl, mscale(fabs(E - k2) / k2, delta, M_E), M_E);
+        if (inside) {
             H->ok = 1;
             H->t = t; H->x = x; H->y = y; H->Q = Q; H->rho = rho; H->h = h; H->u = u; H->g = g; H->E = E;
-            H->F1 = H->linear ? B : 2.0 * A * t + B;
+            H->F1 = 2.0 * A * t + B;
+            ctl_flip(ctl, mscale(Drel, delta, M_DCOND), M_DCOND);
             break;
         }
     }
-    H->margin = margin;
 }
 
 /* unit normal of the paraboloid at the hit, flipped to face the camera */
@@ -836,6 +922,8 @@ typedef struct {
 typedef struct {
     int32_t list;   /* index into the active order */
     double alpha, T;
+    double flip;    /* the normal's facing sign the forward took */
+    ohit H;         /* the hit the forward took */
 } oentry;
 
 typedef struct {
@@ -890,16 +978,16 @@ static double curvature_K(double l1, double l2, double x, double y)
     return 4.0 * l1 * l2 / (den * den);
 }
 
-static void entry_backward(const oprim *P, const ohit *H, const double *dcam, const double *opts,
+static void entry_backward(const oprim *P, const ohit *H, double flip, const double *dcam, const double *opts,
                            double dalpha, double w, const double gc[3], double dt_direct, const double gn[3],
                            double dK, ograd *G)
 {
     /* direct colour, depth (and the depth terms of median and distortion),
-       normal and curvature terms */
+       normal (facing sign `flip` as the forward took it) and curvature terms */
     for (int c = 0; c < 3; ++c) G->drgb[c] += gc[c] * w;
     double dt = dt_direct;
-    double nl[3], flip, vlen;
-    hit_normal(P, H, nl, &flip, &vlen);
+    double nl[3], flip_natural, vlen;
+    hit_normal(P, H, nl, &flip_natural, &vlen);
     double dncam[3] = {gn[0] * w, gn[1] * w, gn[2] * w};
     double dx = 0.0, dy = 0.0;
     /* n_cam = flip * Rc nl */
@@ -960,16 +1048,10 @@ static void entry_backward(const oprim *P, const ohit *H, const double *dcam, co
     double dO[3] = {dx, dy, 0.0};
     double dD[3] = {H->t * dx, H->t * dy, 0.0};
     dt += d[0] * dx + d[1] * dy;
-    /* root: quadratic (implicit) or linear t = -C/B */
-    double dA = 0.0, dB, dC;
-    if (H->linear) {
-        dC = -dt / H->B;
-        dB = -H->t / H->B * dt; /* t = -C/B  ->  dt/dB = C/B^2 = -t/B */
-    } else {
-        dA = -H->t * H->t / H->F1 * dt;
-        dB = -H->t / H->F1 * dt;
-        dC = -1.0 / H->F1 * dt;
-    }
+    /* root of A t^2 + B t + C = 0 (implicit differentiation) */
+    const double dA = -H->t * H->t / H->F1 * dt;
+    const double dB = -H->t / H->F1 * dt;
+    const double dC = -1.0 / H->F1 * dt;
     const double *o = P->o, l1 = P->l1, l2 = P->l2;
     /* A = l1 d1^2 + l2 d2^2 */
     G->dl[0] += d[0] * d[0] * dA;
@@ -998,17 +1080,17 @@ static void entry_backward(const oprim *P, const ohit *H, const double *dcam, co
         }
 }
 
-/* the whole per-pixel sequence; with g != NULL also its backward */
-static void render_pixel(const obins *B, const double *cam, const double *opts, const double *delta,
+/* the whole per-pixel sequence; with g != NULL also its backward.  ctl holds
+   the forced outcomes of near-tied decisions and receives every margin. */
+static void render_pixel(const obins *B, const double *cam, const double *opts, const double *delta, octl *ctl,
                          int px, int py, int cell, double out[NCH], double *T_out, int32_t *nb_out,
-                         double *margin_out, int64_t *evals, const double g[NCH], ograd *grads, oentry **scratch,
+                         int64_t *evals, const double g[NCH], int grad_skip, ograd *grads, oentry **scratch,
                          int *scratch_cap)
 {
     double dcam[3];
     pixel_ray(cam, px, py, dcam);
     double T = 1.0, acc[NCH] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double margin = INFINITY;
-    int nb = 0, med_k = -1;
+    int nb = 0, med_k = -1, med2_k = -1;
     double med = 0.0, med2 = -INFINITY;
     /* blended (w, t) for the depth distortion, kept for its plain double sum */
     double *wt = NULL;
@@ -1029,6 +1111,10 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
         }
         qsort(order, (size_t)(e - s), sizeof(ocand), cmp_cand);
     }
+    /* the backward runs only if some upstream gradient of the pixel is non-zero */
+    int do_bwd = 0;
+    if (g)
+        for (int c = 0; c < NCH; ++c) do_bwd |= g[c] != 0.0;
     /* per-pixel resort (supplement, per-pixel resorting): accepted hits wait in
        a buffer of K entries; whenever it is full the nearest (smallest t, the
        earliest arrival among equal t) is blended, and at the end of the list
@@ -1042,17 +1128,15 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
             const oprim *P = &B->prims[li];
             ohit H;
             ++*evals;
-            ray_hit(P, dcam, opts, delta, &H);
-            if (H.margin < margin) margin = H.margin;
+            ray_hit(P, dcam, opts, delta, ctl, &H);
             if (!H.ok) continue;
             const double Gv = exp(-0.5 * H.E);
             const double aa = P->op * Gv;
-            double m = mscale(fabs(aa - opts[O_AMAX]) / opts[O_AMAX], delta, M_CLAMP);
-            if (m < margin) margin = m;
+            ctl_flip(ctl, mscale(fabs(aa - opts[O_AMAX]) / opts[O_AMAX], delta, M_CLAMP), M_CLAMP);
             const double alpha = aa < opts[O_AMAX] ? aa : opts[O_AMAX];
-            m = mscale(fabs(alpha - opts[O_AMIN]) / opts[O_AMIN], delta, M_AMIN);
-            if (m < margin) margin = m;
-            if (alpha < opts[O_AMIN]) continue;
+            const int skip = (alpha < opts[O_AMIN]) ^
+                             ctl_flip(ctl, mscale(fabs(alpha - opts[O_AMIN]) / opts[O_AMIN], delta, M_AMIN), M_AMIN);
+            if (skip) continue;
             buf[nbuf].list = li;
             buf[nbuf].seq = nseq++;
             buf[nbuf].alpha = alpha;
@@ -1067,12 +1151,15 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
                 if (buf[b].H.t < buf[best].H.t || (buf[b].H.t == buf[best].H.t && buf[b].seq < buf[best].seq))
                     best = b;
             if (nbuf > 1) {
-                /* choosing the nearest of two close depths is a discrete decision */
-                double gap = INFINITY;
+                /* choosing the nearest of two close depths is a discrete
+                   decision; its other side takes the runner-up */
+                int next = -1;
                 for (int b = 0; b < nbuf; ++b)
-                    if (b != best && buf[b].H.t - buf[best].H.t < gap) gap = buf[b].H.t - buf[best].H.t;
-                const double m = mscale(gap / fabs(buf[best].H.t), delta, M_SORT);
-                if (m < margin) margin = m;
+                    if (b != best && (next < 0 || buf[b].H.t < buf[next].H.t ||
+                                      (buf[b].H.t == buf[next].H.t && buf[b].seq < buf[next].seq)))
+                        next = b;
+                const double gap = buf[next].H.t - buf[best].H.t;
+                if (ctl_flip(ctl, mscale(gap / fabs(buf[best].H.t), delta, M_SORT), M_SORT)) best = next;
             }
             const opending en = buf[best];
             buf[best] = buf[--nbuf];
@@ -1080,17 +1167,17 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
             const ohit H = en.H;
             const double alpha = en.alpha;
             const double Tn = T * (1.0 - alpha);
-            double m = mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T);
-            if (m < margin) margin = m;
-            if (Tn < opts[O_TEPS]) {
+            const int stop = (Tn < opts[O_TEPS]) ^
+                             ctl_flip(ctl, mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T), M_T);
+            if (stop) {
                 stopped = 1;
                 break;
             }
             const double w = alpha * T;
             double nl[3], flip, vlen;
             hit_normal(P, &H, nl, &flip, &vlen);
-            m = mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N);
-            if (m < margin) margin = m;
+            if (ctl_flip(ctl, mscale(fabs(nl[0] * H.d[0] + nl[1] * H.d[1] + nl[2] * H.d[2]), delta, M_N), M_N))
+                flip = -flip;
             for (int c = 0; c < 3; ++c) acc[c] += w * P->rgb[c];
             acc[CH_DEPTH] += w * H.t;
             for (int i = 0; i < 3; ++i)
@@ -1098,15 +1185,15 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
             acc[CH_K] += w * curvature_K(P->l1, P->l2, H.x, H.y);
             /* median depth (mesh extraction, Sec. 4.1): the largest hit depth among
                entries whose incoming transmittance exceeds 0.5 */
-            m = mscale(fabs(T - 0.5) / 0.5, delta, M_MED);
-            if (m < margin) margin = m;
-            if (T > 0.5) {
+            const int qualifies = (T > 0.5) ^ ctl_flip(ctl, mscale(fabs(T - 0.5) / 0.5, delta, M_MED), M_MED);
+            if (qualifies) {
                 if (med_k < 0 || H.t > med) {
-                    if (med_k >= 0) med2 = med;
+                    if (med_k >= 0) { med2 = med; med2_k = med_k; }
                     med = H.t;
                     med_k = nb;
                 } else if (H.t > med2) {
                     med2 = H.t;
+                    med2_k = nb;
                 }
             }
             if (nb >= wt_cap) {
@@ -1115,7 +1202,7 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
             }
             wt[2 * nb] = w;
             wt[2 * nb + 1] = H.t;
-            if (g) {
+            if (do_bwd) {
                 if (nb >= *scratch_cap) {
                     *scratch_cap = *scratch_cap ? 2 * *scratch_cap : 256;
                     *scratch = (oentry *)realloc(*scratch, sizeof(oentry) * (size_t)*scratch_cap);
@@ -1123,6 +1210,8 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
                 (*scratch)[nb].list = en.list;
                 (*scratch)[nb].alpha = alpha;
                 (*scratch)[nb].T = T;
+                (*scratch)[nb].flip = flip;
+                (*scratch)[nb].H = H;
             }
             ++nb;
             T = Tn;
@@ -1140,10 +1229,13 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
             dist += wt[2 * i] * wt[2 * j] * d * d;
         }
     }
-    /* the median's choice between two close hit depths is a discrete decision */
-    if (med_k >= 0 && med2 > -INFINITY) {
-        const double m = mscale((med - med2) / fabs(med), delta, M_MED);
-        if (m < margin) margin = m;
+    /* the median's choice between two close hit depths is a discrete decision;
+       its other side takes the second largest */
+    if (med_k >= 0 && med2_k >= 0) {
+        if (ctl_flip(ctl, mscale((med - med2) / fabs(med), delta, M_MED), M_MED)) {
+            med = med2;
+            med_k = med2_k;
+        }
     }
     acc[CH_MED] = med;
     acc[CH_DIST] = dist;
@@ -1151,9 +1243,11 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
     for (int c = 0; c < NCH; ++c) out[c] = acc[c];
     *T_out = T;
     *nb_out = nb;
-    *margin_out = margin;
 
-    if (!g) {
+    /* grad_skip: a pixel whose derivative is ill-conditioned or ambiguous
+       (a near-tie of GRAD_KINDS) contributes no gradient */
+    if (grad_skip && ctl_margin(ctl, GRAD_KINDS) < 1.0) do_bwd = 0;
+    if (!do_bwd) {
         free(wt);
         return;
     }
@@ -1170,24 +1264,24 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
     for (int k = nb - 1; k >= 0; --k) {
         const oentry *en = &(*scratch)[k];
         const oprim *P = &B->prims[en->list];
-        ohit H;
-        ray_hit(P, dcam, opts, delta, &H);
-        double nl[3], flip, vlen;
-        hit_normal(P, &H, nl, &flip, &vlen);
+        const ohit *H = &en->H;
+        double nl[3], flip_natural, vlen;
+        hit_normal(P, H, nl, &flip_natural, &vlen);
+        const double flip = en->flip;
         double X[NX];
         for (int c = 0; c < 3; ++c) X[c] = P->rgb[c];
-        X[3] = H.t;
+        X[3] = H->t;
         for (int i = 0; i < 3; ++i)
             X[4 + i] = flip * (P->Rc[3 * i] * nl[0] + P->Rc[3 * i + 1] * nl[1] + P->Rc[3 * i + 2] * nl[2]);
-        X[7] = curvature_K(P->l1, P->l2, H.x, H.y);
-        X[8] = (W > 0.0 ? dist / W : 0.0) + W * (H.t - mean) * (H.t - mean);
+        X[7] = curvature_K(P->l1, P->l2, H->x, H->y);
+        X[8] = (W > 0.0 ? dist / W : 0.0) + W * (H->t - mean) * (H->t - mean);
         const double a = en->alpha, Ti = en->T, w = a * Ti;
         double dalpha = 0.0;
         for (int c = 0; c < NX; ++c) dalpha += gx[c] * (Ti * X[c] - S[c] / (1.0 - a));
         for (int c = 0; c < NX; ++c) S[c] += w * X[c];
-        double dt = g[CH_DEPTH] * w + g[CH_DIST] * 2.0 * w * W * (H.t - mean);
+        double dt = g[CH_DEPTH] * w + g[CH_DIST] * 2.0 * w * W * (H->t - mean);
         if (k == med_k) dt += g[CH_MED];
-        entry_backward(P, &H, dcam, opts, dalpha, w, g, dt, g + CH_N, g[CH_K] * w, &grads[en->list]);
+        entry_backward(P, H, flip, dcam, opts, dalpha, w, g, dt, g + CH_N, g[CH_K] * w, &grads[en->list]);
     }
     free(wt);
 }
@@ -1222,36 +1316,22 @@ static int cmp_order(const void *a, const void *b)
     return x->id < y->id ? -1 : (x->id > y->id);
 }
 
-/*
- * Render the pixel window [x0, x0+w) x [y0, y0+h) of a width x height view.
- * Parameters are FP64 (exact copies of FP32 inputs, or perturbed for finite
- * differences).  culled/depth_bits come from oracle_keys and fix the active set
- * and the order; with frame != NULL (oracle_keys' frames, and keycam the
- * key-stage camera) each pixel takes its tile's per-tile-depth order instead.
- * opts[O_RESORT] > 1 enables the per-pixel resort buffer of that size.
- * cam = {R[9], t[3], fx, fy, cx, cy}.
- * Outputs (window-sized, planar): color[3][h][w], depth, normal[3][h][w],
- * T_final, n_blend (entries blended), margin (min over decisions of the
- * relative distance to the boundary divided by its scale in delta).
- * If dL_color != NULL the backward runs and parameter gradients are written
- * (full [n] arrays, zero for inactive primitives).
- * Returns the number of (pixel, candidate) evaluations, or -1 on error.
- */
-int64_t oracle_render(int64_t n, const double *center, const double *quat, const double *scale,
-                      const double *curv, const double *opac, const double *rgb,
-                      const uint8_t *culled, const uint32_t *depth_bits, const double *frame,
-                      const double *keycam, const double *cam, int32_t width, int32_t height,
-                      const double *opts, const double *delta,
-                      int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
-                      double *color, double *depth, double *normal, double *T_final,
-                      int32_t *n_blend, double *margin, double *curvature, double *median_depth,
-                      double *distortion,
-                      const double *dL_color, const double *dL_depth, const double *dL_normal,
-                      const double *dL_curv, const double *dL_median, const double *dL_dist,
-                      double *g_center, double *g_quat, double *g_scale, double *g_curv,
-                      double *g_opac, double *g_rgb, const double *sh, int32_t sh_deg, double *g_sh)
+/* active primitives of a window, in global order, binned into cells of
+   OT x OT window pixels with the projected-ball bound */
+typedef struct {
+    obins B;
+    oprim *tmp;
+    int64_t *ids, nw;
+    int32_t *cnt, *items, *box;
+    oorder *ord;
+} owin;
+
+static void window_bins(owin *Wn, int64_t n, const double *center, const double *quat, const double *scale,
+                        const double *curv, const double *opac, const double *rgb, const uint8_t *culled,
+                        const uint32_t *depth_bits, const double *frame, const double *keycam, const double *cam,
+                        int32_t width, int32_t height, const double *opts, int32_t x0, int32_t y0, int32_t w,
+                        int32_t h, const double *sh, int32_t sh_deg)
 {
-    if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height) return -1;
     const double *W = cam, *T = cam + 9;
     /* active primitives in global order: depth key, then index */
     int64_t na = 0;
@@ -1300,7 +1380,90 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
     for (int64_t i = 0; i < nw; ++i)
         for (int cy = box[4 * i + 1]; cy <= box[4 * i + 3]; ++cy)
             for (int cx = box[4 * i]; cx <= box[4 * i + 2]; ++cx) items[fill[cy * cx_n + cx]++] = (int32_t)i;
+    free(fill);
     obins Bn = {tmp, ids, cnt, items, cx_n, cy_n, frame, depth_bits, keycam, width, height, opts[O_NEAR]};
+    Wn->B = Bn;
+    Wn->tmp = tmp;
+    Wn->ids = ids;
+    Wn->nw = nw;
+    Wn->cnt = cnt;
+    Wn->items = items;
+    Wn->box = box;
+    Wn->ord = ord;
+}
+
+static void window_free(owin *Wn)
+{
+    free(Wn->items); free(Wn->cnt); free(Wn->box); free(Wn->tmp); free(Wn->ids); free(Wn->ord);
+}
+
+/* decision kinds that change the compared maps (colour, depth, normal, T and,
+   with branch_median, the median depth) */
+static unsigned forward_kinds(int branch_median)
+{
+    unsigned k = (1u << M_A) | (1u << M_D) | (1u << M_NEAR) | (1u << M_E) | (1u << M_AMIN) | (1u << M_T) |
+                 (1u << M_N) | (1u << M_SORT);
+    if (branch_median) k |= 1u << M_MED;
+    return k;
+}
+
+
+/*
+ * Render the pixel window [x0, x0+w) x [y0, y0+h) of a width x height view.
+ * Parameters are FP64 (exact copies of FP32 inputs, or perturbed for finite
+ * differences).  culled/depth_bits come from oracle_keys and fix the active set
+ * and the order; with frame != NULL (oracle_keys' frames, and keycam the
+ * key-stage camera) each pixel takes its tile's per-tile-depth order instead.
+ * opts[O_RESORT] > 1 enables the per-pixel resort buffer of that size.
+ * cam = {R[9], t[3], fx, fy, cx, cy}.
+ * Outputs (window-sized, planar): color[3][h][w], depth, normal[3][h][w],
+ * T_final, n_blend (entries blended), margin (min over the decisions of the
+ * kinds forward_kinds(branch_median) selects of the scaled distance to the
+ * boundary), optional gmargin (the same over GRAD_KINDS) and kind_bits (bit k
+ * set where kind k has a margin below 1).
+ * Near-tied decisions of the window pixels forced[i] (row-major index in the
+ * window, i < n_forced) take the outcomes forced_path[i * OPATH_MAX ...] of
+ * their first forced_len[i] branch points (see octl).
+ * If dL_color != NULL the backward runs and parameter gradients are written
+ * (full [n] arrays, zero for inactive primitives); with grad_skip, pixels
+ * whose gmargin is below 1 contribute none.
+ * Returns the number of (pixel, candidate) evaluations, or -1 on error.
+ */
+int64_t oracle_render(int64_t n, const double *center, const double *quat, const double *scale,
+                      const double *curv, const double *opac, const double *rgb,
+                      const uint8_t *culled, const uint32_t *depth_bits, const double *frame,
+                      const double *keycam, const double *cam, int32_t width, int32_t height,
+                      const double *opts, const double *delta,
+                      int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
+                      double *color, double *depth, double *normal, double *T_final,
+                      int32_t *n_blend, double *margin, double *curvature, double *median_depth,
+                      double *distortion,
+                      const double *dL_color, const double *dL_depth, const double *dL_normal,
+                      const double *dL_curv, const double *dL_median, const double *dL_dist,
+                      double *g_center, double *g_quat, double *g_scale, double *g_curv,
+                      double *g_opac, double *g_rgb, const double *sh, int32_t sh_deg, double *g_sh,
+                      int32_t branch_median, int64_t n_forced, const int32_t *forced, const uint8_t *forced_path,
+                      const int32_t *forced_len, double *gmargin, uint16_t *kind_bits, int32_t grad_skip)
+{
+    if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height) return -1;
+    const double *W = cam, *T = cam + 9;
+    owin Wn;
+    window_bins(&Wn, n, center, quat, scale, curv, opac, rgb, culled, depth_bits, frame, keycam, cam, width, height,
+                opts, x0, y0, w, h, sh, sh_deg);
+    const obins Bn = Wn.B;
+    const int64_t nw = Wn.nw;
+    const int64_t *ids = Wn.ids;
+    const oprim *tmp = Wn.tmp;
+    const int cx_n = Bn.cells_x;
+    const unsigned fkinds = forward_kinds(branch_median);
+    /* window pixel -> forced path */
+    int32_t *fmap = NULL;
+    if (n_forced > 0) {
+        fmap = (int32_t *)malloc(sizeof(int32_t) * (size_t)w * (size_t)h);
+        for (size_t i = 0; i < (size_t)w * (size_t)h; ++i) fmap[i] = -1;
+        for (int64_t i = 0; i < n_forced; ++i)
+            if (forced[i] >= 0 && (int64_t)forced[i] < (int64_t)w * h) fmap[forced[i]] = (int32_t)i;
+    }
 
     int nthr = nthreads > 0 ? nthreads : 1;
 #ifdef _OPENMP
@@ -1340,8 +1503,23 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
                     if (dL_median) gg[CH_MED] = dL_median[pix];
                     if (dL_dist) gg[CH_DIST] = dL_dist[pix];
                 }
-                render_pixel(&Bn, cam, opts, delta, x0 + i, y0 + j, cell, out, &Tf, &nb, &mg, &ev,
-                             do_bwd ? gg : NULL, mine, &scratch, &cap);
+                octl ctl;
+                const int32_t fi = fmap ? fmap[pix] : -1;
+                if (fi >= 0)
+                    ctl_init(&ctl, fkinds, forced_path + (size_t)fi * OPATH_MAX,
+                             forced_len[fi] < OPATH_MAX ? forced_len[fi] : OPATH_MAX);
+                else
+                    ctl_init(&ctl, fkinds, NULL, 0);
+                render_pixel(&Bn, cam, opts, delta, &ctl, x0 + i, y0 + j, cell, out, &Tf, &nb, &ev,
+                             do_bwd ? gg : NULL, grad_skip, mine, &scratch, &cap);
+                mg = ctl_margin(&ctl, fkinds);
+                if (gmargin) gmargin[pix] = ctl_margin(&ctl, GRAD_KINDS);
+                if (kind_bits) {
+                    uint16_t bits = 0;
+                    for (int k = 0; k < M_COUNT; ++k)
+                        if (ctl.kmin[k] < 1.0) bits |= (uint16_t)(1u << k);
+                    kind_bits[pix] = bits;
+                }
                 for (int c = 0; c < 3; ++c) color[c * npx + pix] = out[c];
                 depth[pix] = out[CH_DEPTH];
                 for (int c = 0; c < 3; ++c) normal[c * npx + pix] = out[CH_N + c];
@@ -1438,7 +1616,110 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
         }
         free(grads);
     }
-    free(items); free(fill); free(cnt); free(box); free(tmp); free(ids); free(ord);
+    free(fmap);
+    window_free(&Wn);
+    return evals_total;
+}
+
+/*
+ * Every result the window pixels pix[i] (row-major index in the window) may
+ * take when their near-tied decisions (kinds forward_kinds(branch_median)) go
+ * either way: a depth-first walk over the branch points (octl) with at most
+ * max_leaves results per pixel.  The outputs per pixel are n_leaves[i] and
+ * overflow[i] (1 if the walk stopped at max_leaves or met more than OPATH_MAX
+ * branch points); per result j of pixel i, at r = i * max_leaves + j:
+ * vals[r * (NCH + 1) + c] = colour 0-2, depth, normal 4-6, curvature, median
+ * depth, distortion, then T_final; paths[r * OPATH_MAX + k] the outcome of its
+ * k-th branch point (1 = the other side) and plen[r] their number.  Result 0
+ * is the one every decision takes on its own side.  Returns the number of
+ * evaluations, or -1 on error.
+ */
+int64_t oracle_render_alts(int64_t n, const double *center, const double *quat, const double *scale,
+                           const double *curv, const double *opac, const double *rgb,
+                           const uint8_t *culled, const uint32_t *depth_bits, const double *frame,
+                           const double *keycam, const double *cam, int32_t width, int32_t height,
+                           const double *opts, const double *delta,
+                           int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t nthreads,
+                           const double *sh, int32_t sh_deg, int32_t branch_median,
+                           int64_t npix, const int32_t *pix, int32_t max_leaves,
+                           int32_t *n_leaves, uint8_t *overflow, double *vals, uint8_t *paths, int32_t *plen)
+{
+    if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height || max_leaves < 1) return -1;
+    for (int64_t i = 0; i < npix; ++i)
+        if (pix[i] < 0 || (int64_t)pix[i] >= (int64_t)w * h) return -1;
+    owin Wn;
+    window_bins(&Wn, n, center, quat, scale, curv, opac, rgb, culled, depth_bits, frame, keycam, cam, width, height,
+                opts, x0, y0, w, h, sh, sh_deg);
+    const unsigned fkinds = forward_kinds(branch_median);
+    const int cx_n = Wn.B.cells_x;
+    int nthr = nthreads > 0 ? nthreads : 1;
+#ifdef _OPENMP
+    omp_set_num_threads(nthr);
+#else
+    nthr = 1;
+#endif
+    int64_t evals_total = 0;
+#pragma omp parallel num_threads(nthr) reduction(+ : evals_total)
+    {
+        /* stack of paths still to walk: their outcomes and lengths */
+        int cap = 64, top = 0;
+        uint8_t *stk = (uint8_t *)malloc((size_t)cap * OPATH_MAX);
+        int32_t *stk_len = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+        int64_t ev = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < npix; ++i) {
+            const int px = x0 + pix[i] % w, py = y0 + pix[i] / w;
+            const int cell = ((py - y0) / OT) * cx_n + (px - x0) / OT;
+            int leaves = 0;
+            uint8_t ovf = 0;
+            top = 0;
+            memset(stk, 0, OPATH_MAX);
+            stk_len[0] = 0;
+            top = 1;
+            while (top > 0) {
+                --top;
+                uint8_t node[OPATH_MAX];
+                memcpy(node, stk + (size_t)top * OPATH_MAX, OPATH_MAX);
+                const int L = stk_len[top];
+                if (leaves == max_leaves) { ovf = 1; break; }
+                octl ctl;
+                ctl_init(&ctl, fkinds, node, L);
+                double out[NCH], Tf;
+                int32_t nb;
+                render_pixel(&Wn.B, cam, opts, delta, &ctl, px, py, cell, out, &Tf, &nb, &ev, NULL, 0, NULL, NULL,
+                             NULL);
+                int m = ctl.seen;
+                if (m > OPATH_MAX) { ovf = 1; m = OPATH_MAX; }
+                const size_t r = (size_t)i * (size_t)max_leaves + (size_t)leaves;
+                for (int c = 0; c < NCH; ++c) vals[r * (NCH + 1) + c] = out[c];
+                vals[r * (NCH + 1) + NCH] = Tf;
+                memset(paths + r * OPATH_MAX, 0, OPATH_MAX);
+                memcpy(paths + r * OPATH_MAX, node, (size_t)L);
+                plen[r] = m;
+                ++leaves;
+                /* children: the natural outcomes up to branch point j, then the other side at j */
+                for (int j = m - 1; j >= L; --j) {
+                    if (top == cap) {
+                        cap *= 2;
+                        stk = (uint8_t *)realloc(stk, (size_t)cap * OPATH_MAX);
+                        stk_len = (int32_t *)realloc(stk_len, sizeof(int32_t) * (size_t)cap);
+                    }
+                    uint8_t *c = stk + (size_t)top * OPATH_MAX;
+                    memset(c, 0, OPATH_MAX);
+                    memcpy(c, node, (size_t)L);
+                    c[j] = 1;
+                    stk_len[top] = j + 1;
+                    ++top;
+                }
+            }
+            n_leaves[i] = leaves;
+            overflow[i] = ovf;
+        }
+        free(stk);
+        free(stk_len);
+        evals_total += ev;
+    }
+    window_free(&Wn);
     return evals_total;
 }
 
@@ -1449,11 +1730,13 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
 void oracle_ray_hit(const double *c, const double *q, const double *s, const double *l,
                     const double *cam, const double *dcam, const double *opts, double *out)
 {
-    const double delta[M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    const double delta[M_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
     oprim P;
     setup_prim(c, q, s, l, 1.0, (const double[3]){0, 0, 0}, cam, cam + 9, &P);
     ohit H;
-    ray_hit(&P, dcam, opts, delta, &H);
+    octl ctl;
+    ctl_init(&ctl, 0u, NULL, 0);
+    ray_hit(&P, dcam, opts, delta, &ctl, &H);
     for (int i = 0; i < 15; ++i) out[i] = 0.0;
     out[0] = H.ok;
     out[1] = H.linear;

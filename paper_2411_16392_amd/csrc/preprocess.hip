@@ -379,8 +379,16 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     cl.nx = tx1 - tx0 + 1;
     cl.ny = ty1 - ty0 + 1;
 
-    // projected centre split into integer + fraction, and the record
-    const double uc = fma(fx, cc[0] / cc[2], cxp), vc = fma(fy, cc[1] / cc[2], cyp);
+    // projected centre split into integer + fraction, and the record.  The
+    // record's centre depth zf is FP32; the centre is projected at that depth,
+    // so that (u_c, v_c, zf) describe the point P0 = (Xc, Yc, zf) exactly, and
+    // the rounding residual zl = Zc - zf (the true centre is P0 + zl z) goes
+    // into the record as well: the rasterizers then measure offsets from the
+    // true centre, where an FP32 depth alone would move the primitive by up to
+    // half an ulp of Zc -- at grazing incidence enough to shift its hits by
+    // 1e-3 of sigma.
+    const double zl = cc[2] - (double)zf;
+    const double uc = fma(fx, cc[0] / (double)zf, cxp), vc = fma(fy, cc[1] / (double)zf, cyp);
     const double U = floor(uc), V = floor(vc);
     const float hu = (float)(0.5 - (uc - U)), hv = (float)(0.5 - (vc - V));
     // the conic in pixels relative to the projected centre, scaled so that
@@ -405,7 +413,7 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     rec[4] = make_float4((float)Rc[0], (float)Rc[1], (float)Rc[2], (float)Rc[3]);
     rec[5] = make_float4((float)Rc[4], (float)Rc[5], (float)Rc[6], (float)Rc[7]);
     rec[6] = make_float4((float)Rc[8], r0, r1, r2);
-    rec[7] = make_float4(cC, cD, cE, 0.0f);
+    rec[7] = make_float4(cC, cD, cE, (float)zl);
 }
 
 __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)

@@ -14,8 +14,7 @@
 // A s^2 + B s + C = 0 with
 //     A = l1 e0^2 + l2 e1^2,  B = 2 (l1 m0 e0 + l2 m1 e1) - e2,  C = l1 m0^2 + l2 m1^2 - m2.
 // A is the unit-ray A of the paper scaled by |e|^2, so the small-|A| test uses
-// A_eps |e|^2; the paper's tangent-plane root t = -C/B, written in s, is
-// s = -(C - A Zc^2) / (B - 2 A Zc).
+// A_eps |e|^2.  The discriminant is the same in s as in the camera-origin t.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -35,7 +34,7 @@ enum : int {
     R_U = 4, R_HU = 5, R_V = 6, R_HV = 7,
     R_ZC = 8, R_L1 = 9, R_L2 = 10, R_OP = 11,
     R_K1 = 12, R_K2 = 13, R_CA = 14, R_CB = 15,
-    R_ROT = 16, R_RGB = 25, R_CC = 28, R_CD = 29, R_CE = 30
+    R_ROT = 16, R_RGB = 25, R_CC = 28, R_CD = 29, R_CE = 30, R_ZL = 31
 };
 
 // slack of the FP32 conic pre-test (the conic is normalised to -1 at the
@@ -67,10 +66,14 @@ __device__ inline PixelRay make_ray(int px, int py, const RasterParams &P)
     return r;
 }
 
-// Geometry of one primitive, as loaded from its record.
+// Geometry of one primitive, as loaded from its record.  The centre sits at
+// (Xc, Yc, Zc + zl) with Zc its FP32 depth and zl the rounding residual; the
+// pixel offsets are measured at depth Zc, so the offset from the centre has
+// the camera-z component -zl, i.e. mz = -zl Rc^T z in the local frame.
 struct Prim {
     float U, hu, V, hv, Zc, l1, l2, op, k1, k2, kx, ky;
     float R[9];  // camera-from-local rotation, row-major R[3 i + j]
+    float mz[3];  // local-frame offset -zl Rc^T z
 };
 
 __device__ inline void load_prim(const float *w, const RasterParams &P, Prim &p)
@@ -89,6 +92,10 @@ __device__ inline void load_prim(const float *w, const RasterParams &P, Prim &p)
     p.R[0] = d.x; p.R[1] = d.y; p.R[2] = d.z; p.R[3] = d.w;
     p.R[4] = e.x; p.R[5] = e.y; p.R[6] = e.z; p.R[7] = e.w;
     p.R[8] = f;
+    const float zl = w[R_ZL];
+    p.mz[0] = -zl * p.R[6];
+    p.mz[1] = -zl * p.R[7];
+    p.mz[2] = -zl * p.R[8];
 }
 
 // Offset of the pixel centre from the projected centre, dxp = u + 0.5 - u_c,
@@ -167,9 +174,9 @@ __device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterPar
     H.dyp = dyp;
     H.mx = p.kx * H.dxp;
     H.my = p.ky * H.dyp;
-    H.m0 = __builtin_fmaf(p.R[0], H.mx, p.R[3] * H.my);
-    H.m1 = __builtin_fmaf(p.R[1], H.mx, p.R[4] * H.my);
-    H.m2 = __builtin_fmaf(p.R[2], H.mx, p.R[5] * H.my);
+    H.m0 = __builtin_fmaf(p.R[0], H.mx, __builtin_fmaf(p.R[3], H.my, p.mz[0]));
+    H.m1 = __builtin_fmaf(p.R[1], H.mx, __builtin_fmaf(p.R[4], H.my, p.mz[1]));
+    H.m2 = __builtin_fmaf(p.R[2], H.mx, __builtin_fmaf(p.R[5], H.my, p.mz[2]));
     H.e0 = __builtin_fmaf(p.R[0], r.xn, __builtin_fmaf(p.R[3], r.yn, p.R[6]));
     H.e1 = __builtin_fmaf(p.R[1], r.xn, __builtin_fmaf(p.R[4], r.yn, p.R[7]));
     H.e2 = __builtin_fmaf(p.R[2], r.xn, __builtin_fmaf(p.R[5], r.yn, p.R[8]));
@@ -178,32 +185,33 @@ __device__ inline bool ray_hit(const Prim &p, const PixelRay &r, const RasterPar
     H.B = 2.0f * __builtin_fmaf(l1e0, H.m0, l2e1 * H.m1) - H.e2;
     H.C = __builtin_fmaf(p.l1 * H.m0, H.m0, __builtin_fmaf(p.l2 * H.m1, H.m1, -H.m2));
 
+    // roots q / A and C / q with q = -(B + sgn(B) sqrt(D)) / 2; for |A| <
+    // A_eps (the paper's nearly flat case) the root q / A, which diverges as A
+    // -> 0, is dropped and C / q -- the tangent-plane intersection at A = 0 --
+    // is the one candidate.  Evaluated relative to the centre, C / q needs no
+    // cancellation of A terms, so the hit stays exact to rounding where A is
+    // small only through cancellation (saddles seen along an asymptote).
     float cand0, cand1;
     int nc = 0;
-    if (__builtin_fabsf(H.A) < P.A_eps * r.e2) {
-        H.linear = true;
-        const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
-        if (M != 0.0f) {
-            const float N = __builtin_fmaf(-H.A * p.Zc, p.Zc, H.C);
-            cand0 = -N * __builtin_amdgcn_rcpf(M);
-            nc = 1;
-        }
-    } else {
-        H.linear = false;
-        const float D = __builtin_fmaf(H.B, H.B, -4.0f * H.A * H.C);
-        if (D >= 0.0f) {
-            const float sq = __builtin_amdgcn_sqrtf(D);
-            const float q = -0.5f * (H.B + (H.B >= 0.0f ? sq : -sq));
-            float r1, r2;
-            if (q == 0.0f) {
-                r1 = r2 = 0.0f;
+    H.linear = __builtin_fabsf(H.A) < P.A_eps * r.e2;
+    const float D = __builtin_fmaf(H.B, H.B, -4.0f * H.A * H.C);
+    if (D >= 0.0f) {
+        const float sq = __builtin_amdgcn_sqrtf(D);
+        const float q = -0.5f * (H.B + (H.B >= 0.0f ? sq : -sq));
+        if (q == 0.0f) {
+            cand0 = cand1 = 0.0f;
+            nc = H.linear ? 0 : 2;
+        } else {
+            const float r2 = H.C * __builtin_amdgcn_rcpf(q);
+            if (H.linear) {
+                cand0 = r2;
+                nc = 1;
             } else {
-                r1 = q * __builtin_amdgcn_rcpf(H.A);
-                r2 = H.C * __builtin_amdgcn_rcpf(q);
+                const float r1 = q * __builtin_amdgcn_rcpf(H.A);
+                cand0 = fminf(r1, r2);
+                cand1 = fmaxf(r1, r2);
+                nc = 2;
             }
-            cand0 = fminf(r1, r2);
-            cand1 = fmaxf(r1, r2);
-            nc = 2;
         }
     }
     // unrolled: a loop over the two candidates costs selects and branches per step

@@ -390,23 +390,11 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     float de0 = H.s * dx, de1 = H.s * dy, de2 = 0.0f;
     float ds = __builtin_fmaf(H.e0, dx, __builtin_fmaf(H.e1, dy, dz));
     float dZc = dz;
-    float dA, dB, dC;
-    if (H.linear) {
-        // s = -(C - A Zc^2) / (B - 2 A Zc)
-        const float M = __builtin_fmaf(-2.0f * H.A, p.Zc, H.B);
-        const float iM = __builtin_amdgcn_rcpf(M);
-        const float dN = -ds * iM;
-        const float dM = -H.s * iM * ds;
-        dC = dN;
-        dA = -p.Zc * p.Zc * dN - 2.0f * p.Zc * dM;
-        dB = dM;
-        dZc += -2.0f * H.A * p.Zc * dN - 2.0f * H.A * dM;
-    } else {
-        const float iF = __builtin_amdgcn_rcpf(__builtin_fmaf(2.0f * H.A, H.s, H.B));
-        dA = -H.s * H.s * iF * ds;
-        dB = -H.s * iF * ds;
-        dC = -iF * ds;
-    }
+    // root of A s^2 + B s + C = 0 (implicit differentiation)
+    const float iF = __builtin_amdgcn_rcpf(__builtin_fmaf(2.0f * H.A, H.s, H.B));
+    const float dA = -H.s * H.s * iF * ds;
+    const float dB = -H.s * iF * ds;
+    const float dC = -iF * ds;
     // A = l1 e0^2 + l2 e1^2
     gr[G_L1] += H.e0 * H.e0 * dA;
     gr[G_L2] += H.e1 * H.e1 * dA;

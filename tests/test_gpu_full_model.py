@@ -1,8 +1,8 @@
 """The paper's full-model ordering on the GPU (per-tile sort depth and the
 8-entry per-pixel resort buffer, with the front-to-back backward) against the
-FP64 oracle with the same ordering, through the C ABI.  Same tolerances as the
-plain path; the oracle's margin includes the buffer's choice between two close
-hit depths."""
+FP64 oracle with the same ordering, through the C ABI.  Same tolerances and
+every-pixel check as the plain path; the buffer's choice between two close hit
+depths is one of the near-tied decisions whose other side is also accepted."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +12,7 @@ from paper_2411_16392_amd import _lib as L
 from paper_2411_16392_amd import render as R
 from paper_2411_16392_amd import scenes
 
-from gpu_helpers import compare_forward, grad_errors, oracle_margin_full, to_np, window_of
+from gpu_helpers import backward_parity, check_forward, to_np, window_of
 
 pytestmark = pytest.mark.gpu
 
@@ -50,11 +50,10 @@ def test_full_model_forward_full_frame(ci, flags, o_opts):
     c = cfg(ci)
     cam = c.cameras[0]
     _, _, st = _fwd(c.scene, cam, flags)
-    o = oracle.render(c.scene, cam, opts=o_opts)
-    res = compare_forward(window_of(st, (0, 0, cam.width, cam.height)), o, o["margin"] >= 1.0, f"full cfg{ci}")
     # the sphere of config 1 puts many hits of one surface within a few 1e-6 of
-    # each other in depth; the buffer's choice between them is excluded
-    assert res["excluded"] < 0.05
+    # each other in depth: the buffer's choice between them is often near-tied
+    res, _, _ = check_forward(window_of(st, (0, 0, cam.width, cam.height)), c.scene, cam, opts=o_opts,
+                              label=f"full cfg{ci}", max_excluded=0.05)
     print("full model", ci, flags, res)
 
 
@@ -64,8 +63,8 @@ def test_full_model_forward_headline_crops():
     _, _, st = _fwd(c.scene, cam)
     ks = oracle.keys(c.scene, cam)
     for win in [(760, 560, 64, 64), (1100, 700, 48, 56)]:
-        o = oracle.render(c.scene, cam, opts=ORACLE_FULL, window=win, key_stage=ks)
-        res = compare_forward(window_of(st, win), o, o["margin"] >= 1.0, f"full cfg2 {win}")
+        res, _, _ = check_forward(window_of(st, win), c.scene, cam, win, opts=ORACLE_FULL, ks=ks,
+                                  label=f"full cfg2 {win}", max_excluded=0.5)
         print("full model cfg2", win, res)
 
 
@@ -80,41 +79,27 @@ def test_resort_changes_the_image():
 
 def _bwd_case(scene, cam, window, seed, flags=FULL, geometry=False):
     dL = scenes.upstream_grads(seed, cam.height, cam.width, crop=window)
-    dG = scenes.upstream_geometry_grads(seed, cam.height, cam.width, crop=window)
-    ks = oracle.keys(scene, cam)
-    oo = dict(ORACLE_FULL)
-    x0, y0, w, h = window
-    o0 = oracle.render(scene, cam, opts=oo, window=window, key_stage=ks)
-    m = np.zeros((cam.height, cam.width), bool)
-    m[y0:y0 + h, x0:x0 + w] = o0["margin"] >= 1.0
-    dLm = [dL[0] * m, dL[1] * m, dL[2] * m]
     if geometry:
-        dLm += [dG[0] * m, dG[1] * m, dG[2] * m]
-    o = oracle.render(scene, cam, opts=oo, window=window, dL=tuple(dLm), key_stage=ks)
-    r, sc_t, st = _fwd(scene, cam, flags, geometry)
-    t = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dLm]
-    kw = dict(dcurvature=t[3], dmedian_depth=t[4], ddistortion=t[5]) if geometry else {}
-    g = r.backward(sc_t, st, t[0], t[1], t[2], **kw)
-    torch.cuda.synchronize()
-    return {k: to_np(v) for k, v in g.items()}, o["grads"]
+        dL = dL + scenes.upstream_geometry_grads(seed, cam.height, cam.width, crop=window)
+    rep, g, o = backward_parity(scene, cam, window, dL, flags=flags, oracle_opts=ORACLE_FULL, geometry=geometry,
+                                label=f"full bwd {window}", max_excluded=0.5, max_grad_excluded=0.04)
+    print("full bwd", window, rep)
+    return g, o
 
 
 def test_full_model_backward_config0():
     c = cfg(0)
-    g, o = _bwd_case(c.scene, c.cameras[0], (0, 0, 128, 128), 27)
-    print("full bwd cfg0 worst", grad_errors(g, o))
+    _bwd_case(c.scene, c.cameras[0], (0, 0, 128, 128), 27)
 
 
 def test_full_model_backward_config1_crop():
     c = cfg(1)
-    g, o = _bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 28)
-    print("full bwd cfg1 worst", grad_errors(g, o))
+    _bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 28)
 
 
 def test_full_model_backward_with_geometry_maps():
     c = cfg(1)
-    g, o = _bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 29, geometry=True)
-    print("full bwd geo worst", grad_errors(g, o))
+    _bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 29, geometry=True)
 
 
 def test_full_model_deterministic_backward():
@@ -123,7 +108,6 @@ def test_full_model_deterministic_backward():
     win = (368, 268, 64, 64)
     flags = FULL | L.QGS_DETERMINISTIC_BWD
     g1, o = _bwd_case(c.scene, cam, win, 28, flags=flags)
-    grad_errors(g1, o)
     g2, _ = _bwd_case(c.scene, cam, win, 28, flags=flags)
     for k in g1:
         assert np.array_equal(g1[k], g2[k]), k
@@ -133,8 +117,7 @@ def test_full_model_geometry_forward():
     c = cfg(0)
     cam = c.cameras[0]
     _, _, st = _fwd(c.scene, cam, FULL, geometry=True)
-    o = oracle.render(c.scene, cam, opts=ORACLE_FULL)
-    m = o["margin"] >= 1.0
-    for key in ("curvature", "median_depth", "distortion"):
-        err = (np.abs(to_np(getattr(st, key)) - o[key]) / np.maximum(1.0, np.abs(o[key])))[m]
-        assert float(err.max()) <= 1e-4, key
+    win = (0, 0, cam.width, cam.height)
+    res, _, _ = check_forward(window_of(st, win, geometry=True), c.scene, cam, opts=ORACLE_FULL, geometry=True,
+                              label="full geo cfg0", max_excluded=0.01)
+    print("full model geometry", res)

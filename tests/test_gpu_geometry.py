@@ -1,9 +1,9 @@
 """Parity of the geometry maps (curvature, median depth, depth distortion) and
 their gradients: HIP path through the C ABI against the FP64 oracle.
 
-Maps within 1e-4 relative to max(1, |value|) on pixels whose oracle margin to
-every discrete decision (including the median's choice) is at least its scale;
-gradients to the same bar as the other outputs.
+Maps within 1e-4 relative to max(1, |value|), every pixel checked (the
+median's choices are among the near-tied decisions whose other side is also
+accepted); gradients to the same bar as the other outputs.
 """
 import numpy as np
 import pytest
@@ -14,7 +14,7 @@ from paper_2411_16392_amd import _lib as L
 from paper_2411_16392_amd import render as R
 from paper_2411_16392_amd import scenes
 
-from gpu_helpers import compare_forward, grad_errors, oracle_margin_full, to_np, window_of
+from gpu_helpers import backward_parity, check_forward, to_np, window_of
 
 pytestmark = pytest.mark.gpu
 
@@ -45,22 +45,15 @@ def _geo_forward(scene, cam, flags=0):
     return r, sc_t, st
 
 
-def _compare_geo(st, o, window, label):
+def _compare_geo(st, scene, cam, window, label, ks=None):
+    res, _, _ = check_forward(window_of(st, window, geometry=True), scene, cam, window, ks=ks, geometry=True,
+                              label=label, max_excluded=0.03)
     x0, y0, w, h = window
     sl = (slice(y0, y0 + h), slice(x0, x0 + w))
-    m = o["margin"] >= 1.0
-    res = {}
-    for key, name in (("curvature", "curvature"), ("median_depth", "median_depth"), ("distortion", "distortion")):
-        g = to_np(getattr(st, name))[sl]
-        ref = o[key]
-        err = (np.abs(g - ref) / np.maximum(1.0, np.abs(ref)))[m]
-        res[key] = float(err.max(initial=0))
-        assert res[key] <= TOL_GEO, (label, key, res)
     # the median is a hit depth of a blended entry; none means 0
     medp = to_np(st.median_pos)[sl]
     assert np.all((medp == 0) == (to_np(st.median_depth)[sl] == 0.0))
     assert np.all(medp <= to_np(st.last)[sl])
-    res["excluded"] = float(1.0 - m.mean())
     return res
 
 
@@ -69,10 +62,7 @@ def test_geometry_maps_full_frame(ci):
     c = cfg(ci)
     cam = c.cameras[0]
     _, _, st = _geo_forward(c.scene, cam)
-    o = oracle.render(c.scene, cam)
-    win = (0, 0, cam.width, cam.height)
-    compare_forward(window_of(st, win), o, o["margin"] >= 1.0, f"geo cfg{ci}")
-    res = _compare_geo(st, o, win, f"cfg{ci}")
+    res = _compare_geo(st, c.scene, cam, (0, 0, cam.width, cam.height), f"cfg{ci}")
     assert res["excluded"] < 0.01
     print("geo", ci, res)
 
@@ -83,8 +73,7 @@ def test_geometry_maps_headline_crops():
     _, _, st = _geo_forward(c.scene, cam)
     ks = oracle.keys(c.scene, cam)
     for win in [(760, 560, 64, 64), (1536, 1136, 64, 64)]:
-        o = oracle.render(c.scene, cam, window=win, key_stage=ks)
-        res = _compare_geo(st, o, win, f"cfg2 {win}")
+        res = _compare_geo(st, c.scene, cam, win, f"cfg2 {win}", ks=ks)
         print("geo cfg2", win, res)
 
 
@@ -102,30 +91,22 @@ def test_geometry_off_leaves_outputs_unchanged():
 
 
 def _geo_bwd_case(scene, cam, window, seed, flags=0):
-    dL = scenes.upstream_grads(seed, cam.height, cam.width, crop=window)
-    dG = scenes.upstream_geometry_grads(seed, cam.height, cam.width, crop=window)
-    ks = oracle.keys(scene, cam)
-    margin_full, _ = oracle_margin_full(scene, cam, window, ks)
-    m = margin_full >= 1.0
-    dLm = (dL[0] * m, dL[1] * m, dL[2] * m, dG[0] * m, dG[1] * m, dG[2] * m)
-    o = oracle.render(scene, cam, window=window, dL=dLm, key_stage=ks)
-    r, sc_t, st = _geo_forward(scene, cam, flags)
-    t = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dLm]
-    g = r.backward(sc_t, st, t[0], t[1], t[2], dcurvature=t[3], dmedian_depth=t[4], ddistortion=t[5])
-    torch.cuda.synchronize()
-    return {k: to_np(v) for k, v in g.items()}, o["grads"]
+    dL = (scenes.upstream_grads(seed, cam.height, cam.width, crop=window) +
+          scenes.upstream_geometry_grads(seed, cam.height, cam.width, crop=window))
+    rep, g, o = backward_parity(scene, cam, window, dL, flags=flags, geometry=True, label=f"geo bwd {window}",
+                                max_excluded=0.03, max_grad_excluded=0.04)
+    print("geo bwd", window, rep)
+    return g, o
 
 
 def test_geometry_backward_config0():
     c = cfg(0)
-    g, o = _geo_bwd_case(c.scene, c.cameras[0], (0, 0, 128, 128), 17)
-    print("geo bwd cfg0 worst", grad_errors(g, o))
+    _geo_bwd_case(c.scene, c.cameras[0], (0, 0, 128, 128), 17)
 
 
 def test_geometry_backward_config1_crop():
     c = cfg(1)
-    g, o = _geo_bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 18)
-    print("geo bwd cfg1 worst", grad_errors(g, o))
+    _geo_bwd_case(c.scene, c.cameras[0], (368, 268, 64, 64), 18)
 
 
 def test_geometry_backward_deterministic():
@@ -133,7 +114,6 @@ def test_geometry_backward_deterministic():
     cam = c.cameras[0]
     win = (368, 268, 64, 64)
     g1, o = _geo_bwd_case(c.scene, cam, win, 18, flags=L.QGS_DETERMINISTIC_BWD)
-    grad_errors(g1, o)
     g2, _ = _geo_bwd_case(c.scene, cam, win, 18, flags=L.QGS_DETERMINISTIC_BWD)
     for k in g1:
         assert np.array_equal(g1[k], g2[k]), k

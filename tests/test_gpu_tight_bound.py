@@ -15,7 +15,7 @@ from paper_2411_16392_amd import _lib as L
 from paper_2411_16392_amd import render as R
 from paper_2411_16392_amd import scenes
 
-from gpu_helpers import compare_forward, gpu_forward, grad_errors, masked_dL, oracle_margin_full, to_np
+from gpu_helpers import backward_parity, gpu_forward, to_np
 from test_gpu_parity import check_keys, check_lists
 
 pytestmark = pytest.mark.gpu
@@ -120,22 +120,9 @@ def test_tight_bound_fewer_pairs_on_curved_primitives():
 
 def test_tight_bound_oracle_parity_curved():
     sc, cam = curved_cfg0()
-    _, st = gpu_forward(sc, cam)
-    o = oracle.render(sc, cam)
-    from gpu_helpers import window_of
-    res = compare_forward(window_of(st, (0, 0, cam.width, cam.height)), o, o["margin"] >= 1.0, "curved")
-    # strongly curved primitives put more pixels near a decision boundary
-    # (grazing rays: discriminant near 0) than workload 0 (1.4% here)
-    assert res["excluded"] < 0.03
     win = (0, 0, cam.width, cam.height)
     dL = scenes.upstream_grads(4, cam.height, cam.width)
-    ks = oracle.keys(sc, cam)
-    margin_full, _ = oracle_margin_full(sc, cam, win, ks)
-    dLm = masked_dL(dL, margin_full)
-    og = oracle.render(sc, cam, window=win, dL=dLm, key_stage=ks)["grads"]
-    r = R.Renderer()
-    sc_t = R.scene_to_device(sc)
-    st = r.forward(sc_t, cam)
-    g = r.backward(sc_t, st, *(torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dLm))
-    torch.cuda.synchronize()
-    print("curved fwd", res, "bwd worst", grad_errors({k: to_np(v) for k, v in g.items()}, og))
+    # strongly curved primitives put more pixels near a decision boundary
+    # (grazing rays: discriminant near 0) than workload 0
+    rep, _, _ = backward_parity(sc, cam, win, dL, label="curved", max_excluded=0.03, max_grad_excluded=0.05)
+    print("curved", rep)

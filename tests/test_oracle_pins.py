@@ -265,7 +265,10 @@ def test_roots_ordered_near_first_when_both_inside():
 
 
 def test_small_A_branch_is_tangent_plane_intersection():
-    # saddle lambda = (1, -1): directions with d1 ~ d2 make A tiny
+    # saddle lambda = (1, -1): directions with d1 ~ d2 make A tiny.  Below
+    # A_eps the root that diverges as A -> 0 is dropped; the other one is the
+    # supplement's tangent-plane intersection at A = 0 and its continuation
+    # (the exact near root) for 0 < |A| < A_eps.
     q = np.array([1.0, 0.0, 0.0, 0.0])
     c = np.array([0.3, -0.2, 5.0])
     o_hat = -c
@@ -280,12 +283,18 @@ def test_small_A_branch_is_tangent_plane_intersection():
         p_o = np.array([o_hat[0], o_hat[1], lam[0] * o_hat[0] ** 2 + lam[1] * o_hat[1] ** 2])
         nrm = np.array([2 * lam[0] * o_hat[0], 2 * lam[1] * o_hat[1], -1.0])
         t_plane = nrm @ (p_o - o_hat) / (nrm @ d)
-        assert abs(h["t"] - t_plane) <= 1e-12 * t_plane
-        # the exact quadratic root approaches the linear one as A -> 0
-        if h["A"] != 0.0:
+        if h["A"] == 0.0:
+            assert abs(h["t"] - t_plane) <= 1e-12 * t_plane
+        else:
+            # the finite root of the quadratic, which approaches the tangent
+            # plane's as A -> 0
             roots = np.roots([h["A"], h["B"], h["C"]])
             t_exact = roots[np.argmin(np.abs(roots - t_plane))].real
+            assert abs(h["t"] - t_exact) <= 1e-10 * t_exact
             assert abs(t_exact - t_plane) <= 50 * abs(h["A"]) * t_plane ** 2 / abs(h["B"])
+            assert abs(h["t"] - t_plane) > 0.0
+        # the diverging root, far beyond the support, is not a candidate
+        assert abs(h["t"]) < 100.0
 
 
 def test_head_on_closed_form():
@@ -438,8 +447,9 @@ def test_backward_matches_finite_differences(seed):
         dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)),
               rng.standard_normal((16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((16, 16)))
         ks = oracle.keys(sc, cam)
-        base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2)
-        if base["margin"].min() >= 1.0 and base["n_blend"].max() >= min(n, 2):
+        base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2, branch_median=True)
+        if (base["margin"].min() >= 1.0 and base["gmargin"].min() >= 1.0 and
+                base["n_blend"].max() >= min(n, 2)):
             break
     else:
         pytest.fail("no base point away from decision boundaries")
@@ -466,10 +476,10 @@ def test_backward_matches_finite_differences(seed):
                 fd.reshape(n, -1)[p, j] = (loss(plus) - loss(minus)) / (2 * hstep)
         scale = np.abs(fd).max() + 1e-12
         err = np.abs(an.reshape(fd.shape) - fd)
-        tol = 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9
+        tol = 1e-6 * (np.abs(fd) + 1e-2 * scale) + 1e-9
         assert np.all(err <= tol), (key, an, fd)
         worst = max(worst, float((err / (np.abs(fd) + 1e-2 * scale)).max()))
-    assert worst < 1e-5
+    assert worst < 1e-6
 
 
 # --------------------------------------------------------------------------
@@ -1036,8 +1046,8 @@ def test_full_model_backward_matches_finite_differences(seed):
         dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)),
               rng.standard_normal((16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((16, 16)))
         ks = oracle.keys(sc, cam)
-        base = oracle.render(sc, cam, opts=opts, dL=dL, key_stage=ks, delta=strict, nthreads=2)
-        if base["margin"].min() >= 1.0 and base["n_blend"].max() >= 3:
+        base = oracle.render(sc, cam, opts=opts, dL=dL, key_stage=ks, delta=strict, nthreads=2, branch_median=True)
+        if base["margin"].min() >= 1.0 and base["gmargin"].min() >= 1.0 and base["n_blend"].max() >= 3:
             break
     else:
         pytest.fail("no base point away from decision boundaries")
@@ -1063,7 +1073,7 @@ def test_full_model_backward_matches_finite_differences(seed):
                 fd.reshape(n, -1)[p, j] = (loss(plus) - loss(minus)) / (2 * hstep)
         scale = np.abs(fd).max() + 1e-12
         err = np.abs(an.reshape(fd.shape) - fd)
-        tol = 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9
+        tol = 1e-6 * (np.abs(fd) + 1e-2 * scale) + 1e-9
         assert np.all(err <= tol), (key, an, fd)
 
 
@@ -1140,7 +1150,7 @@ def test_sh_backward_matches_finite_differences(seed, deg):
         dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)))
         ks = oracle.keys(sc, cam)
         base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2)
-        if base["margin"].min() >= 1.0 and base["n_blend"].max() >= 2:
+        if base["margin"].min() >= 1.0 and base["gmargin"].min() >= 1.0 and base["n_blend"].max() >= 2:
             break
     else:
         pytest.fail("no base point away from decision boundaries")
@@ -1162,4 +1172,4 @@ def test_sh_backward_matches_finite_differences(seed, deg):
             minus[ki].reshape(-1)[j] -= h
             fd.reshape(-1)[j] = (loss(plus) - loss(minus)) / (2 * h)
         scale = np.abs(fd).max() + 1e-12
-        assert np.all(np.abs(an - fd) <= 1e-5 * (np.abs(fd) + 1e-2 * scale) + 1e-9), key
+        assert np.all(np.abs(an - fd) <= 1e-6 * (np.abs(fd) + 1e-2 * scale) + 1e-9), key
