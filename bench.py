@@ -98,10 +98,11 @@ def parse():
                     help="the k-sigma local box without the chord bound (QGS_TIGHT_BOUND off)")
     ap.add_argument("--cpu-rows", type=int, default=1200, help="rows of view 0 the CPU oracle renders (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-quick", action="store_true", help="only the all-thread oracle timing of view 0")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-no-graphs", action="store_true", help="serving with direct launches instead of graphs")
     ap.add_argument("--full-model", action="store_true",
                     help="the paper's full-model ordering (per-tile sort depth and the 8-entry resort buffer)")
@@ -320,28 +321,104 @@ def main():
     }
 
     if not args.no_cpu_baseline and args.cpu_rows > 0:
-        import oracle
-        cam = cams[0]
-        rows = min(args.cpu_rows, H)
-        y0 = (H - rows) // 2
-        win = (0, y0, W, rows)
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-        threads = min(threads, os.cpu_count() or threads)
-        dl = scenes.upstream_grads(0, H, W)
-        t = time.perf_counter()
-        ks = oracle.keys(cfg.scene, cam)
-        oracle.render(cfg.scene, cam, window=win, key_stage=ks, nthreads=threads, dL=dl)
-        dt = time.perf_counter() - t
-        result["cpu_baseline"] = {"value": round(W * rows / dt / 1e6, 5), "unit": "Mpix/s", "cores": threads,
-                                  "kind": "oracle",
-                                  "sample": f"view 0, rows {y0}-{y0 + rows - 1} ({W}x{rows} px), key stage + "
-                                            f"FP64 forward + backward, {dt:.1f}s"}
-        log(f"[bench] cpu oracle {result['cpu_baseline']}", q)
+        result["cpu_baseline"], result["units_pin"] = cpu_baseline(args, cfg, cams, cnt_r, sc_t, mode, q)
 
     if not args.no_serve and args.serve_requests > 0:
         result["serving"] = bench_serving(args, dev, q)
 
     print(json.dumps(result), flush=True)
+
+
+def oracle_entries_processed(oracle, ks, cam, stop_id):
+    """E of one view from the oracle: per pixel, the entries of its tile's
+    list (the key stage's sorted lists, bit-identical to the GPU's) up to and
+    including the one it stopped at, or the whole list."""
+    import numpy as np
+    keys_, prims, ranges = oracle.bin_sort(ks, cam)
+    n = len(ks["tiles"])
+    tile = (keys_ >> np.uint64(32)).astype(np.int64)
+    pos = np.arange(len(prims), dtype=np.int64) - ranges[tile, 0].astype(np.int64)
+    combo = tile * n + prims.astype(np.int64)
+    order = np.argsort(combo)
+    combo_s = combo[order]
+    H, W = stop_id.shape
+    py, px = np.mgrid[0:H, 0:W]
+    t = (py // 16) * cam.tiles_x + px // 16
+    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    e = lens[t].copy()
+    st = stop_id >= 0
+    idx = np.searchsorted(combo_s, t[st] * n + stop_id[st])
+    assert np.array_equal(combo_s[idx], t[st] * n + stop_id[st]), "stopping primitive not in its tile's list"
+    e[st] = pos[order[idx]] + 1
+    return int(e.sum())
+
+
+def cpu_baseline(args, cfg, cams, cnt_r, sc_t, mode, q):
+    """The FP64 oracle timed on the host (forward + backward of view 0, all
+    threads), plus its work units pinned against the forward's counters on the
+    same view: E (list entries processed up to and including each pixel's
+    stop) and the pairs blended."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2411_16392_amd import scenes
+
+    cam = cams[0]
+    W, H = cam.width, cam.height
+    rows = min(args.cpu_rows, H)
+    y0 = (H - rows) // 2
+    win = (0, y0, W, rows)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = min(threads, os.cpu_count() or threads)
+    dl = scenes.upstream_grads(0, H, W)
+    oo = dict(resort=8, tile_depth=True) if mode else None
+    t = time.perf_counter()
+    # the key stage with the bound the GPU lists were built with (E counts list entries)
+    ks = oracle.keys(cfg.scene, cam, tight=not args.loose_bound)
+    o = oracle.render(cfg.scene, cam, opts=oo, window=win, key_stage=ks, nthreads=threads, dL=dl)
+    dt = time.perf_counter() - t
+    base = {"value": round(W * rows / dt / 1e6, 5), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": f"view 0, rows {y0}-{y0 + rows - 1} ({W}x{rows} px), key stage + FP64 forward + backward, "
+                      f"{dt:.1f}s"}
+    log(f"[bench] cpu oracle {base}", q)
+    pin = None
+    if rows == H and not mode:
+        st = cnt_r.forward(sc_t, cam, exact=False)
+        torch.cuda.synchronize()
+        c = st.counters.cpu().numpy().view(np.uint32)
+        e_gpu, bl_gpu = int(c[2]), int(c[4])
+        e_or = oracle_entries_processed(oracle, ks, cam, o["stop_id"])
+        bl_or = int(o["n_blend"].sum())
+        near = int((o["margin"] < 1.0).sum())
+        pin = {"view": 0, "E_gpu": e_gpu, "E_oracle": e_or, "blended_gpu": bl_gpu, "blended_oracle": bl_or,
+               "E_ratio": round(e_gpu / max(e_or, 1), 7), "blended_ratio": round(bl_gpu / max(bl_or, 1), 7),
+               "near_tied_pixels": near,
+               "note": "the two may differ only on pixels with a near-tied decision"}
+        log(f"[bench] units pinned against the oracle: {pin}", q)
+    if not args.cpu_quick:
+        # the oracle's throughput on one host thread (a band of rows of the
+        # same view) and on the 100K-quadric sphere at 800 x 600 (full frame,
+        # all threads, and a band on one thread)
+        runs = []
+        c1 = scenes.make_config(1)
+        cam1 = c1.cameras[0]
+        ks1 = oracle.keys(c1.scene, cam1, tight=not args.loose_bound)
+        dl1 = scenes.upstream_grads(0, cam1.height, cam1.width)
+        for label, sc, cm, kk, dd, nthr, nrows in (
+                ("500K quadrics 1600x1200 view 0", cfg.scene, cam, ks, dl, 1, max(1, H // 16)),
+                ("100K quadrics 800x600", c1.scene, cam1, ks1, dl1, threads, cam1.height),
+                ("100K quadrics 800x600", c1.scene, cam1, ks1, dl1, 1, cam1.height // 16)):
+            yy = (cm.height - nrows) // 2
+            t = time.perf_counter()
+            r = oracle.render(sc, cm, opts=oo, window=(0, yy, cm.width, nrows), key_stage=kk, nthreads=nthr,
+                              dL=dd)
+            d = time.perf_counter() - t
+            runs.append({"workload": label, "threads": nthr, "rows": nrows, "s": round(d, 2),
+                         "Mpix_s": round(cm.width * nrows / d / 1e6, 5), "evals_per_s": round(r["evals"] / d, 1)})
+        base["more"] = runs
+        log(f"[bench] cpu oracle, more: {runs}", q)
+    return base, pin
 
 
 def bench_serving(args, dev, q):
@@ -373,14 +450,42 @@ def bench_serving(args, dev, q):
     s_s = serve.latency_summary(seq["latency"][n_warm:])
     log(f"[bench] one at a time: {seq['frames_per_s']:.1f} frames/s, {s_s}", q)
     # saturation: the same request mix with every request arriving at once
-    # (the client keeps at most 48 output buffers per resolution in flight)
+    # (the client keeps at most 48 output buffers per resolution in flight);
+    # latency is arrival to completion, so it includes the queueing
     n2 = max(200, n_req // 2)
     trace2 = scenes.serve_trace(n2 + 50, rate_hz=1e7, seed=5)
     with serve.Server(sc_t, budget_bytes=budget, max_slots=8, n_streams=4, graphs=graphs) as srv:
         res2 = serve.run_trace(srv, trace2)
     seq2 = serve.run_sequential(sc_t, trace2)
-    log(f"[bench] saturated: batched {res2['frames_per_s']:.1f} frames/s, one at a time "
-        f"{seq2['frames_per_s']:.1f} frames/s", q)
+    s2b = serve.latency_summary(res2["latency"][50:])
+    s2s = serve.latency_summary(seq2["latency"][50:])
+    log(f"[bench] saturated: batched {res2['frames_per_s']:.1f} frames/s {s2b}, one at a time "
+        f"{seq2['frames_per_s']:.1f} frames/s {s2s}", q)
+    # small views alone: does one request fill the chip?  Device time of one
+    # view rendered alone (events around preprocess, count + sort and forward
+    # on one stream) against the batched throughput of a saturated trace of
+    # such views; fill = batched frames/s x device time per view, above 1 when
+    # overlapping requests gets more out of the chip than one request does
+    small = {}
+    for wh in ((256, 256), (512, 384)):
+        tr = scenes.serve_trace(400, rate_hz=1e7, seed=6, sizes=[wh])
+        r1 = R.Renderer(device=dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for k, (_, cam) in enumerate(tr[:60]):
+            ev0.record()
+            r1.forward(sc_t, cam, exact=True)
+            ev1.record()
+            torch.cuda.synchronize()
+            if k >= 10:
+                times.append(ev0.elapsed_time(ev1))
+        t_alone = float(np.median(times))
+        with serve.Server(sc_t, budget_bytes=budget, max_slots=8, n_streams=4, graphs=graphs) as srv:
+            rs = serve.run_trace(srv, tr)
+        small[f"{wh[0]}x{wh[1]}"] = {"device_ms_alone": round(t_alone, 4),
+                                     "batched_frames_per_s": round(rs["frames_per_s"], 1),
+                                     "fill": round(rs["frames_per_s"] * t_alone * 1e-3, 3)}
+    log(f"[bench] small views: {small}", q)
     torch.cuda.synchronize()
     return {"workload": "1M quadrics (shells + background ball), Poisson 500/s, views 256x256 / 512x384 / "
                         "1280x720 / 1920x1080, colour only",
@@ -394,8 +499,12 @@ def bench_serving(args, dev, q):
             "one_at_a_time": {"frames_per_s": round(seq["frames_per_s"], 2), "p50_ms": round(s_s["p50_ms"], 3),
                               "p99_ms": round(s_s["p99_ms"], 3), "mean_ms": round(s_s["mean_ms"], 3)},
             "saturated": {"requests": n2 + 50, "frames_per_s": round(res2["frames_per_s"], 2),
+                          "p50_ms": round(s2b["p50_ms"], 3), "p99_ms": round(s2b["p99_ms"], 3),
                           "one_at_a_time_frames_per_s": round(seq2["frames_per_s"], 2),
-                          "all_done": bool((res2["state"] == 0).all())}}
+                          "one_at_a_time_p50_ms": round(s2s["p50_ms"], 3),
+                          "one_at_a_time_p99_ms": round(s2s["p99_ms"], 3),
+                          "all_done": bool((res2["state"] == 0).all())},
+            "small_views": small}
 
 
 if __name__ == "__main__":

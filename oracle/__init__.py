@@ -65,7 +65,7 @@ def _lib():
                                     i32, i32, i32, i32, i32,
                                     P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P,
                                     P, i32, P,
-                                    i32, i64, P, P, P, P, P, i32]
+                                    i32, i64, P, P, P, P, P, i32, P]
         L.oracle_render.restype = i64
         L.oracle_render_alts.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, i32, i32, P, P,
                                          i32, i32, i32, i32, i32, P, i32, i32,
@@ -251,14 +251,15 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
     ambiguous derivative) contribute no gradient.
     Returns a dict of window-sized FP64 maps (colour, depth, normal, curvature, median depth,
     depth distortion, final transmittance, blend count, decision margin, gradient margin,
-    near-tie kinds as bits of KINDS) and, with dL, parameter gradients.
+    near-tie kinds as bits of KINDS, the primitive at which the pixel stopped or -1) and, with
+    dL, parameter gradients.
     """
     head, (x0, y0, w, h), sh, sh64, sh_deg, keep = _render_inputs(scene, cam, opts, window, params64, key_stage,
                                                                   delta, cam_vec64)
     n = scene.n
     color = np.zeros((3, h, w)); depth = np.zeros((h, w)); normal = np.zeros((3, h, w))
     T = np.zeros((h, w)); nb = np.zeros((h, w), np.int32); margin = np.zeros((h, w))
-    gmargin = np.zeros((h, w)); kinds = np.zeros((h, w), np.uint16)
+    gmargin = np.zeros((h, w)); kinds = np.zeros((h, w), np.uint16); stop_id = np.zeros((h, w), np.int64)
     curvature = np.zeros((h, w)); median = np.zeros((h, w)); dist = np.zeros((h, w))
     if nthreads is None:
         nthreads = os.cpu_count() or 1
@@ -288,13 +289,14 @@ def render(scene, cam, opts=None, window=None, dL=None, nthreads=None, params64=
                               _ptr(curvature), _ptr(median), _ptr(dist), *gp,
                               _ptr(sh64) if sh64 is not None else None, sh_deg,
                               _ptr(grads["sh"]) if (grads is not None and sh is not None) else None,
-                              int(bool(branch_median)), *fargs, _ptr(gmargin), _ptr(kinds), int(bool(grad_skip)))
+                              int(bool(branch_median)), *fargs, _ptr(gmargin), _ptr(kinds), int(bool(grad_skip)),
+                              _ptr(stop_id))
     del keep
     if ev < 0:
         raise ValueError("bad window")
     out = dict(color=color, depth=depth, normal=normal, curvature=curvature, median_depth=median,
                distortion=dist, T_final=T, n_blend=nb, margin=margin, gmargin=gmargin, kinds=kinds,
-               evals=int(ev))
+               stop_id=stop_id, evals=int(ev))
     if grads is not None:
         out["grads"] = grads
     return out

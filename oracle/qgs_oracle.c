@@ -1084,8 +1084,8 @@ static void entry_backward(const oprim *P, const ohit *H, double flip, const dou
    the forced outcomes of near-tied decisions and receives every margin. */
 static void render_pixel(const obins *B, const double *cam, const double *opts, const double *delta, octl *ctl,
                          int px, int py, int cell, double out[NCH], double *T_out, int32_t *nb_out,
-                         int64_t *evals, const double g[NCH], int grad_skip, ograd *grads, oentry **scratch,
-                         int *scratch_cap)
+                         int64_t *stop_out, int64_t *evals, const double g[NCH], int grad_skip, ograd *grads,
+                         oentry **scratch, int *scratch_cap)
 {
     double dcam[3];
     pixel_ray(cam, px, py, dcam);
@@ -1115,6 +1115,7 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
     int do_bwd = 0;
     if (g)
         for (int c = 0; c < NCH; ++c) do_bwd |= g[c] != 0.0;
+    if (stop_out) *stop_out = -1;
     /* per-pixel resort (supplement, per-pixel resorting): accepted hits wait in
        a buffer of K entries; whenever it is full the nearest (smallest t, the
        earliest arrival among equal t) is blended, and at the end of the list
@@ -1171,6 +1172,7 @@ static void render_pixel(const obins *B, const double *cam, const double *opts, 
                              ctl_flip(ctl, mscale(fabs(Tn - opts[O_TEPS]) / opts[O_TEPS], delta, M_T), M_T);
             if (stop) {
                 stopped = 1;
+                if (stop_out) *stop_out = B->ids[en.list];
                 break;
             }
             const double w = alpha * T;
@@ -1419,8 +1421,9 @@ static unsigned forward_kinds(int branch_median)
  * Outputs (window-sized, planar): color[3][h][w], depth, normal[3][h][w],
  * T_final, n_blend (entries blended), margin (min over the decisions of the
  * kinds forward_kinds(branch_median) selects of the scaled distance to the
- * boundary), optional gmargin (the same over GRAD_KINDS) and kind_bits (bit k
- * set where kind k has a margin below 1).
+ * boundary), optional gmargin (the same over GRAD_KINDS), kind_bits (bit k
+ * set where kind k has a margin below 1) and stop_id (the primitive at which
+ * the pixel stopped, -1 if it did not).
  * Near-tied decisions of the window pixels forced[i] (row-major index in the
  * window, i < n_forced) take the outcomes forced_path[i * OPATH_MAX ...] of
  * their first forced_len[i] branch points (see octl).
@@ -1443,7 +1446,8 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
                       double *g_center, double *g_quat, double *g_scale, double *g_curv,
                       double *g_opac, double *g_rgb, const double *sh, int32_t sh_deg, double *g_sh,
                       int32_t branch_median, int64_t n_forced, const int32_t *forced, const uint8_t *forced_path,
-                      const int32_t *forced_len, double *gmargin, uint16_t *kind_bits, int32_t grad_skip)
+                      const int32_t *forced_len, double *gmargin, uint16_t *kind_bits, int32_t grad_skip,
+                      int64_t *stop_id)
 {
     if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > width || y0 + h > height) return -1;
     const double *W = cam, *T = cam + 9;
@@ -1510,8 +1514,9 @@ int64_t oracle_render(int64_t n, const double *center, const double *quat, const
                              forced_len[fi] < OPATH_MAX ? forced_len[fi] : OPATH_MAX);
                 else
                     ctl_init(&ctl, fkinds, NULL, 0);
-                render_pixel(&Bn, cam, opts, delta, &ctl, x0 + i, y0 + j, cell, out, &Tf, &nb, &ev,
-                             do_bwd ? gg : NULL, grad_skip, mine, &scratch, &cap);
+                render_pixel(&Bn, cam, opts, delta, &ctl, x0 + i, y0 + j, cell, out, &Tf, &nb,
+                             stop_id ? stop_id + pix : NULL, &ev, do_bwd ? gg : NULL, grad_skip, mine, &scratch,
+                             &cap);
                 mg = ctl_margin(&ctl, fkinds);
                 if (gmargin) gmargin[pix] = ctl_margin(&ctl, GRAD_KINDS);
                 if (kind_bits) {
@@ -1686,8 +1691,8 @@ int64_t oracle_render_alts(int64_t n, const double *center, const double *quat, 
                 ctl_init(&ctl, fkinds, node, L);
                 double out[NCH], Tf;
                 int32_t nb;
-                render_pixel(&Wn.B, cam, opts, delta, &ctl, px, py, cell, out, &Tf, &nb, &ev, NULL, 0, NULL, NULL,
-                             NULL);
+                render_pixel(&Wn.B, cam, opts, delta, &ctl, px, py, cell, out, &Tf, &nb, NULL, &ev, NULL, 0, NULL,
+                             NULL, NULL);
                 int m = ctl.seen;
                 if (m > OPATH_MAX) { ovf = 1; m = OPATH_MAX; }
                 const size_t r = (size_t)i * (size_t)max_leaves + (size_t)leaves;

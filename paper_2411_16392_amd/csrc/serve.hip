@@ -53,6 +53,7 @@ struct Req {
     double t_submit = 0, t_admit = 0;
     uint64_t pairs = 0;
     bool cancelled = false;
+    bool admitting = false;  // taken by the scheduler for admission: no longer cancellable
     size_t mem_off = 0, mem_bytes = 0;
 };
 
@@ -311,10 +312,16 @@ void scheduler(qgs_server *s)
         // 1. observe finished device work
         for (auto &sl : s->slots) {
             if (sl.phase != COUNTING && sl.phase != RENDERING) continue;
-            if (hipEventQuery(sl.ev) != hipSuccess) continue;
+            const hipError_t q = hipEventQuery(sl.ev);
+            if (q == hipErrorNotReady) continue;
             progressed = true;
             Req &r = *sl.req;
-            if (sl.phase == COUNTING) {
+            if (q != hipSuccess) {
+                // the slot's device work failed: the request fails with the
+                // HIP error, its memory and slot are released
+                if (sl.phase == RENDERING) s->pool.release(r.mem_off, r.mem_bytes);
+                complete(s, r, QGS_REQ_FAILED, QGS_ERR_HIP);
+            } else if (sl.phase == COUNTING) {
                 r.pairs = sl.counters_host[0];
                 bool cancelled;
                 {
@@ -349,8 +356,11 @@ void scheduler(qgs_server *s)
             Req &r = *oldest->req;
             bool cancelled;
             {
+                // the cancel check and the mark that ends cancellability in
+                // one critical section: a cancel after it returns QGS_ERR_STATE
                 std::lock_guard<std::mutex> g(s->mu);
                 cancelled = r.cancelled;
+                if (!cancelled) r.admitting = true;
             }
             if (cancelled) {
                 complete(s, r, QGS_REQ_CANCELLED, QGS_OK);
@@ -361,7 +371,12 @@ void scheduler(qgs_server *s)
                 continue;
             }
             r.mem_bytes = list_bytes(r.pairs);
-            if (!s->pool.alloc(r.mem_bytes, r.mem_off)) break;  // keep arrival order
+            if (!s->pool.alloc(r.mem_bytes, r.mem_off)) {
+                // not admitted yet (keep arrival order): cancellable again
+                std::lock_guard<std::mutex> g(s->mu);
+                r.admitting = false;
+                break;
+            }
             {
                 std::lock_guard<std::mutex> g(s->mu);
                 r.t_admit = s->now();
@@ -556,7 +571,7 @@ qgs_status qgs_serve_cancel(qgs_server *s, uint64_t id)
         if (!hit) {
             // in a slot: cancellable until admitted for rendering; the scheduler
             // completes it when it next looks at the slot
-            if (lv->second->t_admit > 0) return QGS_ERR_STATE;
+            if (lv->second->admitting || lv->second->t_admit > 0) return QGS_ERR_STATE;
             lv->second->cancelled = true;
             return QGS_OK;
         }

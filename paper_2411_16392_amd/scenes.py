@@ -345,16 +345,17 @@ def make_config(i: int, seed: int | None = None, n_override: int | None = None,
     raise ValueError(f"no workload {i}")
 
 
-def serve_trace(n_requests: int, rate_hz: float = 500.0, seed: int = 4, radius: float = 3.0):
+def serve_trace(n_requests: int, rate_hz: float = 500.0, seed: int = 4, radius: float = 3.0, sizes=None):
     """Poisson arrival trace: list of (arrival_s, Camera), resolutions drawn
-    uniformly from RESOLUTIONS_SERVE, eyes uniform on a sphere looking at the
-    origin."""
+    uniformly from `sizes` (default RESOLUTIONS_SERVE), eyes uniform on a
+    sphere looking at the origin."""
+    sizes = RESOLUTIONS_SERVE if sizes is None else list(sizes)
     rng = np.random.Generator(np.random.PCG64(2000 + seed))
     gaps = rng.exponential(1.0 / rate_hz, size=n_requests)
     arr = np.cumsum(gaps)
     out = []
     for k in range(n_requests):
-        w, h = RESOLUTIONS_SERVE[int(rng.integers(0, len(RESOLUTIONS_SERVE)))]
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
         eye = unit_vectors(rng, 1)[0] * radius
         out.append((float(arr[k]), look_at(eye, width=w, height=h, f=w)))
     return out

@@ -59,9 +59,12 @@ def window_of(st, window, geometry=False):
 
 
 def _stack(m, geometry):
-    """[11, h, w] in oracle.ALT_CHANNELS order (geometry maps zero if absent)."""
-    h, w = m["depth"].shape
+    """[11, h, w] in oracle.ALT_CHANNELS order (maps a colour-only image lacks,
+    and the geometry maps unless asked for, are zero)."""
+    h, w = m["color"].shape[1:]
     z = np.zeros((h, w))
+    if "depth" not in m:
+        return np.stack([m["color"][0], m["color"][1], m["color"][2]] + [z] * 8).astype(np.float64)
     geo = [m.get("curvature", z), m.get("median_depth", z), m.get("distortion", z)] if geometry else [z, z, z]
     return np.stack([m["color"][0], m["color"][1], m["color"][2], m["depth"], m["normal"][0], m["normal"][1],
                      m["normal"][2], *geo, m["T_final"]]).astype(np.float64)
@@ -77,17 +80,18 @@ def _ratios(G, O, chans):
 
 
 def check_forward(g, scene, cam, window=None, opts=None, ks=None, geometry=False, label="", nthreads=None,
-                  max_excluded=None):
+                  max_excluded=None, color_only=False):
     """g: GPU maps of the window (window_of).  Checks every pixel as the module
     docstring says and returns (report, forced, oracle result): report holds
     the largest error per channel over all pixels (against the matched
     result), `excluded` (share of pixels with a near-tied decision),
     `alt_taken` (share matching a result other than the oracle's own),
     `unchecked` (pixels whose enumeration was cut short and matched none) and
-    `unmatched`; forced = (pixels, paths, lengths) of the matched results."""
+    `unmatched`; forced = (pixels, paths, lengths) of the matched results.
+    color_only: g holds only "color" (a served image), the one map compared."""
     win = window if window is not None else (0, 0, cam.width, cam.height)
     o = oracle.render(scene, cam, opts=opts, window=win, key_stage=ks, branch_median=geometry, nthreads=nthreads)
-    chans = _CH_BASE + (_CH_GEO if geometry else [])
+    chans = _CH_BASE[:3] if color_only else _CH_BASE + (_CH_GEO if geometry else [])
     G = _stack(g, geometry)
     O = _stack(o, geometry)
     C, h, w = G.shape

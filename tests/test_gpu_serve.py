@@ -1,5 +1,6 @@
-"""Serving: results in the mix equal results alone; admission by memory;
-cancellation; budget refusal; a Poisson trace completes."""
+"""Serving: served images against the FP64 oracle; results in the mix equal
+results alone; admission by memory; cancellation; budget refusal; a Poisson
+trace completes."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +10,18 @@ from paper_2411_16392_amd import render as R
 from paper_2411_16392_amd import scenes
 from paper_2411_16392_amd import serve
 
+from gpu_helpers import check_forward
+
 pytestmark = pytest.mark.gpu
+
+
+_SCENE = {}
+
+
+def _scene():
+    if "s" not in _SCENE:
+        _SCENE["s"] = scenes.scene_unbounded(200_000, 4)
+    return _SCENE["s"]
 
 
 @pytest.fixture(scope="module")
@@ -17,8 +29,7 @@ def scene_t():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     L.lib()
-    sc = scenes.scene_unbounded(200_000, 4)
-    return R.scene_to_device(sc)
+    return R.scene_to_device(_scene())
 
 
 def _views(n, seed):
@@ -146,3 +157,32 @@ def test_poisson_trace_completes(scene_t):
     for i, img in res["kept"].items():
         ref, _ = _alone(scene_t, trace[i][1])
         assert float((img - ref).abs().max()) <= 1e-6
+
+
+def test_served_images_match_the_oracle(scene_t):
+    # served colour against the FP64 oracle, every pixel of a 256 x 256 view
+    # and crops of 1280 x 720 and 1920 x 1080 views (centre and a corner),
+    # requests overlapping in the server
+    sc = _scene()
+    rng = np.random.default_rng(17)
+    cams = []
+    for (w, h) in ((256, 256), (1280, 720), (1920, 1080)):
+        eye = scenes.unit_vectors(rng, 1)[0] * 3.0
+        cams.append(scenes.look_at(eye, width=w, height=h, f=w))
+    outs = [torch.full((3, c.height, c.width), -1.0, device="cuda") for c in cams]
+    with serve.Server(scene_t, budget_bytes=2 << 30, max_slots=4, n_streams=4) as srv:
+        ids = [srv.submit(c, o) for c, o in zip(cams, outs)]
+        got = _drain(srv, len(ids))
+    assert all(got[i][0] == L.QGS_REQ_DONE for i in ids)
+    for cam, out in zip(cams, outs):
+        img = out.cpu().numpy()
+        if cam.width == 256:
+            wins = [(0, 0, 256, 256)]
+        else:
+            wins = [(cam.width // 2 - 32, cam.height // 2 - 32, 64, 64), (cam.width - 48, cam.height - 40, 48, 40)]
+        for win in wins:
+            x0, y0, w, h = win
+            g = dict(color=img[:, y0:y0 + h, x0:x0 + w])
+            rep, _, _ = check_forward(g, sc, cam, win, color_only=True, label=f"served {cam.width}x{cam.height} {win}",
+                                      max_excluded=0.02)
+            print("served", cam.width, cam.height, win, rep)
