@@ -102,7 +102,7 @@ __device__ inline void load_prim(const float *w, const RasterParams &P, Prim &p)
 // from the integer + fraction split of u_c (exact to the rounding of a small
 // number), and the conic pre-test: false means the pixel's ray misses the
 // ellipsoid that encloses the support.
-__device__ inline bool conic_offsets(const float *w, const PixelRay &r, float &dxp, float &dyp)
+__host__ __device__ inline bool conic_offsets(const float *w, const PixelRay &r, float &dxp, float &dyp)
 {
     const float4 a = *reinterpret_cast<const float4 *>(w + 4);
     dxp = (r.fpx - a.x) + a.y;
@@ -113,6 +113,48 @@ __device__ inline bool conic_offsets(const float *w, const PixelRay &r, float &d
     const float fy_ = __builtin_fmaf(c2.x, dyp, c2.z);
     const float f = __builtin_fmaf(fx_, dxp, __builtin_fmaf(fy_, dyp, -1.0f));
     return f <= CONIC_SLACK;
+}
+
+// Conservative test of the pre-test conic of conic_offsets against the 8 x 8
+// pixel block whose top-left pixel is (bx, by): false only where no pixel of
+// the block can pass the pre-test.  In pixel offsets from the projected
+// centre the conic is f = a x^2 + b x y + c y^2 + d x + e y - 1, which is -1
+// at the origin.  With a, c > 0, each connected part of {f <= t} either holds
+// the origin (it is convex if f is) or is unbounded, so unless the origin lies
+// in the block's box of offsets the set meets the box only across the box's
+// boundary; on each of the four edges f is a convex quadratic of one variable,
+// smallest at its clamped vertex.  FP32 rounding of these minima and of the
+// per-pixel values stays below 2^-19 of the sum of absolute terms over the
+// box, which the threshold adds.  (Host-callable, like conic_offsets, for the
+// brute-force check of this bound over the pixels of a block.)
+__host__ __device__ inline bool conic_meets_block(const float4 *__restrict__ rec, float bx, float by)
+{
+    const float4 cu = rec[1];  // record words 4..7: U, 0.5 - frac(u_c), V, 0.5 - frac(v_c)
+    const float2 ab = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(rec) + 14);
+    const float4 cz = rec[7];  // words 28..31: c, d, e, zl
+    const float X0 = (bx - cu.x) + cu.y, X1 = X0 + 7.0f;
+    const float Y0 = (by - cu.z) + cu.w, Y1 = Y0 + 7.0f;
+    const float a = ab.x, b = ab.y, c = cz.x, d = cz.y, e = cz.z;
+    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+    if (!(a > 0.0f && c > 0.0f)) return true;
+    const float ha = 0.5f / a, hc = 0.5f / c;  // once per batch entry: plain divisions
+    float fmin;
+    {
+        // edges x = X0, X1: vertex at y = -(b X + e) / (2 c)
+        const float y0 = fminf(fmaxf(-__builtin_fmaf(b, X0, e) * hc, Y0), Y1);
+        const float y1 = fminf(fmaxf(-__builtin_fmaf(b, X1, e) * hc, Y0), Y1);
+        const float f0 = __builtin_fmaf(__builtin_fmaf(a, X0, __builtin_fmaf(b, y0, d)), X0, __builtin_fmaf(__builtin_fmaf(c, y0, e), y0, -1.0f));
+        const float f1 = __builtin_fmaf(__builtin_fmaf(a, X1, __builtin_fmaf(b, y1, d)), X1, __builtin_fmaf(__builtin_fmaf(c, y1, e), y1, -1.0f));
+        // edges y = Y0, Y1: vertex at x = -(b Y + d) / (2 a)
+        const float x0 = fminf(fmaxf(-__builtin_fmaf(b, Y0, d) * ha, X0), X1);
+        const float x1 = fminf(fmaxf(-__builtin_fmaf(b, Y1, d) * ha, X0), X1);
+        const float f2 = __builtin_fmaf(__builtin_fmaf(a, x0, __builtin_fmaf(b, Y0, d)), x0, __builtin_fmaf(__builtin_fmaf(c, Y0, e), Y0, -1.0f));
+        const float f3 = __builtin_fmaf(__builtin_fmaf(a, x1, __builtin_fmaf(b, Y1, d)), x1, __builtin_fmaf(__builtin_fmaf(c, Y1, e), Y1, -1.0f));
+        fmin = fminf(fminf(f0, f1), fminf(f2, f3));
+    }
+    const float xm = fmaxf(__builtin_fabsf(X0), __builtin_fabsf(X1)), ym = fmaxf(__builtin_fabsf(Y0), __builtin_fabsf(Y1));
+    const float S = __builtin_fmaf(a * xm, xm, __builtin_fmaf(__builtin_fabsf(b) * xm, ym, __builtin_fmaf(c * ym, ym, __builtin_fmaf(__builtin_fabsf(d), xm, __builtin_fmaf(__builtin_fabsf(e), ym, 1.0f)))));
+    return fmin <= __builtin_fmaf(0x1p-19f, S, CONIC_SLACK);
 }
 
 // arc-length factor g(u) = l / rho for u = 2 |a| rho (geodesic equation, Sec.

@@ -5,7 +5,9 @@
 // it.  The waves walk the tile's list independently, without LDS or barriers:
 // 64 entries at a time, lane i fetches entry b + i's primitive id and pixel
 // rectangle (one batch ahead), a ballot keeps the entries whose rectangle
-// meets the wave's block, and only those are visited.  A visited entry's
+// meets the wave's block, and only those are visited; the forwards also drop
+// entries whose pre-test conic misses the block (conic_meets_block, one test
+// per lane and batch instead of a wave step per entry).  A visited entry's
 // 128-byte record is read with a wave-uniform address, i.e. by scalar loads
 // into scalar registers, once per wave.  Each lane first applies the conic
 // pre-test (no per-lane rectangle test: it removed almost nothing the conic
@@ -138,8 +140,9 @@ __device__ inline size_t replay_base(uint32_t start, uint32_t len, int tile, int
 
 // Each wave walks its tile's list on its own, with no LDS and no barrier: the
 // list is read 64 entries at a time (lane i fetches entry b + i's primitive id
-// and pixel rectangle, one batch ahead), a ballot selects the entries whose
-// rectangle meets the wave's 8 x 8 block, and only those are visited.  A
+// two batches ahead and its pixel rectangle one batch ahead), a ballot selects
+// the entries whose rectangle and pre-test conic meet the wave's 8 x 8 block,
+// and only those are visited.  A
 // visited entry's record is read with a wave-uniform address, so it is
 // fetched once for the wave (scalar loads) and sits in scalar registers.
 // `recs` is a.records again and `replay` o.steps, as restrict arguments: the
@@ -177,22 +180,27 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
     uint32_t n_words = 0;
 
     // batch fetch: lane i holds entry b + i's primitive and rectangle
-    uint32_t nxt_pid = 0;
+    // primitive ids two batches ahead, rectangles one batch ahead
+    uint32_t nxt_pid = 0, nn_pid = 0;
     int4 nxt_rect = make_int4(0, -1, 0, -1);
     if ((uint32_t)lane < n) {
         nxt_pid = a.pair_prim[start + lane];
         nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
     }
+    if (64u + (uint32_t)lane < n) nn_pid = a.pair_prim[start + 64 + lane];
     bool wave_alive = __ballot(!done) != 0ull;
     for (uint32_t b = 0; b < n && wave_alive; b += 64) {
         const uint32_t cur_pid = nxt_pid;
         const int4 cur_rect = nxt_rect;
-        if (b + 64 + (uint32_t)lane < n) {
-            nxt_pid = a.pair_prim[start + b + 64 + lane];
-            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
-        }
-        const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
-                                                       cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        // entries whose rectangle and pre-test conic meet the block (the
+        // conic test's loads come before the next batch's, so waiting for
+        // them leaves those in flight)
+        bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                 cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        if (rel) rel = conic_meets_block(recs + (size_t)cur_pid * 8, (float)wx0, (float)wy0);
+        nxt_pid = nn_pid;
+        if (b + 64 + (uint32_t)lane < n) nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        if (b + 128 + (uint32_t)lane < n) nn_pid = a.pair_prim[start + b + 128 + lane];
         uint64_t m = __ballot(rel);
         uint64_t blended = 0ull;
         while (m != 0ull && wave_alive) {
@@ -802,22 +810,27 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
         ++n_blend;
     };
 
-    uint32_t nxt_pid = 0;
+    // primitive ids two batches ahead, rectangles one batch ahead
+    uint32_t nxt_pid = 0, nn_pid = 0;
     int4 nxt_rect = make_int4(0, -1, 0, -1);
     if ((uint32_t)lane < n) {
         nxt_pid = a.pair_prim[start + lane];
         nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
     }
+    if (64u + (uint32_t)lane < n) nn_pid = a.pair_prim[start + 64 + lane];
     bool wave_alive = __ballot(!done) != 0ull;
     for (uint32_t b = 0; b < n && wave_alive; b += 64) {
         const uint32_t cur_pid = nxt_pid;
         const int4 cur_rect = nxt_rect;
-        if (b + 64 + (uint32_t)lane < n) {
-            nxt_pid = a.pair_prim[start + b + 64 + lane];
-            nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
-        }
-        const bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
-                                                       cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        // entries whose rectangle and pre-test conic meet the block (the
+        // conic test's loads come before the next batch's, so waiting for
+        // them leaves those in flight)
+        bool rel = b + (uint32_t)lane < n && !(cur_rect.y < wx0 || cur_rect.x > wx0 + 7 ||
+                                                 cur_rect.w < wy0 || cur_rect.z > wy0 + 7);
+        if (rel) rel = conic_meets_block(recs + (size_t)cur_pid * 8, (float)wx0, (float)wy0);
+        nxt_pid = nn_pid;
+        if (b + 64 + (uint32_t)lane < n) nxt_rect = *reinterpret_cast<const int4 *>(recs + (size_t)nxt_pid * 8);
+        if (b + 128 + (uint32_t)lane < n) nn_pid = a.pair_prim[start + b + 128 + lane];
         uint64_t m = __ballot(rel);
         uint64_t taken = 0ull;
         while (m != 0ull && wave_alive) {
