@@ -38,12 +38,17 @@
 // Minimum number of waves per SIMD the compiler is asked to fit (0: no request).
 // For the forward, 7 makes the compiler keep the scalar registers to 94, which
 // lets 8 waves share a SIMD (about 100 would allow 7); asking for 8 costs
-// more instructions than the occupancy gains.
+// more instructions than the occupancy gains.  For the backward, 7 holds it
+// to 72 vector registers (7 waves per SIMD) without spills; the geometry
+// variant needs 88 and is left to the compiler (5).
 #ifndef QGS_FWD_MIN_WAVES
 #define QGS_FWD_MIN_WAVES 7
 #endif
 #ifndef QGS_BWD_MIN_WAVES
-#define QGS_BWD_MIN_WAVES 0
+#define QGS_BWD_MIN_WAVES 7
+#endif
+#ifndef QGS_BWD_GEO_MIN_WAVES
+#define QGS_BWD_GEO_MIN_WAVES 5
 #endif
 
 namespace qgs {
@@ -320,10 +325,11 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-// adjoint of one blended entry; adds into gr (the primitive's record
-// gradient).  dt: gradient with respect to the hit depth t; qn: the normal
-// map's upstream gradient in the local frame, Rc^T gn; dK (GEO): with respect
-// to the curvature value K at the hit.
+// adjoint of one blended entry: writes every field of gr (the entry's
+// contribution to the primitive's record gradient).  dt: gradient with
+// respect to the hit depth t; qn: the normal map's upstream gradient in the
+// local frame, Rc^T gn; dK (GEO): with respect to the curvature value K at
+// the hit.  Each sum starts from its first term (no addition to a zero).
 template <bool GEO>
 __device__ inline void entry_grad(const Prim &p, const float rgb[3], const PixelRay &ray, const RasterParams &P,
                                   const Hit &H, float G, float dalpha, float w, const float gc[3], float dt,
@@ -332,96 +338,95 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     // gradient arithmetic only (no decisions): products may fuse into fma
 #pragma clang fp contract(fast)
     // colour and depth outputs
-    gr[G_R] += gc[0] * w;
-    gr[G_G] += gc[1] * w;
-    gr[G_B] += gc[2] * w;
-    float dz = dt * ray.enorm;  // t = (Zc + s) |e|
-    float dx = 0.0f, dy = 0.0f;
-    float dphi0 = 0.0f, dphi1 = 0.0f, dphi2 = 0.0f;
+    gr[G_R] = gc[0] * w;
+    gr[G_G] = gc[1] * w;
+    gr[G_B] = gc[2] * w;
+    const float dz = dt * ray.enorm;  // t = (Zc + s) |e|
+    float dx, dy, dphi0, dphi1, dphi2, gl1, gl2;
     // normal output: n_cam = f Rc nl, nl = v / |v|, v = (-2 l1 x, -2 l2 y, 1)
     {
         float nl[3], il;
         const float f = hit_normal(p, H, nl, il);
         // Rc^T (w gn)
         const float q0 = qn[0] * w, q1 = qn[1] * w, q2 = qn[2] * w;
-        // rotation: dphi += n_f x (Rc^T g), n_f = f nl
+        // rotation: dphi = n_f x (Rc^T g), n_f = f nl, plus the terms below
         const float nf0 = f * nl[0], nf1 = f * nl[1], nf2 = f * nl[2];
-        dphi0 += nf1 * q2 - nf2 * q1;
-        dphi1 += nf2 * q0 - nf0 * q2;
-        dphi2 += nf0 * q1 - nf1 * q0;
+        dphi0 = nf1 * q2 - nf2 * q1;
+        dphi1 = nf2 * q0 - nf0 * q2;
+        dphi2 = nf0 * q1 - nf1 * q0;
         // through the normalisation
         const float d0 = f * q0, d1 = f * q1, d2 = f * q2;
         const float dot = nl[0] * d0 + nl[1] * d1 + nl[2] * d2;
         const float dv0 = (d0 - nl[0] * dot) * il, dv1 = (d1 - nl[1] * dot) * il;
-        gr[G_L1] += -2.0f * H.x * dv0;
-        gr[G_L2] += -2.0f * H.y * dv1;
-        dx += -2.0f * p.l1 * dv0;
-        dy += -2.0f * p.l2 * dv1;
+        gl1 = -2.0f * H.x * dv0;
+        gl2 = -2.0f * H.y * dv1;
+        dx = -2.0f * p.l1 * dv0;
+        dy = -2.0f * p.l2 * dv1;
         // curvature output: K = 4 l1 l2 / D^2, D = 1 + 4 l1^2 x^2 + 4 l2^2 y^2 = 1 / il^2
         if (GEO) {
             const float i2 = il * il, i4 = i2 * i2;
             const float K = 4.0f * p.l1 * p.l2 * i4;
             const float dD = -2.0f * K * i2 * dK;
-            gr[G_L1] += 4.0f * p.l2 * i4 * dK + 8.0f * p.l1 * H.x * H.x * dD;
-            gr[G_L2] += 4.0f * p.l1 * i4 * dK + 8.0f * p.l2 * H.y * H.y * dD;
+            gl1 += 4.0f * p.l2 * i4 * dK + 8.0f * p.l1 * H.x * H.x * dD;
+            gl2 += 4.0f * p.l1 * i4 * dK + 8.0f * p.l2 * H.y * H.y * dD;
             dx += 8.0f * p.l1 * p.l1 * H.x * dD;
             dy += 8.0f * p.l2 * p.l2 * H.y * dD;
         }
     }
     // alpha = min(alpha_max, op G), G = exp(-E / 2), E = g(u)^2 Q
-    float dG = 0.0f;
+    float dG = 0.0f, gop = 0.0f;
     if (p.op * G < P.alpha_max) {
-        gr[G_OP] += dalpha * G;
+        gop = dalpha * G;
         dG = dalpha * p.op;
     }
+    gr[G_OP] = gop;
     const float dE = -0.5f * G * dG;
     const float dQ = H.g * H.g * dE;
     const float du = 2.0f * H.g * gprime(H.u) * H.Q * dE;
     const float xx = H.x * H.x, yy = H.y * H.y;
     dx += 2.0f * p.k1 * H.x * dQ;
     dy += 2.0f * p.k2 * H.y * dQ;
-    gr[G_K1] += xx * dQ;
-    gr[G_K2] += yy * dQ;
+    gr[G_K1] = xx * dQ;
+    gr[G_K2] = yy * dQ;
     // u = 2 |h| / rho, h = l1 x^2 + l2 y^2
     if (H.rho2 > 0.0f && du != 0.0f) {
         const float irho = __builtin_amdgcn_rsqf(H.rho2);
         const float sg = H.h > 0.0f ? 1.0f : (H.h < 0.0f ? -1.0f : 0.0f);
         const float dh = du * 2.0f * sg * irho;
         const float drho = -du * 2.0f * __builtin_fabsf(H.h) * irho * irho;
-        gr[G_L1] += xx * dh;
-        gr[G_L2] += yy * dh;
+        gl1 += xx * dh;
+        gl2 += yy * dh;
         dx += (2.0f * p.l1 * dh + drho * irho) * H.x;
         dy += (2.0f * p.l2 * dh + drho * irho) * H.y;
     }
     // x = m0 + s e0, y = m1 + s e1, z = Zc + s
-    float dm0 = dx, dm1 = dy, dm2 = 0.0f;
-    float de0 = H.s * dx, de1 = H.s * dy, de2 = 0.0f;
-    float ds = __builtin_fmaf(H.e0, dx, __builtin_fmaf(H.e1, dy, dz));
-    float dZc = dz;
+    float dm0 = dx, dm1 = dy;
+    float de0 = H.s * dx, de1 = H.s * dy;
+    const float ds = __builtin_fmaf(H.e0, dx, __builtin_fmaf(H.e1, dy, dz));
     // root of A s^2 + B s + C = 0 (implicit differentiation)
     const float iF = __builtin_amdgcn_rcpf(__builtin_fmaf(2.0f * H.A, H.s, H.B));
     const float dA = -H.s * H.s * iF * ds;
     const float dB = -H.s * iF * ds;
     const float dC = -iF * ds;
     // A = l1 e0^2 + l2 e1^2
-    gr[G_L1] += H.e0 * H.e0 * dA;
-    gr[G_L2] += H.e1 * H.e1 * dA;
+    gl1 += H.e0 * H.e0 * dA;
+    gl2 += H.e1 * H.e1 * dA;
     de0 += 2.0f * p.l1 * H.e0 * dA;
     de1 += 2.0f * p.l2 * H.e1 * dA;
     // B = 2 (l1 m0 e0 + l2 m1 e1) - e2
-    gr[G_L1] += 2.0f * H.m0 * H.e0 * dB;
-    gr[G_L2] += 2.0f * H.m1 * H.e1 * dB;
+    gl1 += 2.0f * H.m0 * H.e0 * dB;
+    gl2 += 2.0f * H.m1 * H.e1 * dB;
     dm0 += 2.0f * p.l1 * H.e0 * dB;
     dm1 += 2.0f * p.l2 * H.e1 * dB;
     de0 += 2.0f * p.l1 * H.m0 * dB;
     de1 += 2.0f * p.l2 * H.m1 * dB;
-    de2 -= dB;
+    const float de2 = -dB;
     // C = l1 m0^2 + l2 m1^2 - m2
-    gr[G_L1] += H.m0 * H.m0 * dC;
-    gr[G_L2] += H.m1 * H.m1 * dC;
+    gl1 += H.m0 * H.m0 * dC;
+    gl2 += H.m1 * H.m1 * dC;
     dm0 += 2.0f * p.l1 * H.m0 * dC;
     dm1 += 2.0f * p.l2 * H.m1 * dC;
-    dm2 -= dC;
+    const float dm2 = -dC;
     // mhat = Rc^T m, ehat = Rc^T e: dphi += dm x m + de x e
     dphi0 += dm1 * H.m2 - dm2 * H.m1 + de1 * H.e2 - de2 * H.e1;
     dphi1 += dm2 * H.m0 - dm0 * H.m2 + de2 * H.e0 - de0 * H.e2;
@@ -429,13 +434,14 @@ __device__ inline void entry_grad(const Prim &p, const float rgb[3], const Pixel
     // m = (kx dxp, ky dyp, 0), kx = Zc / fx, dxp = u + 0.5 - u_c
     const float dmx = __builtin_fmaf(p.R[0], dm0, __builtin_fmaf(p.R[1], dm1, p.R[2] * dm2));
     const float dmy = __builtin_fmaf(p.R[3], dm0, __builtin_fmaf(p.R[4], dm1, p.R[5] * dm2));
-    dZc += dmx * H.dxp * P.ifx + dmy * H.dyp * P.ify;
-    gr[G_UC] += -dmx * p.kx;
-    gr[G_VC] += -dmy * p.ky;
-    gr[G_ZC] += dZc;
-    gr[G_PHI0] += dphi0;
-    gr[G_PHI1] += dphi1;
-    gr[G_PHI2] += dphi2;
+    gr[G_L1] = gl1;
+    gr[G_L2] = gl2;
+    gr[G_UC] = -dmx * p.kx;
+    gr[G_VC] = -dmy * p.ky;
+    gr[G_ZC] = dz + (dmx * H.dxp * P.ifx + dmy * H.dyp * P.ify);
+    gr[G_PHI0] = dphi0;
+    gr[G_PHI1] = dphi1;
+    gr[G_PHI2] = dphi2;
 }
 
 // The backward walks each wave's entries from its pixels' largest `last` down
@@ -448,16 +454,9 @@ template <bool DET, bool GEO>
 // `recs` is a.records again, as a restrict argument: the records are never
 // written here, which lets the compiler read them with scalar loads although
 // the loop stores gradients.
-#if QGS_BWD_MIN_WAVES > 0
-__global__ __launch_bounds__(BLOCK, QGS_BWD_MIN_WAVES) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
-                                                                         const float4 *__restrict__ recs,
-                                                                         float *__restrict__ grad_rec,
-                                                                         float *__restrict__ pair_scratch)
-#else
-__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams P, BwdIn in,
-                                                      const float4 *__restrict__ recs, float *__restrict__ grad_rec,
-                                                      float *__restrict__ pair_scratch)
-#endif
+__global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WAVES) void k_render_bwd(
+    RasterArgs a, RasterParams P, BwdIn in, const float4 *__restrict__ recs, float *__restrict__ grad_rec,
+    float *__restrict__ pair_scratch)
 {
     const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
@@ -518,9 +517,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
         float dxp, dyp;
         const bool lane_on = pos < last && conic_offsets(wr, ray, dxp, dyp);
         if (__ballot(lane_on) == 0ull) return;
+        // written only by contributing lanes; the others give zeros below
+        // (one select per field, instead of zeroing on every other path)
         float gr[NGRAD];
-#pragma unroll
-        for (int f = 0; f < NGRAD; ++f) gr[f] = 0.0f;
         bool contrib = false;
         if (lane_on) {
             Prim p;
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, RasterParams
         if (__ballot(contrib) != 0ull) {
             float g16[16];
 #pragma unroll
-            for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD ? gr[f] : 0.0f;
+            for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD && contrib ? gr[f] : 0.0f;
             // lane 4f (f < NGRAD) ends with the wave total of field f
             const float tot = wave_reduce_scatter16(g16);
             const int f = lane >> 2;
