@@ -393,6 +393,30 @@ def test_single_primitive_and_deep_stack():
     check_forward(window_of(st1, (0, 0, 32, 32)), one, cam, label="single")
 
 
+@pytest.mark.parametrize("n", [3000, 6000])
+def test_long_tile_lists_with_depth_ties(n):
+    # every primitive covers all four tiles of a 32 x 32 view, so each tile's
+    # list holds n entries (more than one radix block of the tile sort); depths
+    # come in groups of three equal values, shuffled against the index order,
+    # so the order of equal depth keys (by primitive index) is checked too
+    rng = np.random.default_rng(n)
+    cam = scenes.look_at((0.0, 0.0, 0.0), target=(0, 0, 1), width=32, height=32, f=32)
+    depth = 1.0 + 0.0005 * (rng.permutation(n) // 3)
+    sc = Scene(center=np.stack([rng.uniform(-0.02, 0.02, n), rng.uniform(-0.02, 0.02, n), depth], 1).astype(np.float32),
+               quat=np.tile(np.array([[0, 1, 0, 0]], np.float32), (n, 1)),
+               scale=np.full((n, 2), 0.6, np.float32), curv=np.zeros((n, 2), np.float32),
+               opacity=np.full(n, 0.3, np.float32),
+               rgb=rng.uniform(0, 1, (n, 3)).astype(np.float32))
+    for det in (False, True):
+        _, st = gpu_forward(sc, cam, opts=dict(flags=L.QGS_DETERMINISTIC_BWD) if det else None)
+        ks = check_keys(sc, cam, st)
+        dk = ks["depth_bits"]
+        assert len(np.unique(dk)) < n  # ties present
+        npairs = check_lists(ks, cam, st)
+        lens = np.diff(to_np(st.ranges).view(np.uint32).reshape(-1, 2), axis=1)
+        assert lens.max() == n and npairs == 4 * n
+
+
 def test_forward_is_repeatable_bitwise():
     c = cfg(1)
     cam = c.cameras[0]
