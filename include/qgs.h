@@ -134,7 +134,11 @@ typedef struct qgs_render_opts {
  *  conic       [n][8] FP64: the image of an ellipsoid enclosing the support
  *              (c00, c01, c11, c02, c12, c22 in normalised camera coordinates),
  *              [6] 1 when it bounds the support on screen (ellipsoid in front of
- *              the near plane), [7] unused.  Tiles of the rectangle that miss it
+ *              the near plane), [7] for a rectangle of at most 64 tiles the
+ *              bits of a 64-bit integer, bit k set when the k-th tile
+ *              (row-major) is kept, else 0: the tile decisions of
+ *              qgs_preprocess, which qgs_bin_sort emits from instead of
+ *              repeating the test.  Tiles of the rectangle that miss the conic
  *              are not emitted.
  *  depth_key   [n] FP32 bit pattern of the centre's camera-space depth (0 if culled)
  *  rect        [n][4] tile rectangle tx0, ty0, tx1, ty1 inclusive; (0, 0, -1, -1) if empty

@@ -369,6 +369,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
             for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
             cl.cok = C[6] != 0.0 ? 1u : 0u;
             if (cl.cok) conic_center(cl.C, cl.mx, cl.my, cl.ia, cl.ic);
+            // the counting pass's decisions for a rectangle of at most 64 tiles
+            cl.mask = reinterpret_cast<const uint64_t *>(C)[7];
+            if ((uint64_t)(rc[2] - rc[0] + 1) * (uint64_t)(rc[3] - rc[1] + 1) <= 64u) cl.cok |= 2u;
             cl.base = base;
             cl.cnt = (uint32_t)cnt;
             cl.prim = p;

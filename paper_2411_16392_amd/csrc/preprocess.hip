@@ -225,8 +225,6 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
         zf = (float)cc[2];
         ok = zf > a.near_plane;
     }
-    double *cq = a.conic + 8 * p;
-    for (int i = 0; i < 8; ++i) cq[i] = 0.0;
     if (!ok) {
         rec[0] = empty_rect;
         a.depth_key[p] = 0u;
@@ -369,8 +367,6 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
         const double dz = ce[2] - near_d;
         cok = dz > 0.0 && dz * dz > S33;
     }
-    for (int i = 0; i < 6; ++i) cq[i] = C[i];
-    cq[6] = cok ? 1.0 : 0.0;
     for (int i = 0; i < 6; ++i) cl.C[i] = C[i];
     if (cok) conic_center(C, cl.mx, cl.my, cl.ia, cl.ic);
     cl.cok = cok ? 1u : 0u;
@@ -423,8 +419,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
     ConicLane cl = {};
     if (p < a.n) preprocess_one(a, p, cl);
     // every thread of the workgroup takes part in the tile tests
-    const uint32_t cnt = wave_conic_tiles<false>(s_cl + (threadIdx.x & ~63u), cl, a.cam, 0, nullptr, nullptr, nullptr);
-    if (p < a.n) a.tiles[p] = cnt;
+    uint64_t mask = 0ull;
+    const uint32_t cnt = wave_conic_tiles<false>(s_cl + (threadIdx.x & ~63u), cl, a.cam, 0, nullptr, nullptr, nullptr,
+                                                 nullptr, nullptr, 0.0, &mask);
+    if (p < a.n) {
+        a.tiles[p] = cnt;
+        // the conic, its validity and the decisions for the emission (the bits
+        // of a 64-bit integer), the whole 64-byte row in one go (zeros for a
+        // culled primitive)
+        double *cq = a.conic + 8 * p;
+        for (int i = 0; i < 6; ++i) cq[i] = cl.C[i];
+        cq[6] = (cl.cok & 1u) ? 1.0 : 0.0;
+        reinterpret_cast<uint64_t *>(cq)[7] = mask;
+    }
 }
 
 // Chain rule from the record gradients (rotation as a right perturbation

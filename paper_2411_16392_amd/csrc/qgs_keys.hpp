@@ -125,14 +125,20 @@ __device__ inline uint32_t tile_depth_bits(const double *F, int tx, int ty, cons
 // per-lane counts) and processed 64 at a time, candidate c on lane c mod 64.
 // Each lane stages its primitive in LDS; a candidate finds its owner by binary
 // search over the scan.  The decisions are those of conic_tile_hit, so counts
-// and emitted tiles are the same as a per-primitive loop's.
+// and emitted tiles are the same as a per-primitive loop's.  The counting pass
+// also returns, for a rectangle of at most 64 tiles, its decisions as a bit
+// mask (bit k: the k-th tile, row-major); the emission pass reads a lane's
+// decisions from that mask when it has one (cok bit 1) instead of testing
+// again, so both passes take the same decisions.
 // ---------------------------------------------------------------------------
 struct ConicLane {
     double C[6];
     double mx, my, ia, ic;
     uint64_t base;               // first emission index (emission only)
     int32_t tx0, ty0, nx, ny;    // tile rectangle, nx * ny candidates (0: none)
-    uint32_t excl, cnt, prim, cok;
+    uint32_t excl, cnt, prim;
+    uint32_t cok;                // bit 0: the conic bounds the support; bit 1: `mask` holds the decisions
+    uint64_t mask;               // decisions of the counting pass (cok bit 1)
 };
 
 __device__ inline uint32_t wave_incl_scan_u32(uint32_t v)
@@ -174,11 +180,13 @@ __device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
 // EMIT: a hit of primitive `prim` with rank k among its hits goes to emission
 // index base + k (if k < cnt): out_tile = tile id, and out_emit = the index
 // with emit_prim = prim (EMIT_INDEX), or out_emit = prim.
+// mask_out (counting pass, may be NULL): the lane's decisions as a bit mask
+// when its rectangle has at most 64 tiles, else 0.
 template <bool EMIT, bool EMIT_INDEX = true>
 __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &me, const qgs_camera &cam,
                                             int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim,
                                             const double *frame = nullptr, uint32_t *out_dkey = nullptr,
-                                            double near_d = 0.0)
+                                            double near_d = 0.0, uint64_t *mask_out = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t R = (me.nx > 0 && me.ny > 0) ? (uint32_t)me.nx * (uint32_t)me.ny : 0u;
@@ -187,6 +195,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
     const uint32_t total = __shfl(incl, 63, 64);
     s_wave[lane] = me;
     s_wave[lane].excl = excl;
+    if (!EMIT) s_wave[lane].mask = 0ull;
     __syncthreads();
     uint32_t hits = 0;
     for (uint32_t base = 0; base < total; base += 64) {
@@ -200,7 +209,16 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
             const uint32_t loc = c - q.excl;
             tx = q.tx0 + (int)(loc % (uint32_t)q.nx);
             ty = q.ty0 + (int)(loc / (uint32_t)q.nx);
-            hit = q.cok == 0u || conic_tile_hit(q.C, q.mx, q.my, q.ia, q.ic, tx, ty, cam, ifx, ify);
+            if (EMIT && (q.cok & 2u))
+                hit = ((q.mask >> loc) & 1ull) != 0ull;
+            else
+                hit = (q.cok & 1u) == 0u || conic_tile_hit(q.C, q.mx, q.my, q.ia, q.ic, tx, ty, cam, ifx, ify);
+        }
+        if (!EMIT && mask_out && hit) {
+            // the owner's decision bit, in its staged copy (LDS atomic)
+            const ConicLane &q = s_wave[o];
+            const uint32_t loc = c - q.excl;
+            if ((uint32_t)q.nx * (uint32_t)q.ny <= 64u) atomicOr(&s_wave[o].mask, 1ull << loc);
         }
         const uint64_t bal = __ballot(hit);
         if (EMIT && hit) {
@@ -220,6 +238,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
         }
         hits += (uint32_t)__popcll(bal & lane_range_mask((int64_t)excl - (int64_t)base, (int64_t)incl - (int64_t)base));
     }
+    if (mask_out) *mask_out = R <= 64u ? s_wave[lane].mask : 0ull;
     return hits;
 }
 
