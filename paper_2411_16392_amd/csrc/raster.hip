@@ -1,10 +1,13 @@
 // Tile rasterizer, forward and backward.
 //
-// One 256-thread workgroup (four wave64s) per 16 x 16 tile; wave w owns the
-// 8 x 8 block (w & 1, w >> 1) of the tile, lane l the pixel (l & 7, l >> 3) in
-// it.  The waves walk the tile's list independently, without LDS or barriers:
-// 64 entries at a time, lane i fetches entry b + i's primitive id and pixel
-// rectangle (one batch ahead), a ballot keeps the entries whose rectangle
+// Four one-wave workgroups per 16 x 16 tile (consecutive workgroup ids, so a
+// finished wave's slot takes new work at once; with four-wave workgroups about
+// a fifth of the wave slots sat empty in mid-kernel); wave w owns the 8 x 8
+// block (w & 1, w >> 1) of the tile, lane l the pixel (l & 7, l >> 3) in it.
+// (The resort kernels keep one 256-thread workgroup per tile.)  The waves
+// walk the tile's list independently, without LDS or barriers: 64 entries at
+// a time, lane i fetches entry b + i's primitive id and pixel rectangle (one
+// batch ahead), a ballot keeps the entries whose rectangle
 // meets the wave's block, and only those are visited; the forwards also drop
 // entries whose pre-test conic misses the block (conic_meets_block, one test
 // per lane and batch instead of a wave step per entry).  A visited entry's
@@ -155,6 +158,7 @@ __device__ inline size_t replay_base(uint32_t start, uint32_t len, int tile, int
 // the loop stores replay words.
 template <bool GEO, bool NRM>
 #if QGS_FWD_MIN_WAVES > 0
+// Launched as one-wave workgroups (4 per tile); BLOCK only bounds the size.
 __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o,
                                                                          const float4 *__restrict__ recs,
                                                                          uint64_t *__restrict__ replay)
@@ -163,10 +167,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                                                       const float4 *__restrict__ recs, uint64_t *__restrict__ replay)
 #endif
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x >> 2] : (int)(blockIdx.x >> 2);
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(blockIdx.x & 3u);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -454,14 +458,15 @@ template <bool DET, bool GEO>
 // `recs` is a.records again, as a restrict argument: the records are never
 // written here, which lets the compiler read them with scalar loads although
 // the loop stores gradients.
+// Launched as one-wave workgroups (4 per tile); BLOCK only bounds the size.
 __global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WAVES) void k_render_bwd(
     RasterArgs a, RasterParams P, BwdIn in, const float4 *__restrict__ recs, float *__restrict__ grad_rec,
     float *__restrict__ pair_scratch)
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x >> 2] : (int)(blockIdx.x >> 2);
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(blockIdx.x & 3u);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -1177,13 +1182,13 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
         return hipGetLastError();
     }
     if (o.curvature)
-        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
                            reinterpret_cast<const float4 *>(a.records), o.steps);
     else if (o.depth)
-        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
                            reinterpret_cast<const float4 *>(a.records), o.steps);
     else
-        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
                            reinterpret_cast<const float4 *>(a.records), o.steps);
     return hipGetLastError();
 }
@@ -1259,20 +1264,20 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
         if (e != hipSuccess) return e;
         if (geo)
-            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
                                reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
         else
-            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
                                reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
         if (n_prims > 0)
             hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
                                (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
                                capacity, grad_rec);
     } else if (geo) {
-        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
                            reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
     } else {
-        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
                            reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
     }
     return hipGetLastError();
