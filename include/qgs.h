@@ -286,8 +286,9 @@ void qgs_default_opts(qgs_render_opts *opts);
  * Host-only size query.  For n primitives, a camera and a pair capacity:
  *  sort_ws_bytes  workspace of qgs_bin_sort
  *  bwd_ws_bytes   workspace of qgs_render_bwd for `flags`: the record
- *                 gradients (64 bytes per primitive) and the backward's tile
- *                 order (8 bytes per tile of the camera); QGS_DETERMINISTIC_BWD
+ *                 gradients (64 bytes per primitive) and the backward's order
+ *                 of its 8 x 8 blocks with their costs (32 bytes per tile of
+ *                 the camera); QGS_DETERMINISTIC_BWD
  *                 adds capacity * 256 bytes: one partial per pair and 8 x 8 block
  * Any output pointer may be NULL.
  */

@@ -94,7 +94,7 @@ RasterParams raster_params(const qgs_camera *c, const qgs_render_opts *o)
 
 RasterArgs raster_args(const qgs_prim_buf *prims, const qgs_tile_lists *lists, const qgs_camera *c)
 {
-    RasterArgs a;
+    RasterArgs a{};
     a.records = reinterpret_cast<const float *>(prims->records);
     a.pair_prim = lists->pair_prim;
     a.pair_tile = lists->pair_tile;
@@ -113,7 +113,7 @@ RasterArgs raster_args(const qgs_prim_buf *prims, const qgs_tile_lists *lists, c
 // and order [2][tiles] u32; deterministic mode: one 16-float partial per
 // (pair, wave of the tile)
 size_t bwd_grad_bytes(int64_t n) { return ((size_t)(n > 0 ? n : 1) * 64 + 255) & ~(size_t)255; }
-size_t bwd_order_bytes(uint64_t ntiles) { return ((size_t)(ntiles > 0 ? ntiles : 1) * 8 + 255) & ~(size_t)255; }
+size_t bwd_order_bytes(uint64_t ntiles) { return ((size_t)(ntiles > 0 ? ntiles : 1) * 32 + 255) & ~(size_t)255; }
 
 size_t bwd_bytes(int64_t n, uint64_t capacity, uint32_t flags, uint64_t ntiles)
 {

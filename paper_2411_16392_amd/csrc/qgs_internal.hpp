@@ -104,6 +104,9 @@ struct RasterArgs {
     const uint32_t *pair_prim, *pair_tile, *ranges, *tile_order, *counters;
     const uint32_t *pair_offset, *tiles, *emit_to_sorted;
     int32_t tiles_x, tiles_y;
+    // the backward's own order of 8 x 8 blocks (id 4 tile + block), taking the
+    // place of tile_order when set; NULL elsewhere
+    const uint32_t *block_order = nullptr;
 };
 
 struct FwdOut {

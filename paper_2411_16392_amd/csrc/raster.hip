@@ -463,10 +463,14 @@ __global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WA
     RasterArgs a, RasterParams P, BwdIn in, const float4 *__restrict__ recs, float *__restrict__ grad_rec,
     float *__restrict__ pair_scratch)
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x >> 2] : (int)(blockIdx.x >> 2);
+    // the block: from the backward's block order, or the tile order's tile
+    const uint32_t bid = a.block_order ? a.block_order[blockIdx.x]
+                                       : 4u * (a.tile_order ? a.tile_order[blockIdx.x >> 2] : (blockIdx.x >> 2)) +
+                                             (blockIdx.x & 3u);
+    const int tile = (int)(bid >> 2);
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(blockIdx.x & 3u);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(bid & 3u);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -1193,11 +1197,13 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
     return hipGetLastError();
 }
 
-// Backward work of each tile: the largest number of entries one of its four
-// 8 x 8 blocks visits, i.e. the set bits of that block's replay words.  One
-// wave per tile, its lanes striding over each block's words.
+// Backward work of each 8 x 8 block: the entries it visits, i.e. the set bits
+// of its replay words; per block (cost[4 t + w], per_block) or per tile (the
+// largest of its four, cost[t]).  One wave per tile, its lanes striding over
+// each block's words.
 __global__ __launch_bounds__(256) void k_bwd_cost(const uint32_t *ranges, const uint64_t *steps,
-                                                  const uint32_t *step_count, uint32_t ntiles, uint32_t *cost)
+                                                  const uint32_t *step_count, uint32_t ntiles, uint32_t *cost,
+                                                  bool per_block)
 {
     const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
@@ -1213,9 +1219,10 @@ __global__ __launch_bounds__(256) void k_bwd_cost(const uint32_t *ranges, const 
         for (uint32_t k = lane; k < nw; k += 64u) v += (uint32_t)__popcll(bm[k]);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (per_block && lane == 0) cost[4 * t + w] = v;
         c = v > c ? v : c;
     }
-    if (lane == 0) cost[t] = c;
+    if (!per_block && lane == 0) cost[t] = c;
 }
 
 hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, const BwdIn &in, float *grad_rec,
@@ -1228,12 +1235,18 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
     if (ntiles == 0) return hipSuccess;
     RasterArgs a = a_in;
     if (order_ws && in.steps) {
-        // the tiles in decreasing order of the entries they will visit
+        // the 8 x 8 blocks (one-wave workgroups), or with QGS_RESORT the tiles
+        // (one workgroup each), in decreasing order of the entries they visit
+        const bool per_block = !(in.flags & QGS_RESORT);
+        const unsigned nu = per_block ? 4u * ntiles : ntiles;
         hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 3) / 4), dim3(256), 0, stream, a.ranges, in.steps,
-                           in.step_count, ntiles, order_ws);
-        e = launch_tile_order(a.ranges, order_ws, ntiles, order_ws + ntiles, stream);
+                           in.step_count, ntiles, order_ws, per_block);
+        e = launch_tile_order(a.ranges, order_ws, nu, order_ws + nu, stream);
         if (e != hipSuccess) return e;
-        a.tile_order = order_ws + ntiles;
+        if (per_block)
+            a.block_order = order_ws + nu;
+        else
+            a.tile_order = order_ws + nu;
     }
     const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
     const float4 *recs = reinterpret_cast<const float4 *>(a.records);

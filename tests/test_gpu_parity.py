@@ -521,10 +521,11 @@ def test_replay_bitmap_gives_identical_gradients(mode):
 
 @pytest.mark.parametrize("mode", ["centre depth", "full model"])
 def test_backward_tile_order_follows_replay_visits(mode):
-    # the backward's own tile order (kept in its workspace after the record
-    # gradients): each tile's cost is the largest number of entries one of its
-    # four 8 x 8 blocks visits, i.e. the set bits of that block's replay words,
-    # and the tiles run in decreasing cost class
+    # the backward's own order (kept in its workspace after the record
+    # gradients): each 8 x 8 block's cost is the number of entries it visits,
+    # i.e. the set bits of its replay words, and the blocks (one-wave
+    # workgroups) run in decreasing cost class; with the per-pixel resort
+    # (one workgroup per tile) the tiles run by the largest of their four
     c = cfg(1)
     cam = c.cameras[0]
     flags = (L.QGS_TILE_DEPTH | L.QGS_RESORT) if mode == "full model" else 0
@@ -537,24 +538,25 @@ def test_backward_tile_order_follows_replay_visits(mode):
     r.backward(sc_t, st, *dL)
     torch.cuda.synchronize()
     ntiles = cam.tiles_x * cam.tiles_y
+    nu = ntiles if mode == "full model" else 4 * ntiles
     off = (max(st.n, 1) * 64 + 255) // 256 * 256
-    ws = to_np(r._bwd_ws)[off:off + 8 * ntiles].view(np.uint32)
-    cost, order = ws[:ntiles], ws[ntiles:2 * ntiles]
+    ws = to_np(r._bwd_ws)[off:off + 8 * nu].view(np.uint32)
+    cost, order = ws[:nu], ws[nu:2 * nu]
     ranges = to_np(st.ranges).view(np.uint32).reshape(-1, 2).astype(np.int64)
     steps = to_np(st.steps).view(np.uint64)
     nwords = to_np(st.step_count).view(np.uint32).astype(np.int64)
-    want = np.zeros(ntiles, np.int64)
+    blk = np.zeros((ntiles, 4), np.int64)
     for t in range(ntiles):
         start, ln = ranges[t, 0], ranges[t, 1] - ranges[t, 0]
         nw_max = (ln + 63) // 64
         for w in range(4):
             base = 4 * (start // 64 + t) + w * nw_max
             nw = min(nwords[4 * t + w], nw_max)
-            bits = sum(bin(int(x)).count("1") for x in steps[base:base + nw])
-            want[t] = max(want[t], bits)
+            blk[t, w] = sum(bin(int(x)).count("1") for x in steps[base:base + nw])
+    want = blk.max(1) if mode == "full model" else blk.ravel()
     assert want.sum() > 0
-    assert np.array_equal(cost.astype(np.int64), want), "tile costs"
-    assert np.array_equal(np.sort(order), np.arange(ntiles, dtype=np.uint32)), "order is a permutation"
+    assert np.array_equal(cost.astype(np.int64), want), "costs"
+    assert np.array_equal(np.sort(order), np.arange(nu, dtype=np.uint32)), "order is a permutation"
     cw = want[order]
     cls = np.minimum(np.where(cw < 2048, cw, 2048 + (cw - 2048) // 16), 4095)
     assert np.all(np.diff(cls) <= 0), "costliest tiles first"
