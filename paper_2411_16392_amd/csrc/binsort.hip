@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
                                               uint32_t *emit_prim, const double *frame, uint32_t *out_dkey,
                                               float near_plane)
 {
-    __shared__ ConicLane s_cl[256];
+    __shared__ ConicLane s_cl[64];
     if (counters[1]) return;  // overflow: the same for every thread
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ConicLane cl = {};
@@ -581,7 +581,7 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
     hipError_t e = hipSuccess;
     const bool emit_map = a.emit_to_sorted != nullptr;
     Count c{a.counters, bound};
-    const unsigned eb = (unsigned)cdiv((uint64_t)n, 256), gb = (unsigned)cdiv(bound, 256);
+    const unsigned eb = (unsigned)cdiv((uint64_t)n, 64), gb = (unsigned)cdiv(bound, 256);
     uint32_t *ki, *vi;
     bool values_are_emission = emit_map;
     if (a.frame) {
@@ -589,7 +589,7 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         // index, primitive) by emission index; four stable passes over the
         // depth key, then the tile passes on the gathered tiles (ties keep the
         // emission order: centre depth, then primitive)
-        hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n, a.cam,
+        hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n, a.cam,
                            a.tiles_x, a.counters, ws.tileT, ws.primT, ws.emit_prim, a.frame, ws.dkeyT,
                            a.near_plane);
         uint32_t *dk = ws.dkeyT, *dv = ws.primT, *ak = a.pair_tile, *av = a.pair_prim;
@@ -611,11 +611,11 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         ki = (passes % 2 == 0) ? a.pair_tile : ws.tileT;
         vi = (passes % 2 == 0) ? a.pair_prim : ws.primT;
         if (emit_map)
-            hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
+            hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
                                (uint32_t *)nullptr, 0.0f);
         else
-            hipLaunchKernelGGL(k_emit<false>, dim3(eb), dim3(256), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
+            hipLaunchKernelGGL(k_emit<false>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
                                (uint32_t *)nullptr, 0.0f);
     }

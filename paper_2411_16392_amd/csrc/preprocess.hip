@@ -414,7 +414,7 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
 
 __global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
 {
-    __shared__ ConicLane s_cl[256];
+    __shared__ ConicLane s_cl[64];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ConicLane cl = {};
     if (p < a.n) preprocess_one(a, p, cl);
@@ -530,8 +530,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreprocessBwdArgs a)
 hipError_t launch_preprocess(const PreprocessArgs &a, hipStream_t stream)
 {
     if (a.n == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((a.n + 255) / 256);
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, stream, a);
+    // one-wave workgroups (the tile tests are cooperative within a wave only)
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -176,7 +176,8 @@ __device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
 
 // Counts (and with EMIT writes) the tiles of each lane's rectangle that pass
 // the conic test (every tile when cok == 0).  s_wave: this wave's 64 LDS
-// entries.  Must be reached by every thread of the workgroup (one barrier).
+// entries.  Must be reached by every thread of the workgroup (one barrier; the
+// kernels run one-wave workgroups).
 // EMIT: a hit of primitive `prim` with rank k among its hits goes to emission
 // index base + k (if k < cnt): out_tile = tile id, and out_emit = the index
 // with emit_prim = prim (EMIT_INDEX), or out_emit = prim.
