@@ -1,8 +1,9 @@
 // Tile rasterizer, forward and backward.
 //
-// Four one-wave workgroups per 16 x 16 tile (consecutive workgroup ids, so a
-// finished wave's slot takes new work at once; with four-wave workgroups about
-// a fifth of the wave slots sat empty in mid-kernel); wave w owns the 8 x 8
+// Four one-wave workgroups per 16 x 16 tile (a finished wave's slot takes new
+// work at once; with four-wave workgroups about a fifth of the wave slots sat
+// empty in mid-kernel); the forward gives a tile's four workgroups ids 8
+// apart, so they run on one XCD and share its L2; wave w owns the 8 x 8
 // block (w & 1, w >> 1) of the tile, lane l the pixel (l & 7, l >> 3) in it.
 // (The resort kernels keep one 256-thread workgroup per tile.)  The waves
 // walk the tile's list independently, without LDS or barriers: 64 entries at
@@ -167,10 +168,18 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                                                       const float4 *__restrict__ recs, uint64_t *__restrict__ replay)
 #endif
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x >> 2] : (int)(blockIdx.x >> 2);
+    // workgroup ids 32 G + 8 k + x take block k of the tile in position 8 G + x
+    // of the order: consecutive ids go to the 8 XCDs in turn, so a tile's four
+    // blocks share one XCD (and its L2) and the tiles still start in order
+    const uint32_t ntl = (uint32_t)(P.tiles_x * P.tiles_y);
+    const uint32_t grp = blockIdx.x >> 5, r32 = blockIdx.x & 31u;
+    const uint32_t left = ntl - 8u * grp, mg = left < 8u ? left : 8u;
+    const uint32_t slot = mg == 8u ? 8u * grp + (r32 & 7u) : 8u * grp + r32 % mg;
+    const uint32_t kblk = mg == 8u ? r32 >> 3 : r32 / mg;
+    const int tile = a.tile_order ? (int)a.tile_order[slot] : (int)slot;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(blockIdx.x & 3u);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)kblk;
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
