@@ -5,7 +5,7 @@
 // empty in mid-kernel); the forward gives a tile's four workgroups ids 8
 // apart, so they run on one XCD and share its L2; wave w owns the 8 x 8
 // block (w & 1, w >> 1) of the tile, lane l the pixel (l & 7, l >> 3) in it.
-// (The resort kernels keep one 256-thread workgroup per tile.)  The waves
+// The resort kernels run the same way.  The waves
 // walk the tile's list independently, without LDS or barriers: 64 entries at
 // a time, lane i fetches entry b + i's primitive id and pixel rectangle (one
 // batch ahead), a ballot keeps the entries whose rectangle
@@ -760,10 +760,17 @@ template <bool GEO>
 __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterParams P, FwdOut o,
                                                          const float4 *__restrict__ recs, uint64_t *__restrict__ replay)
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    // one-wave workgroups, ids mapped as in k_render_fwd (a tile's four blocks
+    // on one XCD, the tiles in order)
+    const uint32_t ntl = (uint32_t)(P.tiles_x * P.tiles_y);
+    const uint32_t grp = blockIdx.x >> 5, r32 = blockIdx.x & 31u;
+    const uint32_t left = ntl - 8u * grp, mg = left < 8u ? left : 8u;
+    const uint32_t slot = mg == 8u ? 8u * grp + (r32 & 7u) : 8u * grp + r32 % mg;
+    const uint32_t kblk = mg == 8u ? r32 >> 3 : r32 / mg;
+    const int tile = a.tile_order ? (int)a.tile_order[slot] : (int)slot;
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)kblk;
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -935,10 +942,15 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
                                                          const float4 *__restrict__ recs,
                                                          float *__restrict__ grad_rec, float *__restrict__ pair_scratch)
 {
-    const int tile = a.tile_order ? (int)a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    // one-wave workgroups: the block from the backward's block order, or the
+    // tile order's tile
+    const uint32_t bid = a.block_order ? a.block_order[blockIdx.x]
+                                       : 4u * (a.tile_order ? a.tile_order[blockIdx.x >> 2] : (blockIdx.x >> 2)) +
+                                             (blockIdx.x & 3u);
+    const int tile = (int)(bid >> 2);
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, wave = (int)(bid & 3u);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -1187,10 +1199,10 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
     if (ntiles == 0) return hipSuccess;
     if (o.flags & QGS_RESORT) {
         if (o.curvature)
-            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
                                reinterpret_cast<const float4 *>(a.records), o.steps);
         else
-            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, o,
+            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
                                reinterpret_cast<const float4 *>(a.records), o.steps);
         return hipGetLastError();
     }
@@ -1244,18 +1256,14 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
     if (ntiles == 0) return hipSuccess;
     RasterArgs a = a_in;
     if (order_ws && in.steps) {
-        // the 8 x 8 blocks (one-wave workgroups), or with QGS_RESORT the tiles
-        // (one workgroup each), in decreasing order of the entries they visit
-        const bool per_block = !(in.flags & QGS_RESORT);
-        const unsigned nu = per_block ? 4u * ntiles : ntiles;
+        // the 8 x 8 blocks (one-wave workgroups) in decreasing order of the
+        // entries they visit
+        const unsigned nu = 4u * ntiles;
         hipLaunchKernelGGL(k_bwd_cost, dim3((ntiles + 3) / 4), dim3(256), 0, stream, a.ranges, in.steps,
-                           in.step_count, ntiles, order_ws, per_block);
+                           in.step_count, ntiles, order_ws, true);
         e = launch_tile_order(a.ranges, order_ws, nu, order_ws + nu, stream);
         if (e != hipSuccess) return e;
-        if (per_block)
-            a.block_order = order_ws + nu;
-        else
-            a.tile_order = order_ws + nu;
+        a.block_order = order_ws + nu;
     }
     const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
     const float4 *recs = reinterpret_cast<const float4 *>(a.records);
@@ -1264,20 +1272,20 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
             e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
             if (e != hipSuccess) return e;
             if (geo)
-                hipLaunchKernelGGL((k_render_bwd_rs<true, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+                hipLaunchKernelGGL((k_render_bwd_rs<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
                                    grad_rec, pair_scratch);
             else
-                hipLaunchKernelGGL((k_render_bwd_rs<true, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in,
+                hipLaunchKernelGGL((k_render_bwd_rs<true, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
                                    recs, grad_rec, pair_scratch);
             if (n_prims > 0)
                 hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
                                    (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
                                    capacity, grad_rec);
         } else if (geo) {
-            hipLaunchKernelGGL((k_render_bwd_rs<false, true>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+            hipLaunchKernelGGL((k_render_bwd_rs<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
                                grad_rec, pair_scratch);
         } else {
-            hipLaunchKernelGGL((k_render_bwd_rs<false, false>), dim3(ntiles), dim3(BLOCK), 0, stream, a, p, in, recs,
+            hipLaunchKernelGGL((k_render_bwd_rs<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
                                grad_rec, pair_scratch);
         }
         return hipGetLastError();

@@ -524,8 +524,7 @@ def test_backward_tile_order_follows_replay_visits(mode):
     # the backward's own order (kept in its workspace after the record
     # gradients): each 8 x 8 block's cost is the number of entries it visits,
     # i.e. the set bits of its replay words, and the blocks (one-wave
-    # workgroups) run in decreasing cost class; with the per-pixel resort
-    # (one workgroup per tile) the tiles run by the largest of their four
+    # workgroups) run in decreasing cost class, also with the per-pixel resort
     c = cfg(1)
     cam = c.cameras[0]
     flags = (L.QGS_TILE_DEPTH | L.QGS_RESORT) if mode == "full model" else 0
@@ -538,7 +537,7 @@ def test_backward_tile_order_follows_replay_visits(mode):
     r.backward(sc_t, st, *dL)
     torch.cuda.synchronize()
     ntiles = cam.tiles_x * cam.tiles_y
-    nu = ntiles if mode == "full model" else 4 * ntiles
+    nu = 4 * ntiles
     off = (max(st.n, 1) * 64 + 255) // 256 * 256
     ws = to_np(r._bwd_ws)[off:off + 8 * nu].view(np.uint32)
     cost, order = ws[:nu], ws[nu:2 * nu]
@@ -553,7 +552,7 @@ def test_backward_tile_order_follows_replay_visits(mode):
             base = 4 * (start // 64 + t) + w * nw_max
             nw = min(nwords[4 * t + w], nw_max)
             blk[t, w] = sum(bin(int(x)).count("1") for x in steps[base:base + nw])
-    want = blk.max(1) if mode == "full model" else blk.ravel()
+    want = blk.ravel()
     assert want.sum() > 0
     assert np.array_equal(cost.astype(np.int64), want), "costs"
     assert np.array_equal(np.sort(order), np.arange(nu, dtype=np.uint32)), "order is a permutation"
