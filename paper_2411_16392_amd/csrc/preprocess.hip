@@ -412,7 +412,9 @@ __device__ inline void preprocess_one(const PreprocessArgs &a, int64_t p, ConicL
     rec[7] = make_float4(cC, cD, cE, (float)zl);
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(PreprocessArgs a)
+// One-wave workgroups; 4 waves per SIMD requested (128 VGPRs, 40 bytes of
+// spills per lane) runs 3% faster than the 3 the unconstrained 144 VGPRs allow.
+__global__ __launch_bounds__(64, 4) void k_preprocess(PreprocessArgs a)
 {
     __shared__ ConicLane s_cl[64];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
