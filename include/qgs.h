@@ -93,6 +93,14 @@ typedef struct qgs_render_opts {
     float bg[3];      /* background colour, added with the final transmittance */
     int32_t tile;     /* must be 16 (16 x 16 tiles) */
     uint32_t flags;   /* QGS_* flags below; default QGS_TIGHT_BOUND */
+    /* NULL, NULL (default), or two hipEvent_t handles created by the caller:
+       qgs_render_fwd and qgs_render_bwd then record [0] on their stream just
+       before their rasterizer kernel and [1] just after it (before the
+       backward's deterministic reduction and preprocess adjoint), so that
+       hipEventElapsedTime gives that kernel's duration alone.  The
+       events stay the caller's; preprocess, bin_sort and the serving queue
+       ignore them. */
+    void *kernel_events[2];
 } qgs_render_opts;
 
 #define QGS_DETERMINISTIC_BWD 1u /* backward: two-pass, bit-reproducible reduction */

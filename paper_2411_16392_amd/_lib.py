@@ -47,7 +47,8 @@ class QgsCamera(ctypes.Structure):
 
 class QgsRenderOpts(ctypes.Structure):
     _fields_ = [("near_plane", c_float), ("k_sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
-                ("T_eps", c_float), ("A_eps", c_float), ("bg", c_float * 3), ("tile", c_int32), ("flags", c_uint32)]
+                ("T_eps", c_float), ("A_eps", c_float), ("bg", c_float * 3), ("tile", c_int32), ("flags", c_uint32),
+                ("kernel_events", c_void_p * 2)]
 
 
 class QgsPrimBuf(ctypes.Structure):

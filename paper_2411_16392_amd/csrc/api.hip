@@ -161,6 +161,7 @@ void qgs_default_opts(qgs_render_opts *o)
     o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
     o->tile = 16;
     o->flags = QGS_TIGHT_BOUND;
+    o->kernel_events[0] = o->kernel_events[1] = nullptr;
 }
 
 qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t capacity, uint32_t flags,
@@ -277,6 +278,8 @@ qgs_status qgs_render_fwd(const qgs_prim_buf *prims, const qgs_tile_lists *lists
     o.median_pos = out->median_pos;
     o.steps = out->steps;
     o.step_count = out->step_count;
+    o.ev_begin = (hipEvent_t)opts->kernel_events[0];
+    o.ev_end = (hipEvent_t)opts->kernel_events[1];
     return hip_status(launch_render_fwd(raster_args(prims, lists, cam), raster_params(cam, opts), o,
                                         (hipStream_t)stream));
 }
@@ -331,6 +334,8 @@ qgs_status render_bwd_impl(const qgs_scene *scene, const qgs_prim_buf *prims, co
     in.steps = fwd->steps;
     in.step_count = fwd->step_count;
     in.flags = opts->flags;
+    in.ev_begin = (hipEvent_t)opts->kernel_events[0];
+    in.ev_end = (hipEvent_t)opts->kernel_events[1];
     qgs_status st = hip_status(launch_render_bwd(raster_args(prims, lists, cam), raster_params(cam, opts), in,
                                                  grad_rec, pair_partials, order_ws, scene->n, lists->capacity, s));
     if (st != QGS_OK) return st;

@@ -120,6 +120,8 @@ struct FwdOut {
     // replay bitmap for the backward (both or null)
     uint64_t *steps;
     uint32_t *step_count;
+    // caller events recorded just before and after the rasterizer kernel (or null)
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 
 struct BwdIn {
@@ -137,6 +139,8 @@ struct BwdIn {
     const uint64_t *steps;
     const uint32_t *step_count;
     uint32_t flags;
+    // caller events recorded just before and after the rasterizer kernel (or null)
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream);

@@ -1193,29 +1193,37 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
     }
 }
 
+// Records a caller's event (if any) on the stream.
+static inline hipError_t mark(hipEvent_t ev, hipStream_t stream)
+{
+    return ev ? hipEventRecord(ev, stream) : hipSuccess;
+}
+
 hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const FwdOut &o, hipStream_t stream)
 {
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
-    if (ntiles == 0) return hipSuccess;
-    if (o.flags & QGS_RESORT) {
+    hipError_t e = mark(o.ev_begin, stream);
+    if (e != hipSuccess) return e;
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
+    if (ntiles == 0) {
+    } else if (o.flags & QGS_RESORT) {
         if (o.curvature)
-            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
-                               reinterpret_cast<const float4 *>(a.records), o.steps);
+            hipLaunchKernelGGL((k_render_fwd_rs<true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs, o.steps);
         else
-            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
-                               reinterpret_cast<const float4 *>(a.records), o.steps);
-        return hipGetLastError();
+            hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
+                               o.steps);
+    } else if (o.curvature) {
+        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs, o.steps);
+    } else if (o.depth) {
+        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
+                           o.steps);
+    } else {
+        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
+                           o.steps);
     }
-    if (o.curvature)
-        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
-                           reinterpret_cast<const float4 *>(a.records), o.steps);
-    else if (o.depth)
-        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
-                           reinterpret_cast<const float4 *>(a.records), o.steps);
-    else
-        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o,
-                           reinterpret_cast<const float4 *>(a.records), o.steps);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return mark(o.ev_end, stream);
 }
 
 // Backward work of each 8 x 8 block: the entries it visits, i.e. the set bits
@@ -1253,9 +1261,8 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
     const unsigned ntiles = (unsigned)(p.tiles_x * p.tiles_y);
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grad_rec), 0u, (uint64_t)n_prims * 16, stream);
     if (e != hipSuccess) return e;
-    if (ntiles == 0) return hipSuccess;
     RasterArgs a = a_in;
-    if (order_ws && in.steps) {
+    if (ntiles > 0 && order_ws && in.steps) {
         // the 8 x 8 blocks (one-wave workgroups) in decreasing order of the
         // entries they visit
         const unsigned nu = 4u * ntiles;
@@ -1265,51 +1272,52 @@ hipError_t launch_render_bwd(const RasterArgs &a_in, const RasterParams &p, cons
         if (e != hipSuccess) return e;
         a.block_order = order_ws + nu;
     }
-    const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
-    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
-    if (in.flags & QGS_RESORT) {
-        if (pair_scratch) {
-            e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
-            if (e != hipSuccess) return e;
-            if (geo)
-                hipLaunchKernelGGL((k_render_bwd_rs<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
-                                   grad_rec, pair_scratch);
-            else
-                hipLaunchKernelGGL((k_render_bwd_rs<true, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
-                                   recs, grad_rec, pair_scratch);
-            if (n_prims > 0)
-                hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
-                                   (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
-                                   capacity, grad_rec);
-        } else if (geo) {
-            hipLaunchKernelGGL((k_render_bwd_rs<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
-                               grad_rec, pair_scratch);
-        } else {
-            hipLaunchKernelGGL((k_render_bwd_rs<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in, recs,
-                               grad_rec, pair_scratch);
-        }
-        return hipGetLastError();
-    }
-    if (pair_scratch) {
+    if (ntiles > 0 && pair_scratch) {
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(pair_scratch), 0u, capacity * 64, stream);
         if (e != hipSuccess) return e;
-        if (geo)
-            hipLaunchKernelGGL((k_render_bwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
-                               reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
-        else
-            hipLaunchKernelGGL((k_render_bwd<true, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
-                               reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
-        if (n_prims > 0)
-            hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
-                               (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims,
-                               capacity, grad_rec);
-    } else if (geo) {
-        hipLaunchKernelGGL((k_render_bwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
-                           reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
-    } else {
-        hipLaunchKernelGGL((k_render_bwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, in,
-                           reinterpret_cast<const float4 *>(a.records), grad_rec, pair_scratch);
     }
+    const bool geo = in.dcurvature || in.dmedian || in.ddistortion;
+    const bool det = pair_scratch != nullptr;
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
+    const dim3 grid(4 * ntiles), wave(64);
+    e = mark(in.ev_begin, stream);
+    if (e != hipSuccess) return e;
+    if (ntiles == 0) {
+    } else if (in.flags & QGS_RESORT) {
+        if (det && geo)
+            hipLaunchKernelGGL((k_render_bwd_rs<true, true>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else if (det)
+            hipLaunchKernelGGL((k_render_bwd_rs<true, false>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else if (geo)
+            hipLaunchKernelGGL((k_render_bwd_rs<false, true>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else
+            hipLaunchKernelGGL((k_render_bwd_rs<false, false>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+    } else {
+        if (det && geo)
+            hipLaunchKernelGGL((k_render_bwd<true, true>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else if (det)
+            hipLaunchKernelGGL((k_render_bwd<true, false>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else if (geo)
+            hipLaunchKernelGGL((k_render_bwd<false, true>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+        else
+            hipLaunchKernelGGL((k_render_bwd<false, false>), grid, wave, 0, stream, a, p, in, recs, grad_rec,
+                               pair_scratch);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = mark(in.ev_end, stream);
+    if (e != hipSuccess) return e;
+    if (ntiles > 0 && det && n_prims > 0)
+        hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_prims + 255) / 256)), dim3(256), 0, stream,
+                           (const float *)pair_scratch, a.pair_offset, a.tiles, a.emit_to_sorted, n_prims, capacity,
+                           grad_rec);
     return hipGetLastError();
 }
 

@@ -520,6 +520,47 @@ def test_replay_bitmap_gives_identical_gradients(mode):
 
 
 @pytest.mark.parametrize("mode", ["centre depth", "full model"])
+def test_kernel_events_time_the_rasterizers_alone(mode):
+    # opts.kernel_events: the library records the caller's pair around the
+    # rasterizer kernel only; the images and (deterministic) gradients are
+    # bit-identical to a call without them, and each kernel's time is positive
+    # and within its call's
+    c = cfg(1)
+    cam = c.cameras[0]
+    flags = L.QGS_DETERMINISTIC_BWD | ((L.QGS_TILE_DEPTH | L.QGS_RESORT) if mode == "full model" else 0)
+    r = R.Renderer(opts=R.make_opts(flags=flags))
+    sc_t = R.scene_to_device(c.scene)
+    dL = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+          for a in scenes.upstream_grads(13, cam.height, cam.width)]
+    st = r.forward(sc_t, cam)
+    img = to_np(st.color).copy()
+    g0 = {k: to_np(v).copy() for k, v in r.backward(sc_t, st, *dL).items()}
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    for e in ev:
+        e.record(stream)  # torch creates an event at its first record
+    torch.cuda.synchronize()
+    st = r.preprocess(sc_t, cam)
+    r.bin_sort(st)
+    r.opts.kernel_events[0], r.opts.kernel_events[1] = ev[1].cuda_event, ev[2].cuda_event
+    ev[0].record(stream)
+    r.render_fwd(st)
+    ev[3].record(stream)
+    r.opts.kernel_events[0], r.opts.kernel_events[1] = ev[5].cuda_event, ev[6].cuda_event
+    ev[4].record(stream)
+    g1 = r.backward(sc_t, st, *dL)
+    ev[7].record(stream)
+    r.opts.kernel_events[0] = r.opts.kernel_events[1] = None
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(st.color), img)
+    for k in g0:
+        assert np.array_equal(to_np(g1[k]), g0[k]), k
+    for a, b, call in ((1, 2, ev[0].elapsed_time(ev[3])), (5, 6, ev[4].elapsed_time(ev[7]))):
+        t = ev[a].elapsed_time(ev[b])
+        assert 0.0 < t <= call, (t, call)
+
+
+@pytest.mark.parametrize("mode", ["centre depth", "full model"])
 def test_backward_tile_order_follows_replay_visits(mode):
     # the backward's own order (kept in its workspace after the record
     # gradients): each 8 x 8 block's cost is the number of entries it visits,
