@@ -64,41 +64,51 @@ __device__ inline float dpp_f(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
 }
 
-// Reduce-scatter of 16 per-lane values over the wave: afterwards every lane l
-// holds the wave total of value (l >> 2).  Each step halves the values a lane
-// keeps: lanes whose step bit is 0 keep the first half and add the partner's
-// first half, the others the second half.  Steps 32 and 16 use the gfx950
-// row-swap instructions (v_permlane32_swap: upper half of the first operand
-// <-> lower half of the second; v_permlane16_swap: odd rows of the first <->
-// even rows of the second), so a swap plus one add merges a pair of values;
-// steps 8 and 4 exchange with the mirrored lane in the row / half-row (partners
-// differ exactly in that bit), and steps 2 and 1 are butterflies inside the
-// quad.  Fixed order, so the result is reproducible.
-__device__ inline float wave_reduce_scatter16(const float (&v)[16])
+// Wave totals of the NGRAD gradient fields over the lanes with `mine` set,
+// transposed through LDS: s_red is the wave's block of 16 rows of RED_ROW
+// floats, zero on entry and again on return (rows NGRAD.. stay zero).  Each
+// such lane writes field f to row f, column lane; lane l then sums the 16
+// values of row l / 4 in columns l % 4, l % 4 + 4, ..., l % 4 + 60 and the
+// quad adds its four partial sums, so lane 4 f (f < NGRAD) ends with the total
+// of field f.  Fixed order, so the result is reproducible.  The row pitch of
+// 68 words puts the rows 4 banks apart: a half-wave of the column reads hits
+// 32 different banks.  Called by the whole wave (its workgroup), so the
+// barriers only order its LDS accesses; about a third of the VALU work of a
+// shuffle-based reduce-scatter.
+constexpr int RED_ROW = 68;
+__device__ inline float wave_reduce_lds(float *s_red, const float (&gr)[NGRAD], bool mine)
 {
     const int lane = threadIdx.x & 63;
-    float a[8], b[4], c[2];
+    if (mine) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
-        a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // lanes 0-31: value i, 32-63: value i + 8
+        for (int f = 0; f < NGRAD; ++f) s_red[f * RED_ROW + lane] = gr[f];
     }
+    __syncthreads();
+    const float *src = s_red + (lane >> 2) * RED_ROW + (lane & 3);
+    float v[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[i]), __float_as_uint(a[i + 4]), false, false);
-        b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // even rows: a[i], odd rows: a[i + 4]
-    }
-    const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+    for (int k = 0; k < 16; ++k) v[k] = src[4 * k];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float keep = hi8 ? b[i + 2] : b[i], send = hi8 ? b[i] : b[i + 2];
-        c[i] = keep + dpp_f<0x140>(send);  // row_mirror: lane 15 - l of the row
-    }
-    const float keep = hi4 ? c[1] : c[0], send = hi4 ? c[0] : c[1];
-    float d = keep + dpp_f<0x141>(send);  // row_half_mirror: lane 7 - l of the half-row
-    d += dpp_f<0x4E>(d);                  // quad_perm [2, 3, 0, 1]
-    d += dpp_f<0xB1>(d);                  // quad_perm [1, 0, 3, 2]
-    return d;
+    for (int f = 0; f < NGRAD; ++f) s_red[f * RED_ROW + lane] = 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] += v[k + 8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += v[k + 4];
+    v[0] += v[2];
+    v[1] += v[3];
+    float tot = v[0] + v[1];
+    tot += dpp_f<0x4E>(tot);  // quad_perm [2, 3, 0, 1]
+    tot += dpp_f<0xB1>(tot);  // quad_perm [1, 0, 3, 2]
+    return tot;
+}
+
+// zeroes the wave's reduction block (all 16 rows)
+__device__ inline void clear_reduce_lds(float *s_red)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int f = 0; f < 16; ++f) s_red[f * RED_ROW + lane] = 0.0f;
 }
 
 // Words 4..31 of primitive pj's record (everything past the rectangle) into
@@ -480,6 +490,8 @@ __global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WA
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = (int)(bid & 3u);
+    __shared__ float s_red[16 * RED_ROW];  // the wave's gradient reduction block
+    clear_reduce_lds(s_red);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -593,11 +605,8 @@ __global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WA
             }
         }
         if (__ballot(contrib) != 0ull) {
-            float g16[16];
-#pragma unroll
-            for (int f = 0; f < 16; ++f) g16[f] = f < NGRAD && contrib ? gr[f] : 0.0f;
             // lane 4f (f < NGRAD) ends with the wave total of field f
-            const float tot = wave_reduce_scatter16(g16);
+            const float tot = wave_reduce_lds(s_red, gr, contrib);
             const int f = lane >> 2;
             if ((lane & 3) == 0 && f < NGRAD) {
                 if (DET)
@@ -951,6 +960,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
     if ((unsigned)tile >= (unsigned)(P.tiles_x * P.tiles_y)) return;  // whole workgroup; cannot happen for lists built here
     const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = (int)(bid & 3u);
+    __shared__ float s_red[16 * RED_ROW];  // the wave's gradient reduction block
+    clear_reduce_lds(s_red);
     const int wx0 = tx * TILE + (wave & 1) * 8, wy0 = ty * TILE + (wave >> 1) * 8;
     const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
     const bool inside = px < P.width && py < P.height;
@@ -1089,10 +1100,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd_rs(RasterArgs a, RasterPar
             const uint32_t pos0 = (uint32_t)__builtin_amdgcn_readlane((int)g_pos, l0);
             const bool mine = has && g_pid == pid0;
             rem &= ~__ballot(mine);
-            float g16[16];
-#pragma unroll
-            for (int f = 0; f < 16; ++f) g16[f] = (mine && f < NGRAD) ? gr[f] : 0.0f;
-            const float tot = wave_reduce_scatter16(g16);
+            const float tot = wave_reduce_lds(s_red, gr, mine);
             const int f = lane >> 2;
             if ((lane & 3) == 0 && f < NGRAD) {
                 if (DET) {
