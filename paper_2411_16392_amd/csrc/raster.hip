@@ -145,7 +145,9 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
 // forward
 // ---------------------------------------------------------------------------
 // GEO: also the curvature, median-depth and depth-distortion maps.  NRM:
-// accumulate depth and normal (off for colour-only rendering).
+// accumulate depth and normal (off for colour-only rendering).  COUNT: the
+// work counters of QGS_COUNT_EVALS (a separate instantiation, so that the
+// plain forward carries none of their per-step bookkeeping).
 //
 // First word of the replay bitmap of 8 x 8 block `wave` of tile `tile`, whose
 // list is [start, start + len): tiles take 4 ceil(len / 64) words each from
@@ -167,7 +169,7 @@ __device__ inline size_t replay_base(uint32_t start, uint32_t len, int tile, int
 // `recs` is a.records again and `replay` o.steps, as restrict arguments: the
 // records are never written here, which keeps the scalar loads legal although
 // the loop stores replay words.
-template <bool GEO, bool NRM>
+template <bool GEO, bool NRM, bool COUNT>
 #if QGS_FWD_MIN_WAVES > 0
 // Launched as one-wave workgroups (4 per tile); BLOCK only bounds the size.
 __global__ __launch_bounds__(BLOCK, QGS_FWD_MIN_WAVES) void k_render_fwd(RasterArgs a, RasterParams P, FwdOut o,
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
         while (m != 0ull && wave_alive) {
             const int j = __builtin_ctzll(m);
             m &= m - 1ull;
-            ++w_rect;
+            if (COUNT) ++w_rect;
             const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)cur_pid, j);
             float rw[32];
             load_record_words(recs, pj, rw);
@@ -242,13 +244,13 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             float dxp, dyp;
             const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
             if (__ballot(lane_on) == 0ull) continue;
-            ++w_eval;
+            if (COUNT) ++w_eval;
             const uint32_t pos1 = b + (uint32_t)j + 1u;
             if (lane_on) {
                 Prim p;
                 load_prim(w, P, p);
                 Hit H;
-                ++n_eval;
+                if (COUNT) ++n_eval;
                 if (ray_hit(p, ray, P, dxp, dyp, H)) {
                     const float G = __expf(-0.5f * H.E);
                     const float alpha = fminf(P.alpha_max, p.op * G);
@@ -288,14 +290,14 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
                             }
                             T = Tn;
                             last = pos1;
-                            ++n_blend;
+                            if (COUNT) ++n_blend;
                         }
                     }
                 }
             }
-            if (o.counters || bm) {
+            if (COUNT || bm) {
                 const bool any_blend = __ballot(last == pos1) != 0ull;
-                if (o.counters) w_blend += any_blend ? 1u : 0u;
+                if (COUNT) w_blend += any_blend ? 1u : 0u;
                 if (any_blend) blended |= 1ull << j;
             }
             wave_alive = __ballot(!done) != 0ull;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             o.median_pos[pix] = med_pos;
         }
     }
-    if (o.counters) {
+    if (COUNT) {
         // list entries processed per pixel (up to and including a stop),
         // intersections evaluated, pairs blended
         uint32_t c[3] = {inside ? (stop_pos ? stop_pos : n) : 0u, n_eval, n_blend};
@@ -1220,14 +1222,21 @@ hipError_t launch_render_fwd(const RasterArgs &a, const RasterParams &p, const F
         else
             hipLaunchKernelGGL((k_render_fwd_rs<false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
                                o.steps);
-    } else if (o.curvature) {
-        hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs, o.steps);
-    } else if (o.depth) {
-        hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
-                           o.steps);
     } else {
-        hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(4 * ntiles), dim3(64), 0, stream, a, p, o, recs,
-                           o.steps);
+        const dim3 grid(4 * ntiles), wave(64);
+        const bool cnt = o.counters != nullptr;
+        if (o.curvature && cnt)
+            hipLaunchKernelGGL((k_render_fwd<true, true, true>), grid, wave, 0, stream, a, p, o, recs, o.steps);
+        else if (o.curvature)
+            hipLaunchKernelGGL((k_render_fwd<true, true, false>), grid, wave, 0, stream, a, p, o, recs, o.steps);
+        else if (o.depth && cnt)
+            hipLaunchKernelGGL((k_render_fwd<false, true, true>), grid, wave, 0, stream, a, p, o, recs, o.steps);
+        else if (o.depth)
+            hipLaunchKernelGGL((k_render_fwd<false, true, false>), grid, wave, 0, stream, a, p, o, recs, o.steps);
+        else if (cnt)
+            hipLaunchKernelGGL((k_render_fwd<false, false, true>), grid, wave, 0, stream, a, p, o, recs, o.steps);
+        else
+            hipLaunchKernelGGL((k_render_fwd<false, false, false>), grid, wave, 0, stream, a, p, o, recs, o.steps);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
