@@ -242,7 +242,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, RasterParams
             load_record_words(recs, pj, rw);
             const float *w = rw;
             float dxp, dyp;
-            const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
+            // bitwise and: the pre-test runs on every lane, with no branch
+            const bool lane_on = conic_offsets(w, ray, dxp, dyp) & !done;
             if (__ballot(lane_on) == 0ull) continue;
             if (COUNT) ++w_eval;
             const uint32_t pos1 = b + (uint32_t)j + 1u;
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(BLOCK, GEO ? QGS_BWD_GEO_MIN_WAVES : QGS_BWD_MIN_WA
     auto visit = [&](uint32_t pos, uint32_t pj) {
         const float *wr = reinterpret_cast<const float *>(recs + (size_t)pj * 8);
         float dxp, dyp;
-        const bool lane_on = pos < last && conic_offsets(wr, ray, dxp, dyp);
+        const bool lane_on = conic_offsets(wr, ray, dxp, dyp) & (pos < last);
         if (__ballot(lane_on) == 0ull) return;
         // written only by contributing lanes; the others give zeros below
         // (one select per field, instead of zeroing on every other path)

@@ -602,6 +602,63 @@ def test_backward_tile_order_follows_replay_visits(mode):
     assert np.all(np.diff(cls) <= 0), "costliest tiles first"
 
 
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_gpu_gradients_match_finite_differences(seed):
+    # the HIP backward directly against FP64 central differences of the
+    # oracle's forward (supplement, back-to-front adjoint), at the gradient
+    # tolerance: 1e-3 relative with a floor of 1e-2 of the tensor's largest
+    # entry; 1-8 primitives in a 16 x 16 view, N(0,1) upstream gradients on
+    # the colour, depth and normal maps, at a base point away from every
+    # decision boundary (oracle margins >= 1)
+    from test_oracle_pins import FD_KEYS, _fd_scene
+    cam = scenes.look_at((0.1, 0.05, -3.0), width=16, height=16, f=20)
+    strict = dict(A=1e-3, D=1e-4, near=1e-4, E=1e-4, alpha_min=1e-4, T=1e-4, normal=1e-4, clamp=1e-4)
+    zero = np.zeros((16, 16))
+    for attempt in range(20):
+        s_ = seed + 1000 * attempt
+        n = 1 + (seed * 3) % 8
+        sc = _fd_scene(s_, n)
+        if seed % 2 == 1:
+            sc.curv[0] = 0.0  # one planar primitive: the small-|A| branch
+        rng = np.random.default_rng(200 + s_)
+        dL = (rng.standard_normal((3, 16, 16)), rng.standard_normal((16, 16)), rng.standard_normal((3, 16, 16)),
+              zero, zero, zero)
+        ks = oracle.keys(sc, cam)
+        base = oracle.render(sc, cam, dL=dL, key_stage=ks, delta=strict, nthreads=2)
+        if (base["margin"].min() >= 1.0 and base["gmargin"].min() >= 1.0 and
+                base["n_blend"].max() >= min(n, 2)):
+            break
+    else:
+        pytest.fail("no base point away from decision boundaries")
+    p64 = [a.astype(np.float64) for a in sc.arrays()]
+
+    def loss(params):
+        r = oracle.render(sc, cam, params64=params, key_stage=ks, nthreads=2)
+        return float(np.sum(dL[0] * r["color"]) + np.sum(dL[1] * r["depth"]) + np.sum(dL[2] * r["normal"]))
+
+    r = R.Renderer()
+    sc_t = R.scene_to_device(sc)
+    st = r.forward(sc_t, cam)
+    dl_t = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in dL[:3]]
+    g = {k: to_np(v) for k, v in r.backward(sc_t, st, *dl_t).items()}
+    torch.cuda.synchronize()
+    for ki, key in enumerate(FD_KEYS):
+        flat = p64[ki].reshape(n, -1)
+        fd = np.zeros_like(flat)
+        for p_ in range(n):
+            for j in range(flat.shape[1]):
+                hstep = 1e-6 * max(1.0, abs(flat[p_, j]))
+                plus = [a.copy() for a in p64]
+                minus = [a.copy() for a in p64]
+                plus[ki].reshape(n, -1)[p_, j] += hstep
+                minus[ki].reshape(n, -1)[p_, j] -= hstep
+                fd[p_, j] = (loss(plus) - loss(minus)) / (2 * hstep)
+        gg = g[key].reshape(n, -1).astype(np.float64)
+        floor = 1e-2 * (np.abs(fd).max() + 1e-12)
+        err = np.abs(gg - fd)
+        assert np.all(err <= 1e-3 * np.maximum(np.abs(fd), floor)), (key, gg, fd)
+
+
 def test_autograd_function_matches_direct_backward():
     c = cfg(0)
     cam = c.cameras[0]
