@@ -180,10 +180,15 @@ typedef struct qgs_prim_buf {
  *                        the qgs_bin_sort that built the lists; building it
  *                        costs a random gather and scatter over all pairs.
  *  ranges                [tiles_x * tiles_y][2] start, end of each tile's run
- *  tile_order            [tiles_x * tiles_y] tiles by decreasing list length
- *                        (exact below 2048 entries, then classes 16 entries
- *                        wide up to 34800): the order in which the rasterizer's
- *                        workgroups take tiles, so the longest start first
+ *  tile_order            [tiles_x * tiles_y] tiles by decreasing forward work
+ *                        (exact below 2048, then classes 16 wide up to 34800):
+ *                        the order in which the rasterizer's workgroups take
+ *                        tiles, so the costliest start first.  The work of a
+ *                        tile is the largest, over its four 8 x 8 blocks, count
+ *                        of its entries whose pixel rectangle and screen conic
+ *                        (the forward's per-block filter) meet the block;
+ *                        with QGS_TILE_DEPTH, and for the serving queue, the
+ *                        list length
  *  counters              [8] uint32: [0] number of pairs, [1] overflow flag
  *                        (1 when [0] > capacity: lists and ranges are then empty
  *                        and the caller must grow and call again); with

@@ -169,7 +169,7 @@ qgs_status qgs_workspace_query(int64_t n, const qgs_camera *cam, uint64_t capaci
 {
     if (n < 0 || n > 0x7FFFFFFFll || !cam_ok(cam) || capacity > 0xFFFFFFFFull) return QGS_ERR_INVALID_ARG;
     const uint64_t ntiles = (uint64_t)((cam->width + 15) / 16) * (uint64_t)((cam->height + 15) / 16);
-    if (sort_ws_bytes) *sort_ws_bytes = sort_workspace_layout(nullptr, n, capacity).bytes;
+    if (sort_ws_bytes) *sort_ws_bytes = sort_workspace_layout(nullptr, n, capacity, ntiles).bytes;
     if (bwd_ws_bytes) *bwd_ws_bytes = bwd_bytes(n, capacity, flags, ntiles);
     return QGS_OK;
 }
@@ -208,9 +208,10 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
 {
     if (!prims || !cam_ok(cam) || !opts_ok(opts) || !prims_ok(prims, prims->n) || !lists_ok(lists))
         return QGS_ERR_INVALID_ARG;
-    const SortWorkspace need = sort_workspace_layout(nullptr, prims->n, lists->capacity);
+    const uint64_t ntiles = (uint64_t)((cam->width + 15) / 16) * (uint64_t)((cam->height + 15) / 16);
+    const SortWorkspace need = sort_workspace_layout(nullptr, prims->n, lists->capacity, ntiles);
     if (!ws || ws_bytes < need.bytes) return QGS_ERR_WORKSPACE;
-    const SortWorkspace w = sort_workspace_layout(ws, prims->n, lists->capacity);
+    const SortWorkspace w = sort_workspace_layout(ws, prims->n, lists->capacity, ntiles);
     BinSortArgs a;
     a.n = prims->n;
     a.depth_key = prims->depth_key;
@@ -230,6 +231,7 @@ qgs_status qgs_bin_sort(qgs_prim_buf *prims, const qgs_camera *cam, const qgs_re
     a.capacity = lists->capacity;
     a.frame = (opts->flags & QGS_TILE_DEPTH) ? prims->frame : nullptr;
     a.near_plane = opts->near_plane;
+    a.records = reinterpret_cast<const float *>(prims->records);
     if ((opts->flags & QGS_TILE_DEPTH) && !prims->frame) return QGS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     qgs_status st = hip_status(bin_sort_phase1(a, w, s));

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qgs_device.hpp"
 #include "qgs_internal.hpp"
 #include "qgs_keys.hpp"
 
@@ -349,14 +350,46 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t *order, con
 // index (EMIT_INDEX, with emit_prim[e] = its primitive, for the emission map)
 // or directly its primitive.  The decisions are those the preprocess counted
 // with the same test.
+// With tag_shift > 0 each emitted tile id also carries, from bit tag_shift
+// on, which of the tile's four 8 x 8 blocks the forward will visit the pair
+// for: the pixel rectangle meets the block and conic_meets_block holds, the
+// forward's own per-batch filter.  The tile sort looks only at the bits
+// below tag_shift, so the tags ride along to the ranges pass, which counts
+// them per block and strips them.
+struct BlockTag {
+    const int4 *rc;
+    const float4 *cu, *abcd, *ehh;  // ehh: e, 0.5 / a, 0.5 / c
+    uint32_t shift;
+    __device__ uint32_t operator()(int o, int tx, int ty) const
+    {
+        if (shift == 0u) return 0u;
+        const int4 r = rc[o];
+        const float4 q = abcd[o], h = ehh[o], c = cu[o];
+        uint32_t m = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int wx0 = tx * TILE + (k & 1) * 8, wy0 = ty * TILE + (k >> 1) * 8;
+            bool rel = !(r.y < wx0 || r.x > wx0 + 7 || r.w < wy0 || r.z > wy0 + 7);
+            if (rel)
+                rel = conic_meets_block_h(c, make_float2(q.x, q.y), make_float4(q.z, q.w, h.x, 0.0f), h.y, h.z,
+                                          (float)wx0, (float)wy0);
+            m |= (rel ? 1u : 0u) << k;
+        }
+        return m << shift;
+    }
+};
+
 template <bool EMIT_INDEX>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
                                               const double *conic, int64_t n, qgs_camera cam, int32_t tiles_x,
                                               const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
                                               uint32_t *emit_prim, const double *frame, uint32_t *out_dkey,
-                                              float near_plane)
+                                              float near_plane, const float4 *recs, uint32_t tag_shift)
 {
     __shared__ ConicLane s_cl[64];
+    // the block tags' words of each lane's primitive (record words 0..7, 14..15, 28..30)
+    __shared__ int4 s_rc[64];
+    __shared__ float4 s_cu[64], s_abcd[64], s_ehh[64];
     if (counters[1]) return;  // overflow: the same for every thread
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ConicLane cl = {};
@@ -379,10 +412,21 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
             cl.ty0 = rc[1];
             cl.nx = rc[2] - rc[0] + 1;
             cl.ny = rc[3] - rc[1] + 1;
+            if (tag_shift) {
+                const float4 *w = recs + (size_t)p * 8;
+                const float4 w3 = w[3], w7 = w[7];
+                s_rc[threadIdx.x] = *reinterpret_cast<const int4 *>(w);
+                s_cu[threadIdx.x] = w[1];
+                s_abcd[threadIdx.x] = make_float4(w3.z, w3.w, w7.x, w7.y);
+                s_ehh[threadIdx.x] = make_float4(w7.z, 0.5f / w3.z, 0.5f / w7.x, 0.0f);
+            }
         }
     }
-    (void)wave_conic_tiles<true, EMIT_INDEX>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit,
-                                             emit_prim, frame, out_dkey, (double)near_plane);
+    // (the barrier in wave_conic_tiles orders these LDS writes before the tags' reads)
+    const BlockTag tag{s_rc, s_cu, s_abcd, s_ehh, tag_shift};
+    (void)wave_conic_tiles<true, EMIT_INDEX, BlockTag>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile,
+                                                       out_emit, emit_prim, frame, out_dkey, (double)near_plane,
+                                                       nullptr, tag);
 }
 
 // tile-depth lists: after the depth passes the values are emission indices;
@@ -419,21 +463,62 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint6
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *tile, Count cnt, uint32_t *ranges, uint32_t ntiles)
+// Each tile's range in the sorted lists, one wave per 256 consecutive pairs
+// (64 at a time).  With tag_shift > 0 the tile ids still carry the emission's
+// block tags (bits tag_shift .. tag_shift + 3): they are stripped here, and
+// each wave adds its pairs' tags per (tile, block) into blk[4 t + k], holding
+// the counts of its current tile until the tile changes (so a long list costs
+// four atomics per 256 pairs).
+__global__ __launch_bounds__(256) void k_ranges(uint32_t *tile, Count cnt, uint32_t *ranges, uint32_t ntiles,
+                                                uint32_t tag_shift, uint32_t *blk)
 {
     const uint64_t n = cnt.get();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = tile[i];
-    if (t >= ntiles) return;  // cannot happen for lists built here
-    if (i == 0 || tile[i - 1] != t) ranges[2 * (uint64_t)t] = (uint32_t)i;
-    if (i == n - 1 || tile[i + 1] != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
+    const int lane = threadIdx.x & 63;
+    const uint64_t base = ((uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6)) * 256u;
+    const uint32_t low = tag_shift ? (1u << tag_shift) - 1u : 0xFFFFFFFFu;
+    uint32_t pend_t = 0xFFFFFFFFu, pend[4] = {0u, 0u, 0u, 0u};
+    auto flush = [&]() {
+        if (pend_t == 0xFFFFFFFFu) return;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (lane == 0 && pend[k]) atomicAdd(blk + 4 * (uint64_t)pend_t + k, pend[k]);
+    };
+    for (int j = 0; j < 4; ++j) {
+        if (base + 64u * (uint64_t)j >= n) break;  // whole wave
+        const uint64_t i = base + 64u * (uint64_t)j + (uint64_t)lane;
+        const uint32_t key = i < n ? tile[i] : 0u;
+        const uint32_t t = key & low;
+        const bool in = i < n && t < ntiles;  // t < ntiles always holds for lists built here
+        if (in) {
+            if (i == 0 || (tile[i - 1] & low) != t) ranges[2 * (uint64_t)t] = (uint32_t)i;
+            if (i == n - 1 || (tile[i + 1] & low) != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
+        }
+        if (!tag_shift) continue;  // uniform
+        // (neighbours may read a stripped or an unstripped id: both mask to t)
+        if (i < n) tile[i] = t;
+        uint64_t todo = __ballot(in);
+        while (todo != 0ull) {
+            const int l0 = __builtin_ctzll(todo);
+            const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)t, l0);
+            const bool mine = in && t == t0;
+            todo &= ~__ballot(mine);
+            if (t0 != pend_t) {
+                flush();
+                pend_t = t0;
+                pend[0] = pend[1] = pend[2] = pend[3] = 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pend[k] += (uint32_t)__popcll(__ballot(mine && ((key >> (tag_shift + k)) & 1u)));
+        }
+    }
+    if (tag_shift) flush();
 }
 
 // Tiles in decreasing order of cost: the rasterizer's workgroups take tiles in
 // this order, so that the costliest start first and the ones that start last
-// are the cheapest (longest-processing-time-first order).  The cost is cost[t]
-// or, with no cost array, the tile's list length.  Counting sort over 4096
+// are the cheapest (longest-processing-time-first order).  The cost is cost[t],
+// the largest of cost[4 t .. 4 t + 3] (max4: per-block costs), or, with no
+// cost array, the tile's list length.  Counting sort over 4096
 // cost classes: one per value below 2048, then classes 16 wide up to 34800
 // (higher costs share the top class); order inside a class is arbitrary.
 constexpr int TO_CLASSES = 4096;
@@ -445,9 +530,15 @@ __device__ inline uint32_t cost_class(uint32_t c)
 }
 
 __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles,
-                                                     uint32_t *order)
+                                                     uint32_t *order, bool max4)
 {
-    auto tile_cost = [&](uint32_t t) { return cost ? cost[t] : ranges[2 * t + 1] - ranges[2 * t]; };
+    auto tile_cost = [&](uint32_t t) -> uint32_t {
+        if (!cost) return ranges[2 * t + 1] - ranges[2 * t];
+        if (!max4) return cost[t];
+        const uint4 v = reinterpret_cast<const uint4 *>(cost)[t];
+        const uint32_t m = v.x > v.y ? v.x : v.y, m2 = v.z > v.w ? v.z : v.w;
+        return m > m2 ? m : m2;
+    };
     __shared__ uint32_t cnt[TO_CLASSES];
     __shared__ uint32_t s_w[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -477,10 +568,10 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *ranges, con
 }
 
 hipError_t launch_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles, uint32_t *order,
-                             hipStream_t stream)
+                             hipStream_t stream, bool max4)
 {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, ranges, cost, ntiles, order);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, stream, ranges, cost, ntiles, order, max4);
     return hipGetLastError();
 }
 
@@ -493,7 +584,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t stre
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
+SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity, uint64_t ntiles)
 {
     SortWorkspace w{};
     const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
@@ -518,6 +609,7 @@ SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity)
     w.primT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.emit_prim = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
     w.dkeyT = (uint32_t *)take(4 * (capacity > 0 ? capacity : 1));
+    w.blk_cost = (uint32_t *)take(16 * (ntiles > 0 ? ntiles : 1));
     w.bytes = o;
     return w;
 }
@@ -553,7 +645,7 @@ hipError_t bin_sort_phase1(const BinSortArgs &a, const SortWorkspace &ws, hipStr
 }
 
 static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, int passes,
-                                   uint64_t ntiles, hipStream_t stream);
+                                   uint64_t ntiles, uint32_t tag_shift, hipStream_t stream);
 
 hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, hipStream_t stream)
 {
@@ -564,19 +656,27 @@ hipError_t bin_sort_phase2(const BinSortArgs &a, const SortWorkspace &ws, uint64
     const int passes = (bits + 7) / 8;
     hipError_t e = launch_fill_u32(a.ranges, 0u, 2 * ntiles, stream);
     if (e != hipSuccess) return e;
+    // the tiles' order by their forward work when the records and room for
+    // the block counts are there (centre-depth lists; the tags need 4 bits
+    // above the tile bits the sort passes look at), else by list length
+    const bool tags = a.tile_order && a.records && ws.blk_cost && !a.frame && passes < 4;
+    if (tags) e = launch_fill_u32(ws.blk_cost, 0u, 4 * ntiles, stream);
+    if (e != hipSuccess) return e;
     if (bound > a.capacity) bound = a.capacity;
-    if (n > 0 && bound > 0) e = emit_sort_ranges(a, ws, bound, passes, ntiles, stream);
+    if (n > 0 && bound > 0) e = emit_sort_ranges(a, ws, bound, passes, ntiles, tags ? 8u * passes : 0u, stream);
     if (e != hipSuccess) return e;
     // the tile order is written on every path: the rasterizer reads it for
     // every workgroup, also when there are no pairs
-    if (a.tile_order) e = launch_tile_order(a.ranges, nullptr, (uint32_t)ntiles, a.tile_order, stream);
+    if (a.tile_order)
+        e = launch_tile_order(a.ranges, tags ? ws.blk_cost : nullptr, (uint32_t)ntiles, a.tile_order, stream, tags);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws, uint64_t bound, int passes,
-                                   uint64_t ntiles, hipStream_t stream)
+                                   uint64_t ntiles, uint32_t tag_shift, hipStream_t stream)
 {
+    const float4 *recs = reinterpret_cast<const float4 *>(a.records);
     const int64_t n = a.n;
     hipError_t e = hipSuccess;
     const bool emit_map = a.emit_to_sorted != nullptr;
@@ -591,7 +691,7 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         // emission order: centre depth, then primitive)
         hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n, a.cam,
                            a.tiles_x, a.counters, ws.tileT, ws.primT, ws.emit_prim, a.frame, ws.dkeyT,
-                           a.near_plane);
+                           a.near_plane, recs, 0u);
         uint32_t *dk = ws.dkeyT, *dv = ws.primT, *ak = a.pair_tile, *av = a.pair_prim;
         for (int pass = 0; pass < 4; ++pass) {
             e = radix_pass<RS_ITEMS_TILE>(dk, dv, ak, av, c, bound, 8 * pass, ws, stream);
@@ -613,11 +713,11 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         if (emit_map)
             hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
-                               (uint32_t *)nullptr, 0.0f);
+                               (uint32_t *)nullptr, 0.0f, recs, tag_shift);
         else
             hipLaunchKernelGGL(k_emit<false>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
-                               (uint32_t *)nullptr, 0.0f);
+                               (uint32_t *)nullptr, 0.0f, recs, tag_shift);
     }
     for (int pass = 0; pass < passes; ++pass) {
         uint32_t *ko = (ki == a.pair_tile) ? (a.frame ? ws.dkeyT : ws.tileT) : a.pair_tile;
@@ -630,8 +730,8 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
     if (values_are_emission)
         hipLaunchKernelGGL(k_gather_prims, dim3(gb), dim3(256), 0, stream, (const uint32_t *)ws.emit_prim, c,
                            a.pair_prim, a.emit_to_sorted);
-    hipLaunchKernelGGL(k_ranges, dim3(gb), dim3(256), 0, stream, (const uint32_t *)a.pair_tile, c, a.ranges,
-                       (uint32_t)ntiles);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(bound, 1024)), dim3(256), 0, stream, a.pair_tile, c, a.ranges,
+                       (uint32_t)ntiles, tag_shift, ws.blk_cost);
     return hipGetLastError();
 }
 

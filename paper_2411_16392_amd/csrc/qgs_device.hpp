@@ -127,17 +127,18 @@ __host__ __device__ inline bool conic_offsets(const float *w, const PixelRay &r,
 // per-pixel values stays below 2^-19 of the sum of absolute terms over the
 // box, which the threshold adds.  (Host-callable, like conic_offsets, for the
 // brute-force check of this bound over the pixels of a block.)
-__host__ __device__ inline bool conic_meets_block(const float4 *__restrict__ rec, float bx, float by)
+// From the record's words: cu = words 4..7 (U, 0.5 - frac(u_c), V,
+// 0.5 - frac(v_c)), ab = words 14..15 (a, b), cz = words 28..31 (c, d, e, zl),
+// and ha = 0.5 / a, hc = 0.5 / c (plain divisions, taken once per primitive
+// by callers that test several blocks; unused unless a, c > 0).
+__host__ __device__ inline bool conic_meets_block_h(float4 cu, float2 ab, float4 cz, float ha, float hc, float bx,
+                                                    float by)
 {
-    const float4 cu = rec[1];  // record words 4..7: U, 0.5 - frac(u_c), V, 0.5 - frac(v_c)
-    const float2 ab = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(rec) + 14);
-    const float4 cz = rec[7];  // words 28..31: c, d, e, zl
     const float X0 = (bx - cu.x) + cu.y, X1 = X0 + 7.0f;
     const float Y0 = (by - cu.z) + cu.w, Y1 = Y0 + 7.0f;
     const float a = ab.x, b = ab.y, c = cz.x, d = cz.y, e = cz.z;
     if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
     if (!(a > 0.0f && c > 0.0f)) return true;
-    const float ha = 0.5f / a, hc = 0.5f / c;  // once per batch entry: plain divisions
     float fmin;
     {
         // edges x = X0, X1: vertex at y = -(b X + e) / (2 c)
@@ -155,6 +156,14 @@ __host__ __device__ inline bool conic_meets_block(const float4 *__restrict__ rec
     const float xm = fmaxf(__builtin_fabsf(X0), __builtin_fabsf(X1)), ym = fmaxf(__builtin_fabsf(Y0), __builtin_fabsf(Y1));
     const float S = __builtin_fmaf(a * xm, xm, __builtin_fmaf(__builtin_fabsf(b) * xm, ym, __builtin_fmaf(c * ym, ym, __builtin_fmaf(__builtin_fabsf(d), xm, __builtin_fmaf(__builtin_fabsf(e), ym, 1.0f)))));
     return fmin <= __builtin_fmaf(0x1p-19f, S, CONIC_SLACK);
+}
+
+// the same test from a record in memory
+__host__ __device__ inline bool conic_meets_block(const float4 *__restrict__ rec, float bx, float by)
+{
+    const float2 ab = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(rec) + 14);
+    const float4 cz = rec[7];
+    return conic_meets_block_h(rec[1], ab, cz, 0.5f / ab.x, 0.5f / cz.x, bx, by);
 }
 
 // arc-length factor g(u) = l / rho for u = 2 |a| rho (geodesic equation, Sec.

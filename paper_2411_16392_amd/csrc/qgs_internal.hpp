@@ -66,16 +66,18 @@ struct SortWorkspace {
     uint32_t *tileT, *primT;          // pair ping-pong [capacity]
     uint32_t *emit_prim;              // primitive of each emitted pair [capacity]
     uint32_t *dkeyT;                  // per-tile depth key of each emitted pair [capacity]
+    uint32_t *blk_cost;               // forward work of each 8 x 8 block [4 tiles], or NULL
     size_t bytes;
 };
 
 // Layout of the bin_sort workspace inside `base` (NULL base: sizes only).
-SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity);
+SortWorkspace sort_workspace_layout(void *base, int64_t n, uint64_t capacity, uint64_t ntiles);
 
-// Tiles by decreasing cost[t] (null cost: by list length, from ranges), the
-// longest-processing-time-first order; one workgroup.
+// Tiles by decreasing cost[t] (max4: the largest of cost[4 t .. 4 t + 3]; null
+// cost: by list length, from ranges), the longest-processing-time-first order;
+// one workgroup.
 hipError_t launch_tile_order(const uint32_t *ranges, const uint32_t *cost, uint32_t ntiles, uint32_t *order,
-                             hipStream_t stream);
+                             hipStream_t stream, bool max4 = false);
 
 struct BinSortArgs {
     int64_t n;
@@ -89,6 +91,8 @@ struct BinSortArgs {
     uint64_t capacity;
     const double *frame;  // non-null: key pairs by the per-tile depth
     float near_plane;
+    // the records (non-null: tiles ordered by the forward's block work)
+    const float *records = nullptr;
 };
 
 // Phase 1: depth sort, offsets, counters.  Phase 2: emission, tile sort, ranges

@@ -83,11 +83,48 @@ def check_lists(ks, cam, st, tile_depth=False):
     assert np.array_equal(to_np(st.ranges).view(np.uint32).reshape(-1, 2), ranges), "tile ranges"
     order = to_np(st.tile_order).view(np.uint32)
     assert np.array_equal(np.sort(order), np.arange(len(ranges), dtype=np.uint32)), "tile order is a permutation"
-    lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)[order]
-    # length classes: exact below 2048, 16 entries wide above, capped
-    cls = np.minimum(np.where(lens < 2048, lens, 2048 + (lens - 2048) // 16), 4095)
-    assert np.all(np.diff(cls) <= 0), "longest lists first"
+    if tile_depth:
+        cost = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)  # list lengths
+    else:
+        # the forward's block work, from the host build of its block filter
+        rec = to_np(st.records).reshape(-1, 32)[:len(ks["tiles"])]
+        cost = block_work(rec, ranges, prims, cam.tiles_x).astype(np.int64)
+        assert cost.max() <= (ranges[:, 1] - ranges[:, 0]).max()
+    c = cost[order]
+    # cost classes: exact below 2048, 16 wide above, capped
+    cls = np.minimum(np.where(c < 2048, c, 2048 + (c - 2048) // 16), 4095)
+    assert np.all(np.diff(cls) <= 0), "costliest tiles first"
     return npairs
+
+
+_BWC = {}
+
+
+def block_work(records, ranges, prims, tiles_x):
+    """Per tile, the largest over its four 8 x 8 blocks of the list entries
+    whose rectangle and pre-test conic meet the block: tests/block_work_check.cpp,
+    the kernels' conic_meets_block compiled for the host."""
+    import os
+    import subprocess
+    import tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if "exe" not in _BWC:
+        d = tempfile.mkdtemp(prefix="bwc")
+        exe = os.path.join(d, "block_work_check")
+        hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+        cmd = [hipcc, "-x", "hip", "--offload-arch=gfx950", "--cuda-host-only", "-O2", "-std=c++17",
+               "-I", os.path.join(root, "include"), "-I", os.path.join(root, "paper_2411_16392_amd", "csrc"),
+               os.path.join(root, "tests", "block_work_check.cpp"), "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
+        _BWC["exe"] = exe
+    with tempfile.TemporaryDirectory(prefix="bwc") as d:
+        np.ascontiguousarray(records, np.float32).tofile(os.path.join(d, "records.bin"))
+        np.ascontiguousarray(ranges, np.uint32).tofile(os.path.join(d, "ranges.bin"))
+        np.ascontiguousarray(prims, np.uint32).tofile(os.path.join(d, "prims.bin"))
+        r = subprocess.run([_BWC["exe"], d, str(tiles_x)], capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, (r.returncode, r.stderr)
+        return np.fromfile(os.path.join(d, "cost.bin"), np.uint32)
 
 
 # ---------------------------------------------------------------------------
