@@ -350,46 +350,42 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t *order, con
 // index (EMIT_INDEX, with emit_prim[e] = its primitive, for the emission map)
 // or directly its primitive.  The decisions are those the preprocess counted
 // with the same test.
-// With tag_shift > 0 each emitted tile id also carries, from bit tag_shift
-// on, which of the tile's four 8 x 8 blocks the forward will visit the pair
-// for: the pixel rectangle meets the block and conic_meets_block holds, the
-// forward's own per-batch filter.  The tile sort looks only at the bits
+// Block tags of the emitted pairs, in emission order (a primitive's pairs
+// are consecutive, so its record words are read once per run of pairs): bits
+// tag_shift .. tag_shift + 3 of a pair's tile id are set for the 8 x 8 blocks
+// of the tile the forward will visit the pair for, where the pixel rectangle
+// meets the block and so does the pre-test conic (conic_meets_block, the
+// forward's own per-batch filter).  The tile sort looks only at the bits
 // below tag_shift, so the tags ride along to the ranges pass, which counts
 // them per block and strips them.
-struct BlockTag {
-    const int4 *rc;
-    const float4 *cu, *abcd, *ehh;  // ehh: e, 0.5 / a, 0.5 / c
-    uint32_t shift;
-    __device__ uint32_t operator()(int o, int tx, int ty) const
-    {
-        if (shift == 0u) return 0u;
-        const int4 r = rc[o];
-        const float4 q = abcd[o], h = ehh[o], c = cu[o];
-        uint32_t m = 0u;
+__global__ __launch_bounds__(256) void k_tag_blocks(uint32_t *keys, const uint32_t *prim_of, Count cnt,
+                                                    const float4 *__restrict__ recs, int32_t tiles_x,
+                                                    uint32_t tag_shift)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt.get()) return;
+    const uint32_t t = keys[i];
+    const float4 *rec = recs + (size_t)prim_of[i] * 8;
+    const int4 r = *reinterpret_cast<const int4 *>(rec);  // x0, x1, y0, y1
+    const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
+    uint32_t m = 0u;  // blocks the pixel rectangle meets
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int wx0 = tx * TILE + (k & 1) * 8, wy0 = ty * TILE + (k >> 1) * 8;
-            bool rel = !(r.y < wx0 || r.x > wx0 + 7 || r.w < wy0 || r.z > wy0 + 7);
-            if (rel)
-                rel = conic_meets_block_h(c, make_float2(q.x, q.y), make_float4(q.z, q.w, h.x, 0.0f), h.y, h.z,
-                                          (float)wx0, (float)wy0);
-            m |= (rel ? 1u : 0u) << k;
-        }
-        return m << shift;
+    for (int k = 0; k < 4; ++k) {
+        const int wx0 = tx * TILE + (k & 1) * 8, wy0 = ty * TILE + (k >> 1) * 8;
+        m |= (r.y < wx0 || r.x > wx0 + 7 || r.w < wy0 || r.z > wy0 + 7) ? 0u : 1u << k;
     }
-};
+    if (m) m &= conic_meets_blocks4(rec, tx * TILE, ty * TILE);
+    keys[i] = t | (m << tag_shift);
+}
 
 template <bool EMIT_INDEX>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint64_t *off, const int32_t *rect,
                                               const double *conic, int64_t n, qgs_camera cam, int32_t tiles_x,
                                               const uint32_t *counters, uint32_t *out_tile, uint32_t *out_emit,
                                               uint32_t *emit_prim, const double *frame, uint32_t *out_dkey,
-                                              float near_plane, const float4 *recs, uint32_t tag_shift)
+                                              float near_plane)
 {
     __shared__ ConicLane s_cl[64];
-    // the block tags' words of each lane's primitive (record words 0..7, 14..15, 28..30)
-    __shared__ int4 s_rc[64];
-    __shared__ float4 s_cu[64], s_abcd[64], s_ehh[64];
     if (counters[1]) return;  // overflow: the same for every thread
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ConicLane cl = {};
@@ -412,21 +408,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *order, const uint6
             cl.ty0 = rc[1];
             cl.nx = rc[2] - rc[0] + 1;
             cl.ny = rc[3] - rc[1] + 1;
-            if (tag_shift) {
-                const float4 *w = recs + (size_t)p * 8;
-                const float4 w3 = w[3], w7 = w[7];
-                s_rc[threadIdx.x] = *reinterpret_cast<const int4 *>(w);
-                s_cu[threadIdx.x] = w[1];
-                s_abcd[threadIdx.x] = make_float4(w3.z, w3.w, w7.x, w7.y);
-                s_ehh[threadIdx.x] = make_float4(w7.z, 0.5f / w3.z, 0.5f / w7.x, 0.0f);
-            }
         }
     }
-    // (the barrier in wave_conic_tiles orders these LDS writes before the tags' reads)
-    const BlockTag tag{s_rc, s_cu, s_abcd, s_ehh, tag_shift};
-    (void)wave_conic_tiles<true, EMIT_INDEX, BlockTag>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile,
-                                                       out_emit, emit_prim, frame, out_dkey, (double)near_plane,
-                                                       nullptr, tag);
+    (void)wave_conic_tiles<true, EMIT_INDEX>(s_cl + (threadIdx.x & ~63u), cl, cam, tiles_x, out_tile, out_emit,
+                                             emit_prim, frame, out_dkey, (double)near_plane);
 }
 
 // tile-depth lists: after the depth passes the values are emission indices;
@@ -691,7 +676,7 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         // emission order: centre depth, then primitive)
         hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n, a.cam,
                            a.tiles_x, a.counters, ws.tileT, ws.primT, ws.emit_prim, a.frame, ws.dkeyT,
-                           a.near_plane, recs, 0u);
+                           a.near_plane);
         uint32_t *dk = ws.dkeyT, *dv = ws.primT, *ak = a.pair_tile, *av = a.pair_prim;
         for (int pass = 0; pass < 4; ++pass) {
             e = radix_pass<RS_ITEMS_TILE>(dk, dv, ak, av, c, bound, 8 * pass, ws, stream);
@@ -713,11 +698,15 @@ static hipError_t emit_sort_ranges(const BinSortArgs &a, const SortWorkspace &ws
         if (emit_map)
             hipLaunchKernelGGL(k_emit<true>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
-                               (uint32_t *)nullptr, 0.0f, recs, tag_shift);
+                               (uint32_t *)nullptr, 0.0f);
         else
             hipLaunchKernelGGL(k_emit<false>, dim3(eb), dim3(64), 0, stream, ws.dvA, ws.off, a.rect, a.conic, n,
                                a.cam, a.tiles_x, a.counters, ki, vi, ws.emit_prim, (const double *)nullptr,
-                               (uint32_t *)nullptr, 0.0f, recs, tag_shift);
+                               (uint32_t *)nullptr, 0.0f);
+        if (tag_shift)
+            hipLaunchKernelGGL(k_tag_blocks, dim3(gb), dim3(256), 0, stream, ki,
+                               emit_map ? (const uint32_t *)ws.emit_prim : (const uint32_t *)vi, c, recs, a.tiles_x,
+                               tag_shift);
     }
     for (int pass = 0; pass < passes; ++pass) {
         uint32_t *ko = (ki == a.pair_tile) ? (a.frame ? ws.dkeyT : ws.tileT) : a.pair_tile;

@@ -127,18 +127,11 @@ __host__ __device__ inline bool conic_offsets(const float *w, const PixelRay &r,
 // per-pixel values stays below 2^-19 of the sum of absolute terms over the
 // box, which the threshold adds.  (Host-callable, like conic_offsets, for the
 // brute-force check of this bound over the pixels of a block.)
-// From the record's words: cu = words 4..7 (U, 0.5 - frac(u_c), V,
-// 0.5 - frac(v_c)), ab = words 14..15 (a, b), cz = words 28..31 (c, d, e, zl),
-// and ha = 0.5 / a, hc = 0.5 / c (plain divisions, taken once per primitive
-// by callers that test several blocks; unused unless a, c > 0).
-__host__ __device__ inline bool conic_meets_block_h(float4 cu, float2 ab, float4 cz, float ha, float hc, float bx,
-                                                    float by)
+// The test of one block past its early outcomes (X0 .. Y1: the block's box of
+// pixel offsets; a, c > 0; ha = 0.5 / a, hc = 0.5 / c)
+__host__ __device__ inline bool conic_block_edges(float X0, float X1, float Y0, float Y1, float a, float b, float c,
+                                                  float d, float e, float ha, float hc)
 {
-    const float X0 = (bx - cu.x) + cu.y, X1 = X0 + 7.0f;
-    const float Y0 = (by - cu.z) + cu.w, Y1 = Y0 + 7.0f;
-    const float a = ab.x, b = ab.y, c = cz.x, d = cz.y, e = cz.z;
-    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
-    if (!(a > 0.0f && c > 0.0f)) return true;
     float fmin;
     {
         // edges x = X0, X1: vertex at y = -(b X + e) / (2 c)
@@ -158,12 +151,41 @@ __host__ __device__ inline bool conic_meets_block_h(float4 cu, float2 ab, float4
     return fmin <= __builtin_fmaf(0x1p-19f, S, CONIC_SLACK);
 }
 
-// the same test from a record in memory
 __host__ __device__ inline bool conic_meets_block(const float4 *__restrict__ rec, float bx, float by)
 {
+    const float4 cu = rec[1];  // record words 4..7: U, 0.5 - frac(u_c), V, 0.5 - frac(v_c)
+    const float2 ab = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(rec) + 14);
+    const float4 cz = rec[7];  // words 28..31: c, d, e, zl
+    const float X0 = (bx - cu.x) + cu.y, X1 = X0 + 7.0f;
+    const float Y0 = (by - cu.z) + cu.w, Y1 = Y0 + 7.0f;
+    const float a = ab.x, b = ab.y, c = cz.x, d = cz.y, e = cz.z;
+    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+    if (!(a > 0.0f && c > 0.0f)) return true;
+    const float ha = 0.5f / a, hc = 0.5f / c;  // once per batch entry: plain divisions
+    return conic_block_edges(X0, X1, Y0, Y1, a, b, c, d, e, ha, hc);
+}
+
+// conic_meets_block for the four 8 x 8 blocks of the tile whose top-left pixel
+// is (x0, y0), bit k for the block at (x0 + 8 (k & 1), y0 + 8 (k >> 1)); the
+// same decisions, with the two divisions taken once
+__device__ inline uint32_t conic_meets_blocks4(const float4 *__restrict__ rec, int x0, int y0)
+{
+    const float4 cu = rec[1];
     const float2 ab = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(rec) + 14);
     const float4 cz = rec[7];
-    return conic_meets_block_h(rec[1], ab, cz, 0.5f / ab.x, 0.5f / cz.x, bx, by);
+    const float a = ab.x, b = ab.y, c = cz.x, d = cz.y, e = cz.z;
+    if (!(a > 0.0f && c > 0.0f)) return 0xFu;
+    const float ha = 0.5f / a, hc = 0.5f / c;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float X0 = ((float)(x0 + 8 * (k & 1)) - cu.x) + cu.y, X1 = X0 + 7.0f;
+        const float Y0 = ((float)(y0 + 8 * (k >> 1)) - cu.z) + cu.w, Y1 = Y0 + 7.0f;
+        const bool in = (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) ||
+                        conic_block_edges(X0, X1, Y0, Y1, a, b, c, d, e, ha, hc);
+        m |= (in ? 1u : 0u) << k;
+    }
+    return m;
 }
 
 // arc-length factor g(u) = l / rho for u = 2 |a| rho (geodesic equation, Sec.

@@ -183,17 +183,11 @@ __device__ inline uint64_t lane_range_mask(int64_t lo, int64_t hi)
 // with emit_prim = prim (EMIT_INDEX), or out_emit = prim.
 // mask_out (counting pass, may be NULL): the lane's decisions as a bit mask
 // when its rectangle has at most 64 tiles, else 0.
-// tag(o, tx, ty) (EMIT): bits or-ed into the tile id of an emitted pair of
-// the wave's lane o (above the bits the tile sort looks at).
-struct NoTileTag {
-    __device__ uint32_t operator()(int, int, int) const { return 0u; }
-};
-template <bool EMIT, bool EMIT_INDEX = true, typename Tag = NoTileTag>
+template <bool EMIT, bool EMIT_INDEX = true>
 __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &me, const qgs_camera &cam,
                                             int tiles_x, uint32_t *out_tile, uint32_t *out_emit, uint32_t *emit_prim,
                                             const double *frame = nullptr, uint32_t *out_dkey = nullptr,
-                                            double near_d = 0.0, uint64_t *mask_out = nullptr,
-                                            const Tag &tag = Tag())
+                                            double near_d = 0.0, uint64_t *mask_out = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t R = (me.nx > 0 && me.ny > 0) ? (uint32_t)me.nx * (uint32_t)me.ny : 0u;
@@ -233,7 +227,7 @@ __device__ inline uint32_t wave_conic_tiles(ConicLane *s_wave, const ConicLane &
             const uint32_t k = run_o + (uint32_t)__popcll(bal & lane_range_mask((int64_t)q.excl - (int64_t)base, lane));
             if (k < q.cnt) {
                 const uint64_t e = q.base + k;
-                out_tile[e] = (uint32_t)(ty * tiles_x + tx) | tag(o, tx, ty);
+                out_tile[e] = (uint32_t)(ty * tiles_x + tx);
                 if (out_dkey) out_dkey[e] = tile_depth_bits(frame + 16 * (size_t)q.prim, tx, ty, cam, near_d);
                 if (EMIT_INDEX) {
                     out_emit[e] = (uint32_t)e;
