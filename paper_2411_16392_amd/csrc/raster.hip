@@ -877,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd_rs(RasterArgs a, RasterPar
             load_record_words(recs, pj, rw);
             const float *w = rw;
             float dxp, dyp;
-            const bool lane_on = !done && conic_offsets(w, ray, dxp, dyp);
+            const bool lane_on = conic_offsets(w, ray, dxp, dyp) & !done;
             if (__ballot(lane_on) == 0ull) continue;
             const uint32_t pos1 = b + (uint32_t)j + 1u;
             if (lane_on) {
